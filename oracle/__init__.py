@@ -1,0 +1,280 @@
+"""FP64 CPU oracle for the treecode hot path: TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_1211_2293_amd``) and never imports it.
+
+Contents
+--------
+* ``liboracle.so`` (``oracle.c``): the FP64 direct sum and the FP64 treecode
+  (root cube, Morton digits, recursive subdivision, moments, opening
+  criterion, walk, forces) of §3.1 of the paper.
+* numpy references written from the same section: a direct sum for small N,
+  a naive geometric subdivision (no keys) used to pin the key-based tree,
+  leapfrog (kick-drift-kick) and FP64 diagnostics.
+* ``mlp``: the learned-closure reference (FP64 MLP with BF16 emulation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib():
+    """Load liboracle.so, building it first if it is missing."""
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        L.orc_direct.argtypes = [i64, i32, P, P, dbl, dbl, i64, P, P, P]
+        L.orc_direct.restype = None
+        L.orc_tree_build.argtypes = [i64, i32, P, P, i32]
+        L.orc_tree_build.restype = P
+        L.orc_tree_free.argtypes = [P]
+        L.orc_tree_free.restype = None
+        L.orc_tree_ncells.argtypes = [P]
+        L.orc_tree_ncells.restype = i64
+        L.orc_tree_root.argtypes = [P, P, P]
+        L.orc_tree_root.restype = None
+        L.orc_tree_bodies.argtypes = [P, P, P, P]
+        L.orc_tree_bodies.restype = None
+        L.orc_tree_cells.argtypes = [P] * 12
+        L.orc_tree_cells.restype = None
+        L.orc_mac_radii.argtypes = [P, dbl, P]
+        L.orc_mac_radii.restype = None
+        L.orc_walk_counts.argtypes = [P, dbl, i32, P, P]
+        L.orc_walk_counts.restype = None
+        L.orc_walk_items.argtypes = [P, dbl, i32, i64, P, i64]
+        L.orc_walk_items.restype = i64
+        L.orc_tree_forces.argtypes = [P, dbl, i32, dbl, dbl, i64, P, P, P]
+        L.orc_tree_forces.restype = None
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Direct sum (§3.1 force law with Plummer softening), FP64.
+# --------------------------------------------------------------------------
+def direct(pos, mass, G=1.0, eps=1e-3, targets=None):
+    """FP64 direct sum for the given original-order target indices (all if
+    None).  Returns (acc [nt][dim], pot [nt])."""
+    pos, mass = _f64(pos), _f64(mass)
+    n, dim = pos.shape
+    if targets is None:
+        nt, tp = n, None
+    else:
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        nt, tp = len(targets), targets
+    acc = np.zeros((nt, dim))
+    pot = np.zeros(nt)
+    lib().orc_direct(n, dim, _p(pos), _p(mass), G, eps, nt, _p(tp), _p(acc), _p(pot))
+    return acc, pot
+
+
+def direct_numpy(pos, mass, G=1.0, eps=1e-3):
+    """The same definition as ``direct`` with numpy broadcasting (N <= ~2000):
+    an independent second implementation used to pin the C one."""
+    pos, mass = _f64(pos), _f64(mass)
+    d = pos[None, :, :] - pos[:, None, :]          # d[i, j] = x_j - x_i
+    r2 = (d * d).sum(-1) + eps * eps
+    np.fill_diagonal(r2, 1.0)                      # self term removed below
+    inv = 1.0 / np.sqrt(r2)
+    np.fill_diagonal(inv, 0.0)
+    w = mass[None, :] * inv
+    acc = G * ((w * inv * inv)[:, :, None] * d).sum(1)
+    pot = -G * w.sum(1)
+    return acc, pot
+
+
+# --------------------------------------------------------------------------
+# Treecode (§3.1), FP64.
+# --------------------------------------------------------------------------
+class Tree:
+    """FP64 treecode tree over positions ``pos`` [n][dim] and masses."""
+
+    def __init__(self, pos, mass, leaf_cap):
+        self.pos, self.mass = _f64(pos), _f64(mass)
+        self.n, self.dim = self.pos.shape
+        self.leaf_cap = leaf_cap
+        self.L = 21 if self.dim == 3 else 31
+        h = lib().orc_tree_build(self.n, self.dim, _p(self.pos), _p(self.mass), leaf_cap)
+        if not h:
+            raise ValueError("bad arguments to orc_tree_build")
+        self._h = C.c_void_p(h)
+        self.ncells = int(lib().orc_tree_ncells(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.orc_tree_free(h)
+            self._h = None
+
+    def root(self):
+        lo = np.zeros(self.dim)
+        size = np.zeros(1)
+        lib().orc_tree_root(self._h, _p(lo), _p(size))
+        return lo, float(size[0])
+
+    def bodies(self):
+        ko = np.zeros(self.n, np.uint64)
+        ks = np.zeros(self.n, np.uint64)
+        pm = np.zeros(self.n, np.uint32)
+        lib().orc_tree_bodies(self._h, _p(ko), _p(ks), _p(pm))
+        return {"key_orig": ko, "key": ks, "perm": pm}
+
+    def cells(self):
+        Cn, d = self.ncells, self.dim
+        out = {
+            "level": np.zeros(Cn, np.int32), "prefix": np.zeros(Cn, np.uint64),
+            "begin": np.zeros(Cn, np.int64), "count": np.zeros(Cn, np.int64),
+            "parent": np.zeros(Cn, np.int32), "skip": np.zeros(Cn, np.int32),
+            "nch": np.zeros(Cn, np.int32), "leaf": np.zeros(Cn, np.int32),
+            "M": np.zeros(Cn), "com": np.zeros((Cn, d)), "Q": np.zeros((Cn, 6)),
+        }
+        o = out
+        lib().orc_tree_cells(self._h, _p(o["level"]), _p(o["prefix"]), _p(o["begin"]),
+                             _p(o["count"]), _p(o["parent"]), _p(o["skip"]), _p(o["nch"]),
+                             _p(o["leaf"]), _p(o["M"]), _p(o["com"]), _p(o["Q"]))
+        return out
+
+    def mac_radii(self, theta):
+        r = np.zeros(self.ncells)
+        lib().orc_mac_radii(self._h, float(theta), _p(r))
+        return r
+
+    def walk_counts(self, theta, gs=64):
+        G = (self.n + gs - 1) // gs
+        m2p = np.zeros(G, np.int64)
+        p2p = np.zeros(G, np.int64)
+        lib().orc_walk_counts(self._h, float(theta), gs, _p(m2p), _p(p2p))
+        return m2p, p2p
+
+    def walk_items(self, theta, g, gs=64):
+        """Terminal items of group g in walk order: c >= 0 accepted cell,
+        -1-c opened leaf c."""
+        cap = 1 << 16
+        while True:
+            buf = np.zeros(cap, np.int32)
+            k = int(lib().orc_walk_items(self._h, float(theta), gs, int(g), _p(buf), cap))
+            if k <= cap:
+                return buf[:k]
+            cap = k
+
+    def forces(self, theta, G=1.0, eps=1e-3, gs=64, groups=None):
+        """FP64 treecode accelerations and potentials in original order.
+        With ``groups`` only those groups' bodies are computed (others 0)."""
+        acc = np.zeros((self.n, self.dim))
+        pot = np.zeros(self.n)
+        if groups is None:
+            lib().orc_tree_forces(self._h, float(theta), gs, G, eps, 0, None, _p(acc), _p(pot))
+        else:
+            gsel = np.ascontiguousarray(groups, dtype=np.int64)
+            lib().orc_tree_forces(self._h, float(theta), gs, G, eps, len(gsel), _p(gsel),
+                                  _p(acc), _p(pot))
+        return acc, pot
+
+
+def group_bodies(tree: Tree, groups, gs=64):
+    """Original indices of the bodies of the given groups (sorted order)."""
+    perm = tree.bodies()["perm"]
+    idx = [np.arange(g * gs, min((g + 1) * gs, tree.n)) for g in groups]
+    return perm[np.concatenate(idx)].astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Naive geometric subdivision (§3.1: divide the space into 4 or 8 subspaces
+# until a subspace holds at most the threshold), with no keys and no sort.
+# --------------------------------------------------------------------------
+def geometric_tree(pos, leaf_cap, lo, size, L):
+    """Cells as (level, frozenset of original body indices), in depth-first
+    order with subspaces visited in the order x-high-bit first.  Each
+    subspace is split at the midpoint of the cube: a body goes to the upper
+    half along an axis iff its offset from the cube's low corner, scaled to
+    2^L units, is at least the midpoint.  Pure Python: small N only."""
+    pos = _f64(pos)
+    n, dim = pos.shape
+    scale = 2.0 ** L / size
+    t = (pos - np.asarray(lo)[None, :]) * scale      # offset in 2^L units
+    out = []
+
+    def rec(level, origin, members):
+        out.append((level, frozenset(members)))
+        if len(members) <= leaf_cap or level == L:
+            return
+        half = 2.0 ** (L - level - 1)
+        kids = {}
+        for b in members:
+            code = 0
+            sub = []
+            for a in range(dim):
+                mid = origin[a] + half
+                # a body on the far face of the root cube (offset 2^L) is
+                # above every midpoint, so it lands in the last subspace
+                up = t[b, a] >= mid
+                code = (code << 1) | int(up)
+                sub.append(origin[a] + half if up else origin[a])
+            kids.setdefault(code, (tuple(sub), []))[1].append(b)
+        for code in sorted(kids):
+            org, mem = kids[code]
+            rec(level + 1, org, mem)
+
+    rec(0, tuple(0.0 for _ in range(dim)), list(range(n)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Leapfrog kick-drift-kick and FP64 diagnostics.
+# --------------------------------------------------------------------------
+def kdk(pos, vel, acc0, dt, force):
+    """One kick-drift-kick step: v+ = v + dt/2 a(x); x' = x + dt v+;
+    v' = v+ + dt/2 a(x').  ``force(x)`` returns the accelerations.  Returns
+    (x', v', a(x'))."""
+    vh = vel + 0.5 * dt * acc0
+    x1 = pos + dt * vh
+    a1 = force(x1)
+    v1 = vh + 0.5 * dt * a1
+    return x1, v1, a1
+
+
+def diagnostics(mass, vel, acc, pot):
+    """FP64 E_kin, E_pot, momentum and sum m a: E_kin = 1/2 sum m v^2,
+    E_pot = 1/2 sum m phi.  Returns 8 numbers: E_kin, E_pot, P[3], F[3]
+    (2D fills the z components with 0)."""
+    mass, vel, acc, pot = _f64(mass), _f64(vel), _f64(acc), _f64(pot)
+    out = np.zeros(8)
+    out[0] = 0.5 * np.sum(mass * np.sum(vel * vel, axis=1))
+    out[1] = 0.5 * np.sum(mass * pot)
+    d = vel.shape[1]
+    out[2:2 + d] = (mass[:, None] * vel).sum(0)
+    out[5:5 + d] = (mass[:, None] * acc).sum(0)
+    return out
+
+
+def rel_l2(a, ref):
+    """Relative L2 error sqrt(sum |a - ref|^2 / sum |ref|^2)."""
+    a, ref = np.asarray(a, np.float64), np.asarray(ref, np.float64)
+    return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))

@@ -1,0 +1,565 @@
+/*
+ * FP64 CPU oracle for the treecode hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or helper with the
+ * GPU library; the two meet only through the seeded input generators.
+ *
+ * What it computes (Duy, Yamazaki & Oyanagi, "Performance Evaluation of
+ * Treecode Algorithm for N-Body Simulation Using GridRPC System"):
+ *
+ *   - the exact result: the direct pairwise sum of the force law of §3.1
+ *     (F = G m_a m_b / r^2, with Plummer softening eps), in FP64;
+ *   - the treecode of §3.1 step by step: the space is divided recursively
+ *     into 4 (2D) or 8 (3D) subspaces until a subspace holds at most leaf_cap
+ *     bodies; each cell carries the total mass of its bodies placed at their
+ *     centre of mass; the walk starts at the root and puts a cell on the
+ *     interaction list when it is distant enough, otherwise descends into its
+ *     children; the force on a body is the sum over its list.
+ *
+ * Readings of what the paper leaves open (shared with the GPU path by
+ * specification, not by code):
+ *   - root cube: per-axis minimum corner, side = smallest power of two >= the
+ *     largest per-axis extent (1 if the extent is 0);
+ *   - subdivision follows Morton digits of FP64-quantised coordinates
+ *     (L = 21 levels in 3D, 31 in 2D), digit = 4bx+2by+bz (3D), 2bx+by (2D);
+ *     a cell is a leaf iff it holds <= leaf_cap bodies or sits at level L;
+ *     empty subspaces are never materialised; children are kept in digit
+ *     order and the cell array is the depth-first pre-order;
+ *   - "distant enough" is a group opening criterion: cell c is accepted for a
+ *     group of bodies iff the squared distance from c's centre of mass to the
+ *     group's bounding box exceeds (s_c/theta + |com_c - centre_c|)^2, strict;
+ *     theta = 0 accepts nothing;
+ *   - groups are runs of gs consecutive bodies in Morton order (gs = 1 is
+ *     the paper's literal per-body list);
+ *   - self-interaction is excluded.
+ *
+ * Every floating-point expression whose result decides an integer (keys,
+ * tree, opening decisions) is written out in a fixed order and this file
+ * must be compiled with -ffp-contract=off.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXD 3
+
+/* ------------------------------------------------------------------------ */
+/* Direct sum: the plain definition of the exact softened result (§3.1).    */
+/* ------------------------------------------------------------------------ */
+
+/* For each target t (an original body index): acc[t] = G sum_{j != t}
+ * m_j (x_j - x_t) / (|x_j - x_t|^2 + eps^2)^{3/2} and
+ * pot[t] = -G sum_{j != t} m_j / (|x_j - x_t|^2 + eps^2)^{1/2}.
+ * pos is [n][dim] row-major.  Outputs are [nt][dim] and [nt]. */
+void orc_direct(int64_t n, int dim, const double *pos, const double *mass,
+                double G, double eps, int64_t nt, const int64_t *targets,
+                double *acc, double *pot)
+{
+    const double e2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        double a[ORC_MAXD] = {0, 0, 0}, p = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[ORC_MAXD], r2 = e2;
+            for (int k = 0; k < dim; ++k) {
+                d[k] = pos[j * dim + k] - pos[i * dim + k];
+                r2 += d[k] * d[k];
+            }
+            const double inv = 1.0 / sqrt(r2);
+            const double w = mass[j] * inv;
+            p -= w;
+            const double w3 = w * inv * inv;
+            for (int k = 0; k < dim; ++k) a[k] += w3 * d[k];
+        }
+        for (int k = 0; k < dim; ++k) acc[t * dim + k] = G * a[k];
+        if (pot) pot[t] = G * p;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree (§3.1): root cube, Morton digits, recursive subdivision, moments.   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct orc_tree {
+    int dim, L, leaf_cap;
+    int64_t n;
+    double lo[ORC_MAXD], size;
+    uint64_t *key_orig;  /* key of each body, original order     */
+    uint64_t *key;       /* keys in sorted order                  */
+    uint32_t *perm;      /* sorted position -> original index     */
+    double *x;           /* sorted positions [n][dim]             */
+    double *m;           /* sorted masses [n]                     */
+    int64_t ncells, cap;
+    int32_t *level, *parent, *skip, *nch, *leaf;
+    uint64_t *prefix;
+    int64_t *begin, *count;
+    double *M, *S, *com, *Q; /* per cell: M, S[dim], com[dim], Q[6] */
+} orc_tree;
+
+static int levels_for(int dim) { return dim == 3 ? 21 : 31; }
+
+/* Root cube of the subdivided space. */
+static void root_cube(int64_t n, int dim, const double *pos, double *lo, double *size)
+{
+    double hi[ORC_MAXD];
+    for (int k = 0; k < dim; ++k) { lo[k] = pos[k]; hi[k] = pos[k]; }
+    for (int64_t i = 1; i < n; ++i)
+        for (int k = 0; k < dim; ++k) {
+            const double v = pos[i * dim + k];
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+    double ext = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        const double e = hi[k] - lo[k];
+        if (e > ext) ext = e;
+    }
+    if (ext == 0.0) { *size = 1.0; return; }
+    int e2;
+    const double f = frexp(ext, &e2);        /* ext = f * 2^e2, f in [0.5,1) */
+    *size = (f == 0.5) ? ext : ldexp(1.0, e2);
+}
+
+/* Quantised coordinate along one axis: floor((x - lo) * 2^L / size),
+ * clamped to 2^L - 1.  size is a power of two so the scale is exact. */
+static uint64_t quantise(double x, double lo, double scale, int L)
+{
+    const double t = (x - lo) * scale;
+    double f = floor(t);
+    const double top = ldexp(1.0, L) - 1.0;
+    if (f > top) f = top;
+    if (f < 0.0) f = 0.0;
+    return (uint64_t)f;
+}
+
+/* Morton key: level-major digits, level 1 most significant. */
+static uint64_t morton(const uint64_t *q, int dim, int L)
+{
+    uint64_t key = 0;
+    for (int l = 1; l <= L; ++l) {
+        uint64_t digit = 0;
+        for (int k = 0; k < dim; ++k)
+            digit = (digit << 1) | ((q[k] >> (L - l)) & 1u);
+        key = (key << dim) | digit;
+    }
+    return key;
+}
+
+typedef struct { uint64_t key; uint32_t idx; } kv_t;
+
+static int kv_cmp(const void *a, const void *b)
+{
+    const kv_t *x = (const kv_t *)a, *y = (const kv_t *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+static void grow(orc_tree *t)
+{
+    int64_t c = t->cap ? t->cap * 2 : 1024;
+    t->level = realloc(t->level, c * sizeof(int32_t));
+    t->parent = realloc(t->parent, c * sizeof(int32_t));
+    t->skip = realloc(t->skip, c * sizeof(int32_t));
+    t->nch = realloc(t->nch, c * sizeof(int32_t));
+    t->leaf = realloc(t->leaf, c * sizeof(int32_t));
+    t->prefix = realloc(t->prefix, c * sizeof(uint64_t));
+    t->begin = realloc(t->begin, c * sizeof(int64_t));
+    t->count = realloc(t->count, c * sizeof(int64_t));
+    t->cap = c;
+}
+
+/* The digit of a key at level l (1..L). */
+static unsigned digit_at(uint64_t key, int dim, int L, int l)
+{
+    return (unsigned)((key >> (dim * (L - l))) & ((1u << dim) - 1u));
+}
+
+/* Recursive subdivision of a cell holding sorted bodies [b, e): the cell is
+ * emitted in pre-order, then, if it holds more than leaf_cap bodies and is
+ * above level L, split into its non-empty subspaces in digit order. */
+static void subdivide(orc_tree *t, int level, uint64_t prefix, int64_t b, int64_t e, int32_t parent)
+{
+    if (t->ncells == t->cap) grow(t);
+    const int64_t c = t->ncells++;
+    t->level[c] = level;
+    t->prefix[c] = prefix;
+    t->begin[c] = b;
+    t->count[c] = e - b;
+    t->parent[c] = parent;
+    t->nch[c] = 0;
+    const int split = (e - b) > t->leaf_cap && level < t->L;
+    t->leaf[c] = !split;
+    if (split) {
+        int64_t s = b;
+        while (s < e) {
+            const unsigned d = digit_at(t->key[s], t->dim, t->L, level + 1);
+            int64_t f = s;
+            while (f < e && digit_at(t->key[f], t->dim, t->L, level + 1) == d) ++f;
+            t->nch[c] += 1;
+            subdivide(t, level + 1, (prefix << t->dim) | d, s, f, (int32_t)c);
+            s = f;
+        }
+    }
+    t->skip[c] = (int32_t)t->ncells;
+}
+
+/* Cell monopole (§3.1: total mass at the centre of mass) and the traceless
+ * quadrupole, bottom-up.  Leaves sum their bodies in sorted order; internal
+ * cells sum their children in digit order.  Q is (xx, yy, zz, xy, xz, yz),
+ * Q_ab = sum m (3 d_a d_b - |d|^2 delta_ab) about the cell's centre of mass,
+ * moved from children by the parallel-axis shift.  3D only (zero in 2D). */
+static void moments(orc_tree *t, int64_t c)
+{
+    const int D = t->dim;
+    double M = 0.0, S[ORC_MAXD] = {0, 0, 0}, Q[6] = {0, 0, 0, 0, 0, 0};
+    if (t->leaf[c]) {
+        for (int64_t j = t->begin[c]; j < t->begin[c] + t->count[c]; ++j) {
+            M = M + t->m[j];
+            for (int k = 0; k < D; ++k) S[k] = S[k] + t->m[j] * t->x[j * D + k];
+        }
+        double com[ORC_MAXD];
+        for (int k = 0; k < D; ++k) com[k] = S[k] / M;
+        if (D == 3) {
+            for (int64_t j = t->begin[c]; j < t->begin[c] + t->count[c]; ++j) {
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = t->x[j * 3 + k] - com[k];
+                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                const double mj = t->m[j];
+                Q[0] = Q[0] + mj * ((3.0 * d[0]) * d[0] - r2);
+                Q[1] = Q[1] + mj * ((3.0 * d[1]) * d[1] - r2);
+                Q[2] = Q[2] + mj * ((3.0 * d[2]) * d[2] - r2);
+                Q[3] = Q[3] + mj * ((3.0 * d[0]) * d[1]);
+                Q[4] = Q[4] + mj * ((3.0 * d[0]) * d[2]);
+                Q[5] = Q[5] + mj * ((3.0 * d[1]) * d[2]);
+            }
+        }
+        t->M[c] = M;
+        for (int k = 0; k < D; ++k) { t->S[c * D + k] = S[k]; t->com[c * D + k] = com[k]; }
+        for (int k = 0; k < 6; ++k) t->Q[c * 6 + k] = Q[k];
+        return;
+    }
+    for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) moments(t, ch);
+    for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) {
+        M = M + t->M[ch];
+        for (int k = 0; k < D; ++k) S[k] = S[k] + t->S[ch * D + k];
+    }
+    double com[ORC_MAXD];
+    for (int k = 0; k < D; ++k) com[k] = S[k] / M;
+    if (D == 3) {
+        for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) {
+            double s[3];
+            for (int k = 0; k < 3; ++k) s[k] = t->com[ch * 3 + k] - com[k];
+            const double r2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
+            const double Mc = t->M[ch];
+            const double *q = t->Q + ch * 6;
+            Q[0] = Q[0] + (q[0] + Mc * ((3.0 * s[0]) * s[0] - r2));
+            Q[1] = Q[1] + (q[1] + Mc * ((3.0 * s[1]) * s[1] - r2));
+            Q[2] = Q[2] + (q[2] + Mc * ((3.0 * s[2]) * s[2] - r2));
+            Q[3] = Q[3] + (q[3] + Mc * ((3.0 * s[0]) * s[1]));
+            Q[4] = Q[4] + (q[4] + Mc * ((3.0 * s[0]) * s[2]));
+            Q[5] = Q[5] + (q[5] + Mc * ((3.0 * s[1]) * s[2]));
+        }
+    }
+    t->M[c] = M;
+    for (int k = 0; k < D; ++k) { t->S[c * D + k] = S[k]; t->com[c * D + k] = com[k]; }
+    for (int k = 0; k < 6; ++k) t->Q[c * 6 + k] = Q[k];
+}
+
+/* Build the tree of n bodies.  pos is [n][dim] (FP64, original order).
+ * Returns NULL on bad arguments. */
+orc_tree *orc_tree_build(int64_t n, int dim, const double *pos, const double *mass, int leaf_cap)
+{
+    if (n < 1 || (dim != 2 && dim != 3) || leaf_cap < 1) return NULL;
+    orc_tree *t = calloc(1, sizeof(orc_tree));
+    t->dim = dim;
+    t->L = levels_for(dim);
+    t->leaf_cap = leaf_cap;
+    t->n = n;
+    root_cube(n, dim, pos, t->lo, &t->size);
+    int e2;
+    frexp(t->size, &e2);                        /* size = 2^(e2-1) */
+    const double scale = ldexp(1.0, t->L - (e2 - 1));
+    t->key_orig = malloc(n * sizeof(uint64_t));
+    kv_t *kv = malloc(n * sizeof(kv_t));
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t q[ORC_MAXD];
+        for (int k = 0; k < dim; ++k) q[k] = quantise(pos[i * dim + k], t->lo[k], scale, t->L);
+        t->key_orig[i] = morton(q, dim, t->L);
+        kv[i].key = t->key_orig[i];
+        kv[i].idx = (uint32_t)i;
+    }
+    qsort(kv, n, sizeof(kv_t), kv_cmp);      /* stable by (key, original index) */
+    t->key = malloc(n * sizeof(uint64_t));
+    t->perm = malloc(n * sizeof(uint32_t));
+    t->x = malloc(n * dim * sizeof(double));
+    t->m = malloc(n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        t->key[i] = kv[i].key;
+        t->perm[i] = kv[i].idx;
+        for (int k = 0; k < dim; ++k) t->x[i * dim + k] = pos[(int64_t)kv[i].idx * dim + k];
+        t->m[i] = mass[kv[i].idx];
+    }
+    free(kv);
+    subdivide(t, 0, 0, 0, n, -1);
+    t->M = malloc(t->ncells * sizeof(double));
+    t->S = malloc(t->ncells * dim * sizeof(double));
+    t->com = malloc(t->ncells * dim * sizeof(double));
+    t->Q = malloc(t->ncells * 6 * sizeof(double));
+    moments(t, 0);
+    return t;
+}
+
+void orc_tree_free(orc_tree *t)
+{
+    if (!t) return;
+    free(t->key_orig); free(t->key); free(t->perm); free(t->x); free(t->m);
+    free(t->level); free(t->parent); free(t->skip); free(t->nch); free(t->leaf);
+    free(t->prefix); free(t->begin); free(t->count);
+    free(t->M); free(t->S); free(t->com); free(t->Q);
+    free(t);
+}
+
+int64_t orc_tree_ncells(const orc_tree *t) { return t->ncells; }
+
+void orc_tree_root(const orc_tree *t, double *lo, double *size)
+{
+    for (int k = 0; k < t->dim; ++k) lo[k] = t->lo[k];
+    *size = t->size;
+}
+
+/* Copy out the body-order arrays (any pointer may be NULL). */
+void orc_tree_bodies(const orc_tree *t, uint64_t *key_orig, uint64_t *key, uint32_t *perm)
+{
+    if (key_orig) memcpy(key_orig, t->key_orig, t->n * sizeof(uint64_t));
+    if (key) memcpy(key, t->key, t->n * sizeof(uint64_t));
+    if (perm) memcpy(perm, t->perm, t->n * sizeof(uint32_t));
+}
+
+/* Copy out the per-cell arrays in pre-order (any pointer may be NULL). */
+void orc_tree_cells(const orc_tree *t, int32_t *level, uint64_t *prefix, int64_t *begin,
+                    int64_t *count, int32_t *parent, int32_t *skip, int32_t *nch, int32_t *leaf,
+                    double *M, double *com, double *Q)
+{
+    const int64_t C = t->ncells;
+    if (level) memcpy(level, t->level, C * sizeof(int32_t));
+    if (prefix) memcpy(prefix, t->prefix, C * sizeof(uint64_t));
+    if (begin) memcpy(begin, t->begin, C * sizeof(int64_t));
+    if (count) memcpy(count, t->count, C * sizeof(int64_t));
+    if (parent) memcpy(parent, t->parent, C * sizeof(int32_t));
+    if (skip) memcpy(skip, t->skip, C * sizeof(int32_t));
+    if (nch) memcpy(nch, t->nch, C * sizeof(int32_t));
+    if (leaf) memcpy(leaf, t->leaf, C * sizeof(int32_t));
+    if (M) memcpy(M, t->M, C * sizeof(double));
+    if (com) memcpy(com, t->com, C * t->dim * sizeof(double));
+    if (Q) memcpy(Q, t->Q, C * 6 * sizeof(double));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Opening criterion and walk (§3.1).                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Squared opening radius of every cell for a given theta:
+ * r = s_c / theta + |com_c - centre_c|, s_c = size / 2^level the cell side,
+ * centre_c the geometric centre of the cell's subspace.  theta = 0 gives
+ * +infinity (nothing is accepted). */
+void orc_mac_radii(const orc_tree *t, double theta, double *rcrit2)
+{
+    const int D = t->dim;
+    for (int64_t c = 0; c < t->ncells; ++c) {
+        if (theta == 0.0) { rcrit2[c] = INFINITY; continue; }
+        const int l = t->level[c];
+        const double s = ldexp(t->size, -l);
+        /* the cell's integer origin along each axis, from its key prefix */
+        uint64_t org[ORC_MAXD] = {0, 0, 0};
+        for (int j = 1; j <= l; ++j) {
+            const unsigned d = (unsigned)((t->prefix[c] >> (D * (l - j))) & ((1u << D) - 1u));
+            for (int k = 0; k < D; ++k)
+                org[k] = (org[k] << 1) | ((d >> (D - 1 - k)) & 1u);
+        }
+        double dd[ORC_MAXD] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) {
+            const double centre = t->lo[k] + ((double)org[k] + 0.5) * s;
+            dd[k] = t->com[c * D + k] - centre;
+        }
+        double d2 = dd[0] * dd[0] + dd[1] * dd[1];
+        if (D == 3) d2 = d2 + dd[2] * dd[2];
+        const double r = s / theta + sqrt(d2);
+        rcrit2[c] = r * r;
+    }
+}
+
+/* Group bounding box of sorted bodies [b, e). */
+static void group_box(const orc_tree *t, int64_t b, int64_t e, double *lo, double *hi)
+{
+    const int D = t->dim;
+    for (int k = 0; k < D; ++k) { lo[k] = t->x[b * D + k]; hi[k] = lo[k]; }
+    for (int64_t j = b + 1; j < e; ++j)
+        for (int k = 0; k < D; ++k) {
+            const double v = t->x[j * D + k];
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+}
+
+/* The opening decision: accept iff dist^2(com, box) > rcrit2, strict. */
+static int accepts(const orc_tree *t, int64_t c, const double *rcrit2, const double *lo, const double *hi)
+{
+    const int D = t->dim;
+    double d[ORC_MAXD] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) {
+        const double x = t->com[c * D + k];
+        const double below = lo[k] - x, above = x - hi[k];
+        double v = 0.0;
+        if (below > v) v = below;
+        if (above > v) v = above;
+        d[k] = v;
+    }
+    double d2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) d2 = d2 + d[2] * d[2];
+    return d2 > rcrit2[c];
+}
+
+typedef struct {
+    int32_t *items;       /* terminal cells in walk order; -1-c marks a P2P leaf c */
+    int64_t nitems, cap;
+    int64_t m2p, p2p;     /* accepted cells, bodies from opened leaves */
+} walk_out;
+
+static void push_item(walk_out *w, int32_t v)
+{
+    if (w->items) {
+        if (w->nitems == w->cap) {
+            w->cap = w->cap ? 2 * w->cap : 256;
+            w->items = realloc(w->items, w->cap * sizeof(int32_t));
+        }
+        w->items[w->nitems] = v;
+    }
+    w->nitems++;
+}
+
+/* Walk from cell c (recursive descent, §3.1). */
+static void walk_rec(const orc_tree *t, int64_t c, const double *rcrit2, const double *lo,
+                     const double *hi, walk_out *w)
+{
+    if (accepts(t, c, rcrit2, lo, hi)) {
+        w->m2p += 1;
+        push_item(w, (int32_t)c);
+        return;
+    }
+    if (t->leaf[c]) {
+        w->p2p += t->count[c];
+        push_item(w, (int32_t)(-1 - c));
+        return;
+    }
+    for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) walk_rec(t, ch, rcrit2, lo, hi, w);
+}
+
+static void walk_group(const orc_tree *t, const double *rcrit2, int gs, int64_t g, walk_out *w)
+{
+    const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
+    double lo[ORC_MAXD], hi[ORC_MAXD];
+    group_box(t, b, e, lo, hi);
+    walk_rec(t, 0, rcrit2, lo, hi, w);
+}
+
+/* Number of accepted cells (m2p) and of bodies from opened leaves (p2p,
+ * the group's own bodies included) for every group of gs sorted bodies. */
+void orc_walk_counts(const orc_tree *t, double theta, int gs, int64_t *m2p, int64_t *p2p)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+    const int64_t G = (t->n + gs - 1) / gs;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t g = 0; g < G; ++g) {
+        walk_out w = {0};
+        walk_group(t, rc, gs, g, &w);
+        m2p[g] = w.m2p;
+        p2p[g] = w.p2p;
+    }
+    free(rc);
+}
+
+/* The terminal items of one group's walk, in walk order: c >= 0 is an
+ * accepted cell, -1-c an opened leaf whose bodies interact directly.
+ * Returns the item count; writes at most cap items. */
+int64_t orc_walk_items(const orc_tree *t, double theta, int gs, int64_t g, int32_t *out, int64_t cap)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+    walk_out w = {0};
+    w.items = malloc(256 * sizeof(int32_t));
+    w.cap = 256;
+    walk_group(t, rc, gs, g, &w);
+    for (int64_t k = 0; k < w.nitems && k < cap; ++k) out[k] = w.items[k];
+    free(w.items);
+    free(rc);
+    return w.nitems;
+}
+
+/* Treecode forces for the bodies of the selected groups (all groups when
+ * groups == NULL): the sum over each body's list of the softened point-mass
+ * interaction, cells as pseudo-bodies of mass M at their centre of mass.
+ * acc [n][dim] and pot [n] are in original body order; only the bodies of
+ * the selected groups are written. */
+void orc_tree_forces(const orc_tree *t, double theta, int gs, double G, double eps,
+                     int64_t ngsel, const int64_t *groups, double *acc, double *pot)
+{
+    const int D = t->dim;
+    const double e2 = eps * eps;
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+    const int64_t NG = groups ? ngsel : (t->n + gs - 1) / gs;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t s = 0; s < NG; ++s) {
+        const int64_t g = groups ? groups[s] : s;
+        walk_out w = {0};
+        w.items = malloc(256 * sizeof(int32_t));
+        w.cap = 256;
+        walk_group(t, rc, gs, g, &w);
+        const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
+        for (int64_t i = b; i < e; ++i) {
+            double a[ORC_MAXD] = {0, 0, 0}, p = 0.0;
+            const double *xi = t->x + i * D;
+            for (int64_t k = 0; k < w.nitems; ++k) {
+                const int32_t it = w.items[k];
+                int64_t jb, je;
+                const double *src, *ms;
+                if (it >= 0) { jb = it; je = it + 1; src = t->com; ms = t->M; }
+                else { const int64_t c = -1 - it; jb = t->begin[c]; je = jb + t->count[c]; src = t->x; ms = t->m; }
+                for (int64_t j = jb; j < je; ++j) {
+                    if (it < 0 && j == i) continue;
+                    double d[ORC_MAXD], r2 = e2;
+                    for (int q = 0; q < D; ++q) { d[q] = src[j * D + q] - xi[q]; r2 += d[q] * d[q]; }
+                    const double inv = 1.0 / sqrt(r2);
+                    const double wv = ms[j] * inv;
+                    p -= wv;
+                    const double w3 = wv * inv * inv;
+                    for (int q = 0; q < D; ++q) a[q] += w3 * d[q];
+                }
+            }
+            const int64_t o = t->perm[i];
+            for (int q = 0; q < D; ++q) acc[o * D + q] = G * a[q];
+            if (pot) pot[o] = G * p;
+        }
+        free(w.items);
+    }
+    free(rc);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
