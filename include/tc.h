@@ -1,0 +1,164 @@
+/*
+ * tc.h - C ABI of the MI355X treecode hot path.
+ *
+ * The library computes softened gravitational accelerations with the
+ * treecode of Duy, Yamazaki & Oyanagi, "Performance Evaluation of Treecode
+ * Algorithm for N-Body Simulation Using GridRPC System", §3.1: bodies are
+ * placed in a quad-tree (2D) or oct-tree (3D) obtained by recursive 4-/8-way
+ * subdivision of space until a subspace holds at most leaf_cap bodies; each
+ * cell stands for its bodies as one body of their total mass at their
+ * centre of mass; a walk from the root puts a cell on the interaction list
+ * when it is distant enough and otherwise descends into its children; the
+ * force on a body (F = G m_a m_b / r^2) is the sum over its list; finally
+ * each body updates its position and velocity.  The step order of the
+ * paper's client program (§3.2: construct the tree, build the lists,
+ * compute the forces, move the bodies) is the call order below.
+ *
+ * Conventions
+ *   - All pointers named dev/pos/mass/vel/acc/pot are DEVICE pointers (HIP
+ *     device memory of the current device) owned by the caller; the library
+ *     never allocates or frees device memory.  Its only device storage is
+ *     the caller's workspace (tc_set_workspace).
+ *   - Positions are [n][dim] row-major, masses [n], velocities [n][dim],
+ *     all of the dtype given to tc_build (TC_F32 or TC_F64), naturally
+ *     aligned.  Accelerations are FP32 [n][dim], potentials FP32 [n], in the
+ *     caller's body order.
+ *   - Every call enqueues work on the stream given to tc_create and returns
+ *     without waiting, except where "synchronises" is stated.  A context is
+ *     not thread-safe and serves one stream.
+ *   - Return values: TC_OK or a negative tc_status_code.  Argument and state
+ *     errors are detected on the host before anything is launched.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_ctx tc_ctx;
+
+enum tc_status_code {
+    TC_OK = 0,
+    TC_EINVAL = -1,      /* bad argument: n, dim, leaf_cap, theta, eps, dt, null/misaligned pointer */
+    TC_EWORKSPACE = -2,  /* no workspace, or smaller than tc_workspace_bytes() */
+    TC_ESTATE = -3,      /* call order violated (see each call) */
+    TC_EHIP = -4,        /* a HIP runtime call or launch failed (tc_strerror names it) */
+    TC_ENONFINITE = -5   /* sticky: a position or mass was NaN/Inf, or a mass was <= 0 */
+};
+
+enum tc_dtype { TC_F32 = 0, TC_F64 = 1 };
+
+/* Largest supported leaf_cap and body count. */
+#define TC_MAX_LEAF_CAP 256
+#define TC_MAX_N 2000000000LL
+
+/* Create a context for dim = 2 or 3 that enqueues on hip_stream (a
+ * hipStream_t; NULL = the null stream).  *out receives the context. */
+int tc_create(tc_ctx **out, int dim, void *hip_stream);
+
+/* Destroy a context (NULL is a no-op).  Does not touch the workspace. */
+void tc_destroy(tc_ctx *ctx);
+
+/* Bytes of device workspace needed for n bodies in dim dimensions with the
+ * given leaf_cap (0 for invalid arguments).  The bound covers the largest
+ * possible tree: at most L * floor(n / (leaf_cap + 1)) internal cells
+ * (L = 21 levels in 3D, 31 in 2D) plus n leaves. */
+size_t tc_workspace_bytes(int64_t n, int dim, int leaf_cap);
+
+/* Hand the context a device workspace of `bytes` bytes, 256-byte aligned,
+ * which it uses until the next tc_set_workspace or tc_destroy.  The caller
+ * keeps ownership. */
+int tc_set_workspace(tc_ctx *ctx, void *dev, size_t bytes);
+
+/* Tree construction (§3.1): root cube, Morton keys, stable radix sort,
+ * gather of bodies into key order, and the cell topology in depth-first
+ * pre-order.  pos/mass are device arrays of `dtype`; the mass pointer is
+ * kept for tc_leapfrog and tc_diag and must stay valid.  1 <= n <= TC_MAX_N,
+ * dim equal to the context's, 1 <= leaf_cap <= TC_MAX_LEAF_CAP.  Non-finite
+ * inputs or non-positive masses raise the sticky TC_ENONFINITE (see
+ * tc_status); the kernels still run to completion on such data. */
+int tc_build(tc_ctx *ctx, const void *pos, const void *mass, int64_t n, int dim,
+             int leaf_cap, int dtype);
+
+/* Cell moments (§3.1: total mass at the centre of mass), bottom-up in FP64,
+ * plus the traceless quadrupole in 3D.  Requires tc_build (TC_ESTATE). */
+int tc_moments(tc_ctx *ctx);
+
+/* Fix the opening parameter theta (0 <= theta <= 1) and prepare each cell's
+ * opening radius r = s/theta + |com - centre| (s the cell side).  A cell is
+ * accepted for a group of 64 Morton-consecutive bodies iff the squared
+ * distance from its centre of mass to the group's bounding box exceeds r^2;
+ * theta = 0 accepts nothing (the direct sum).  Requires tc_moments. */
+int tc_walk(tc_ctx *ctx, double theta);
+
+/* Walk and force summation (§3.1, §3.2): for every body, the softened
+ * acceleration G sum m (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^{3/2} and
+ * potential -G sum m / (|x_j - x_i|^2 + eps^2)^{1/2} over its group's
+ * interaction list (accepted cells as pseudo-bodies, bodies of opened
+ * leaves directly, self excluded), FP32 with compensated accumulation.
+ * eps > 0 and finite, G finite.  acc ([n][dim] FP32) and pot ([n] FP32)
+ * may each be NULL; the results are also kept for tc_leapfrog/tc_diag.
+ * Requires tc_walk. */
+int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
+
+/* One kick-drift-kick leapfrog step of size dt (finite) on pos and vel (in
+ * place, dtype of tc_build, caller order): v += dt/2 a(x); x += dt v;
+ * rebuild, moments, walk and forces at the new x with the last theta, G and
+ * eps; v += dt/2 a(x').  Requires a previous tc_forces. */
+int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
+
+/* FP64 diagnostics of the last forces, with deterministic reductions:
+ * out[0] = 1/2 sum m v^2, out[1] = 1/2 sum m phi, out[2..4] = sum m v,
+ * out[5..7] = sum m a (z entries 0 in 2D).  vel is a device array of the
+ * build dtype; out is HOST memory.  Synchronises.  Requires tc_forces. */
+int tc_diag(tc_ctx *ctx, const void *vel, double out[8]);
+
+/* Synchronise the stream and return TC_OK, the sticky TC_ENONFINITE raised
+ * by a build, or TC_EHIP if an earlier call recorded a HIP failure. */
+int tc_status(tc_ctx *ctx);
+
+/* Static message for a status code (TC_EHIP includes the last HIP error). */
+const char *tc_strerror(int code);
+
+/* ---- inspection (tests and benchmarks) -------------------------------- */
+
+/* Number of cells of the current tree.  Synchronises.  Requires tc_build. */
+int tc_num_cells(tc_ctx *ctx, int64_t *ncells);
+
+/* Root cube: lo[dim] corner and side.  Synchronises.  Requires tc_build. */
+int tc_get_root(tc_ctx *ctx, double *lo, double *size);
+
+/* Copy the sorted keys (u64 [n]) and the permutation (u32 [n], sorted
+ * position -> original index) into device buffers (either may be NULL). */
+int tc_get_keys(tc_ctx *ctx, uint64_t *key_sorted, uint32_t *perm);
+
+/* Copy the per-cell arrays, in pre-order, into device buffers of at least
+ * tc_num_cells() elements (com: [C][dim], Q: [C][6]); any may be NULL.
+ * M/com/Q require tc_moments.  begin/count index the sorted bodies; skip is
+ * the pre-order index just past the cell's subtree; parent is -1 for the
+ * root; leaf is 1 for leaves. */
+int tc_get_cells(tc_ctx *ctx, int32_t *level, uint64_t *prefix, int32_t *begin,
+                 int32_t *count, int32_t *parent, int32_t *skip, int32_t *nch,
+                 int32_t *leaf, double *M, double *com, double *Q);
+
+/* Per-group interaction counts of the last tc_forces (device int64 arrays
+ * of ceil(n/64) entries): accepted cells and bodies of opened leaves. */
+int tc_get_counts(tc_ctx *ctx, int64_t *m2p, int64_t *p2p);
+
+/* Time the force kernel with HIP events on the context's stream: when on,
+ * every tc_forces accumulates the kernel's duration. */
+int tc_set_timing(tc_ctx *ctx, int on);
+
+/* Total milliseconds and launch count of the timed force kernels since
+ * timing was switched on.  Synchronises. */
+int tc_get_timing(tc_ctx *ctx, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

@@ -1,0 +1,423 @@
+// C ABI of the treecode library (declared in include/tc.h): argument and
+// call-order checks, the carve-up of the caller's workspace, and the
+// sequence of launches for each call.  The call order mirrors the client
+// program of §3.2 (construct the tree, build the lists, compute the forces,
+// move the bodies).
+#include "tc.h"
+#include "tc_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+using namespace tc;
+
+namespace {
+
+enum State { kNone = 0, kBuilt = 1, kMoments = 2, kWalked = 3, kForced = 4 };
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+thread_local char g_errbuf[256];
+
+}  // namespace
+
+namespace tc {
+
+Layout make_layout(int64_t n, int dim, int leaf_cap) {
+    Layout l;
+    memset(&l, 0, sizeof(l));
+    l.n = n;
+    l.dim = dim;
+    l.leaf_cap = leaf_cap;
+    l.cmax = (int64_t)levels_for(dim) * (n / (leaf_cap + 1)) + n + 1;
+    l.groups = (n + kGroup - 1) / kGroup;
+    l.sort_tiles = (n + kSortTile - 1) / kSortTile;
+    l.scan_tiles = (n + kScanTile - 1) / kScanTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.off_params = take(sizeof(DevParams));
+    l.off_keys_a = take(8 * (size_t)n);
+    l.off_keys_b = take(8 * (size_t)n);
+    l.off_idx_a = take(4 * (size_t)n);
+    l.off_idx_b = take(4 * (size_t)n);
+    l.off_bodies = take(sizeof(Body) * (size_t)n);
+    l.off_range = take(4 * (size_t)n);
+    l.off_nper = take(4 * (size_t)n);
+    l.off_cstart = take(4 * (size_t)(n + 1));
+    l.off_scan_part = take(4 * (size_t)l.scan_tiles);
+    l.off_hist = take(4 * 256 * (size_t)l.sort_tiles);
+    l.off_digit_tot = take(4 * 256);
+    l.off_cells = take(sizeof(Cell) * (size_t)l.cmax);
+    l.off_mom = take(sizeof(Moments) * (size_t)l.cmax);
+    l.off_walk = take(sizeof(WalkCell) * (size_t)l.cmax);
+    l.off_arrive = take(4 * (size_t)l.cmax);
+    l.off_acc = take(4 * (size_t)n * dim);
+    l.off_pot = take(4 * (size_t)n);
+    l.off_m2p = take(8 * (size_t)l.groups);
+    l.off_p2p = take(8 * (size_t)l.groups);
+    l.off_bbox_part = take(7 * 8 * 1024);
+    l.off_diag_part = take(8 * 8 * (size_t)kDiagBlocks);
+    l.off_diag_out = take(8 * 8);
+    l.total = off;
+    return l;
+}
+
+}  // namespace tc
+
+struct tc_ctx {
+    int dim = 3;
+    hipStream_t stream = nullptr;
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay;
+    int state = kNone;
+    const void* mass = nullptr;
+    int dtype = TC_F32;
+    int64_t n = 0;
+    int leaf_cap = 0;
+    double theta = 0.0, G = 1.0, eps = 0.0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pending;   // (start, stop) pairs not yet summed
+    std::vector<hipEvent_t> ev_pool;
+    double t_total_ms = 0.0;
+    int64_t t_launches = 0;
+    hipError_t last_hip = hipSuccess;
+
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    DevParams* prm() const { return at<DevParams>(lay.off_params); }
+};
+
+namespace {
+
+int hip_fail(tc_ctx* ctx, hipError_t e) {
+    if (ctx) ctx->last_hip = e;
+    snprintf(g_errbuf, sizeof(g_errbuf), "HIP failure: %s", hipGetErrorString(e));
+    return TC_EHIP;
+}
+
+#define TC_HIP(ctx, expr)                                  \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_);  \
+    } while (0)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool valid_sizes(int64_t n, int dim, int leaf_cap) {
+    if (n < 1 || n > TC_MAX_N) return false;
+    if (dim != 2 && dim != 3) return false;
+    if (leaf_cap < 1 || leaf_cap > TC_MAX_LEAF_CAP) return false;
+    const int64_t cmax = (int64_t)levels_for(dim) * (n / (leaf_cap + 1)) + n + 1;
+    return cmax < ((int64_t)1 << 31);
+}
+
+hipEvent_t pooled_event(tc_ctx* ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Everything tc_build enqueues, after its checks.
+int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf_cap, int dtype) {
+    const int dim = ctx->dim;
+    ctx->lay = make_layout(n, dim, leaf_cap);
+    const Layout& l = ctx->lay;
+    const int f64 = dtype == TC_F64;
+    hipStream_t s = ctx->stream;
+    DevParams* prm = ctx->prm();
+    TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part), prm, s));
+    TC_HIP(ctx, launch_keys(pos, n, dim, f64, prm, ctx->at<uint64_t>(l.off_keys_a),
+                            ctx->at<uint32_t>(l.off_idx_a), s));
+    TC_HIP(ctx, launch_sort(ctx->at<uint64_t>(l.off_keys_a), ctx->at<uint32_t>(l.off_idx_a),
+                            ctx->at<uint64_t>(l.off_keys_b), ctx->at<uint32_t>(l.off_idx_b), n,
+                            dim * levels_for(dim), ctx->at<uint32_t>(l.off_hist),
+                            ctx->at<uint32_t>(l.off_digit_tot), l.sort_tiles, s));
+    TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
+                              ctx->at<Body>(l.off_bodies), s));
+    TC_HIP(ctx, launch_topology(ctx->at<uint64_t>(l.off_keys_a), n, dim, leaf_cap,
+                                ctx->at<uint32_t>(l.off_range), ctx->at<uint32_t>(l.off_nper),
+                                ctx->at<uint32_t>(l.off_cstart), ctx->at<uint32_t>(l.off_scan_part),
+                                l.scan_tiles, ctx->at<Cell>(l.off_cells), ctx->at<uint32_t>(l.off_arrive),
+                                l.cmax, prm, s));
+    ctx->mass = mass;
+    ctx->n = n;
+    ctx->leaf_cap = leaf_cap;
+    ctx->dtype = dtype;
+    ctx->state = kBuilt;
+    return TC_OK;
+}
+
+int do_moments(tc_ctx* ctx) {
+    const Layout& l = ctx->lay;
+    TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
+                               ctx->at<Moments>(l.off_mom), ctx->at<WalkCell>(l.off_walk),
+                               ctx->at<uint32_t>(l.off_arrive), ctx->prm(), ctx->stream));
+    ctx->state = kMoments;
+    return TC_OK;
+}
+
+int do_walk(tc_ctx* ctx, double theta) {
+    const Layout& l = ctx->lay;
+    TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta, l.cmax,
+                           ctx->at<WalkCell>(l.off_walk), ctx->prm(), ctx->stream));
+    ctx->theta = theta;
+    ctx->state = kWalked;
+    return TC_OK;
+}
+
+int do_forces(tc_ctx* ctx, double G, double eps) {
+    const Layout& l = ctx->lay;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        e0 = pooled_event(ctx);
+        e1 = pooled_event(ctx);
+        if (!e0 || !e1) return hip_fail(ctx, hipErrorOutOfMemory);
+        TC_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    }
+    TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
+                                  ctx->at<uint32_t>(l.off_idx_a), ctx->n, ctx->dim, (float)G,
+                                  (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
+                                  ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
+                                  ctx->at<int64_t>(l.off_p2p), ctx->stream));
+    if (ctx->timing) {
+        TC_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        ctx->ev_pending.push_back(e0);
+        ctx->ev_pending.push_back(e1);
+    }
+    ctx->G = G;
+    ctx->eps = eps;
+    ctx->state = kForced;
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_create(tc_ctx** out, int dim, void* hip_stream) {
+    if (!out || (dim != 2 && dim != 3)) return TC_EINVAL;
+    tc_ctx* c = new (std::nothrow) tc_ctx();
+    if (!c) return TC_EINVAL;
+    c->dim = dim;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return TC_OK;
+}
+
+void tc_destroy(tc_ctx* ctx) {
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->ev_pending) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+size_t tc_workspace_bytes(int64_t n, int dim, int leaf_cap) {
+    if (!valid_sizes(n, dim, leaf_cap)) return 0;
+    return make_layout(n, dim, leaf_cap).total;
+}
+
+int tc_set_workspace(tc_ctx* ctx, void* dev, size_t bytes) {
+    if (!ctx || !dev || !aligned(dev, 256)) return TC_EINVAL;
+    ctx->ws = (uint8_t*)dev;
+    ctx->ws_bytes = bytes;
+    ctx->state = kNone;
+    return TC_OK;
+}
+
+int tc_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int dim, int leaf_cap,
+             int dtype) {
+    if (!ctx || !pos || !mass) return TC_EINVAL;
+    if (dim != ctx->dim || !valid_sizes(n, dim, leaf_cap)) return TC_EINVAL;
+    if (dtype != TC_F32 && dtype != TC_F64) return TC_EINVAL;
+    const size_t es = dtype == TC_F64 ? 8 : 4;
+    if (!aligned(pos, es) || !aligned(mass, es)) return TC_EINVAL;
+    if (!ctx->ws || ctx->ws_bytes < make_layout(n, dim, leaf_cap).total) return TC_EWORKSPACE;
+    return do_build(ctx, pos, mass, n, leaf_cap, dtype);
+}
+
+int tc_moments(tc_ctx* ctx) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    return do_moments(ctx);
+}
+
+int tc_walk(tc_ctx* ctx, double theta) {
+    if (!ctx) return TC_EINVAL;
+    if (!(theta >= 0.0 && theta <= 1.0)) return TC_EINVAL;
+    if (ctx->state < kMoments) return TC_ESTATE;
+    return do_walk(ctx, theta);
+}
+
+int tc_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
+    if (!ctx) return TC_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
+    if (ctx->state < kWalked) return TC_ESTATE;
+    int rc = do_forces(ctx, G, eps);
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    if (acc)
+        TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * ctx->dim,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (pot)
+        TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
+}
+
+int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
+    if (!ctx || !pos || !vel || !isfinite(dt)) return TC_EINVAL;
+    const size_t es = ctx->dtype == TC_F64 ? 8 : 4;
+    if (!aligned(pos, es) || !aligned(vel, es)) return TC_EINVAL;
+    if (ctx->state < kForced) return TC_ESTATE;
+    const int f64 = ctx->dtype == TC_F64;
+    const float* acc = ctx->at<float>(ctx->lay.off_acc);
+    TC_HIP(ctx, launch_kick_drift(pos, vel, acc, ctx->n, ctx->dim, f64, dt, ctx->stream));
+    int rc = do_build(ctx, pos, ctx->mass, ctx->n, ctx->leaf_cap, ctx->dtype);
+    if (rc == TC_OK) rc = do_moments(ctx);
+    if (rc == TC_OK) rc = do_walk(ctx, ctx->theta);
+    if (rc == TC_OK) rc = do_forces(ctx, ctx->G, ctx->eps);
+    if (rc != TC_OK) return rc;
+    TC_HIP(ctx, launch_kick(vel, acc, ctx->n, ctx->dim, f64, dt, ctx->stream));
+    return TC_OK;
+}
+
+int tc_diag(tc_ctx* ctx, const void* vel, double out[8]) {
+    if (!ctx || !vel || !out) return TC_EINVAL;
+    if (!aligned(vel, ctx->dtype == TC_F64 ? 8 : 4)) return TC_EINVAL;
+    if (ctx->state < kForced) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    double* dout = ctx->at<double>(l.off_diag_out);
+    TC_HIP(ctx, launch_diag(ctx->mass, vel, ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), ctx->n,
+                            ctx->dim, ctx->dtype == TC_F64, ctx->at<double>(l.off_diag_part), dout,
+                            ctx->stream));
+    double host[8];
+    TC_HIP(ctx, hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
+    TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    memcpy(out, host, sizeof(host));
+    return TC_OK;
+}
+
+int tc_status(tc_ctx* ctx) {
+    if (!ctx) return TC_EINVAL;
+    TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->last_hip != hipSuccess) return hip_fail(ctx, ctx->last_hip);
+    if (!ctx->ws || ctx->state < kBuilt) return TC_OK;
+    DevParams p;
+    TC_HIP(ctx, hipMemcpy(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost));
+    if (p.status & kFlagNonFinite) return TC_ENONFINITE;
+    if (p.status & kFlagOverflow) return TC_EWORKSPACE;
+    return TC_OK;
+}
+
+const char* tc_strerror(int code) {
+    switch (code) {
+        case TC_OK: return "ok";
+        case TC_EINVAL: return "invalid argument";
+        case TC_EWORKSPACE: return "workspace missing or too small";
+        case TC_ESTATE: return "call order violated (build -> moments -> walk -> forces -> leapfrog)";
+        case TC_EHIP: return g_errbuf[0] ? g_errbuf : "HIP failure";
+        case TC_ENONFINITE: return "non-finite position or mass, or non-positive mass";
+        default: return "unknown status";
+    }
+}
+
+int tc_num_cells(tc_ctx* ctx, int64_t* ncells) {
+    if (!ctx || !ncells) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    DevParams p;
+    TC_HIP(ctx, hipMemcpyAsync(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost, ctx->stream));
+    TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *ncells = p.ncells < ctx->lay.cmax ? p.ncells : ctx->lay.cmax;
+    return TC_OK;
+}
+
+int tc_get_root(tc_ctx* ctx, double* lo, double* size) {
+    if (!ctx || !lo || !size) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    DevParams p;
+    TC_HIP(ctx, hipMemcpyAsync(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost, ctx->stream));
+    TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int a = 0; a < ctx->dim; ++a) lo[a] = p.lo[a];
+    *size = p.size;
+    return TC_OK;
+}
+
+int tc_get_keys(tc_ctx* ctx, uint64_t* key_sorted, uint32_t* perm) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    if (key_sorted)
+        TC_HIP(ctx, hipMemcpyAsync(key_sorted, ctx->at<uint64_t>(l.off_keys_a), 8 * (size_t)ctx->n,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (perm)
+        TC_HIP(ctx, hipMemcpyAsync(perm, ctx->at<uint32_t>(l.off_idx_a), 4 * (size_t)ctx->n,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
+}
+
+int tc_get_cells(tc_ctx* ctx, int32_t* level, uint64_t* prefix, int32_t* begin, int32_t* count,
+                 int32_t* parent, int32_t* skip, int32_t* nch, int32_t* leaf, double* M, double* com,
+                 double* Q) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    if ((M || com || Q) && ctx->state < kMoments) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    TC_HIP(ctx, launch_export(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, l.cmax,
+                              ctx->prm(), level, prefix, begin, count, parent, skip, nch, leaf, M, com, Q,
+                              ctx->stream));
+    return TC_OK;
+}
+
+int tc_get_counts(tc_ctx* ctx, int64_t* m2p, int64_t* p2p) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kForced) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    if (m2p)
+        TC_HIP(ctx, hipMemcpyAsync(m2p, ctx->at<int64_t>(l.off_m2p), 8 * (size_t)l.groups,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (p2p)
+        TC_HIP(ctx, hipMemcpyAsync(p2p, ctx->at<int64_t>(l.off_p2p), 8 * (size_t)l.groups,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
+}
+
+int tc_set_timing(tc_ctx* ctx, int on) {
+    if (!ctx) return TC_EINVAL;
+    ctx->timing = on != 0;
+    ctx->t_total_ms = 0.0;
+    ctx->t_launches = 0;
+    return TC_OK;
+}
+
+int tc_get_timing(tc_ctx* ctx, double* total_ms, int64_t* launches) {
+    if (!ctx || !total_ms || !launches) return TC_EINVAL;
+    for (size_t k = 0; k + 1 < ctx->ev_pending.size(); k += 2) {
+        TC_HIP(ctx, hipEventSynchronize(ctx->ev_pending[k + 1]));
+        float ms = 0.f;
+        TC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_pending[k], ctx->ev_pending[k + 1]));
+        ctx->t_total_ms += ms;
+        ctx->t_launches += 1;
+        ctx->ev_pool.push_back(ctx->ev_pending[k]);
+        ctx->ev_pool.push_back(ctx->ev_pending[k + 1]);
+    }
+    ctx->ev_pending.clear();
+    *total_ms = ctx->t_total_ms;
+    *launches = ctx->t_launches;
+    return TC_OK;
+}
+
+}  // extern "C"

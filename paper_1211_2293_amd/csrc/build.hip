@@ -1,0 +1,756 @@
+// Tree construction and cell moments (§3.1 of the paper: recursive 4-/8-way
+// subdivision until a subspace holds at most leaf_cap bodies; each cell is
+// its bodies' total mass at their centre of mass).
+//
+// Pipeline, one stream, no host synchronisation:
+//   bbox     root cube: per-axis minimum corner, power-of-two side (FP64)
+//   keys     Morton key of FP64-quantised coordinates, index iota
+//   sort     stable LSD radix sort of (key, index), 8 bits per pass
+//   gather   bodies into key order, FP64
+//   topology all cells at once from the sorted keys (no per-level launches):
+//            body i starts the cells of levels a_i..l*_i, where a_i is one
+//            more than its common-prefix length with body i-1 and l*_i is
+//            one below the deepest level at which a run of leaf_cap+1
+//            consecutive keys around i still shares a prefix; their
+//            exclusive scan is the depth-first pre-order index
+//   moments  FP64, leaves over bodies in order, parents over children in
+//            digit order, driven bottom-up by arrival counters
+//   mac      opening radius per cell for the current theta
+//
+// Every expression that decides an integer (keys, topology, opening radii)
+// is compiled without floating-point contraction.
+#include "tc_internal.h"
+
+#include <math.h>
+
+namespace tc {
+namespace {
+
+__device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
+
+// ---------------------------------------------------------------- bbox ----
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_bbox_part(const T* __restrict__ pos, const T* __restrict__ mass,
+                                                   int64_t n, double* __restrict__ part) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double v = (double)pos[i * D + a];
+            if (!isfinite(v)) { bad = 1; continue; }
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+        const double m = (double)mass[i];
+        if (!(isfinite(m) && m > 0.0)) bad = 1;
+    }
+    __shared__ double s_lo[3][256], s_hi[3][256];
+    __shared__ int s_bad[256];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { s_lo[a][t] = lo[a]; s_hi[a][t] = hi[a]; }
+    s_bad[t] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s_lo[a][t] = fmin(s_lo[a][t], s_lo[a][t + w]);
+                s_hi[a][t] = fmax(s_hi[a][t], s_hi[a][t + w]);
+            }
+            s_bad[t] |= s_bad[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* o = part + blockIdx.x * 7;
+        for (int a = 0; a < 3; ++a) { o[a] = s_lo[a][0]; o[3 + a] = s_hi[a][0]; }
+        o[6] = (double)s_bad[0];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ part, int nb, int dim,
+                                                    DevParams* prm) {
+    __shared__ double s_lo[3][256], s_hi[3][256];
+    __shared__ int s_bad[256];
+    const int t = threadIdx.x;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int b = t; b < nb; b += 256) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], part[b * 7 + a]);
+            hi[a] = fmax(hi[a], part[b * 7 + 3 + a]);
+        }
+        bad |= part[b * 7 + 6] != 0.0;
+    }
+    for (int a = 0; a < 3; ++a) { s_lo[a][t] = lo[a]; s_hi[a][t] = hi[a]; }
+    s_bad[t] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int a = 0; a < 3; ++a) {
+                s_lo[a][t] = fmin(s_lo[a][t], s_lo[a][t + w]);
+                s_hi[a][t] = fmax(s_hi[a][t], s_hi[a][t + w]);
+            }
+            s_bad[t] |= s_bad[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int L = dim == 3 ? 21 : 31;
+        double ext = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            double l = s_lo[a][0];
+            if (!isfinite(l)) l = 0.0;            // no finite coordinate on this axis
+            prm->lo[a] = l;
+            const double e = s_hi[a][0] - s_lo[a][0];
+            if (e > ext) ext = e;
+        }
+        for (int a = dim; a < 3; ++a) prm->lo[a] = 0.0;
+        double size = 1.0;
+        if (ext > 0.0 && isfinite(ext)) {
+            int e2;
+            const double f = frexp(ext, &e2);     // ext = f 2^e2, f in [0.5, 1)
+            size = (f == 0.5) ? ext : ldexp(1.0, e2);
+        }
+        int e2;
+        frexp(size, &e2);                         // size = 2^(e2-1)
+        prm->size = size;
+        prm->scale = ldexp(1.0, L - (e2 - 1));
+        prm->status = s_bad[0] ? kFlagNonFinite : 0u;
+        prm->ncells = 0;
+    }
+}
+
+// ---------------------------------------------------------------- keys ----
+
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {   // bit b -> bit 3b (21 bits)
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t spread2(uint64_t x) {   // bit b -> bit 2b (32 bits)
+    x &= 0xffffffffull;
+    x = (x | x << 16) & 0x0000ffff0000ffffull;
+    x = (x | x << 8) & 0x00ff00ff00ff00ffull;
+    x = (x | x << 4) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | x << 2) & 0x3333333333333333ull;
+    x = (x | x << 1) & 0x5555555555555555ull;
+    return x;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double scale) {
+    constexpr int L = D == 3 ? 21 : 31;
+    const double top = (double)((1ull << L) - 1ull);
+    double f = floor((x - lo) * scale);
+    if (!(f >= 0.0)) f = 0.0;                     // also catches NaN
+    if (f > top) f = top;
+    return (uint64_t)f;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t n,
+                                              const DevParams* __restrict__ prm,
+                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+    const double scale = prm->scale;
+    const double lo0 = prm->lo[0], lo1 = prm->lo[1], lo2 = prm->lo[2];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t key;
+        if (D == 3) {
+            const uint64_t qx = quantise<3>((double)pos[i * 3 + 0], lo0, scale);
+            const uint64_t qy = quantise<3>((double)pos[i * 3 + 1], lo1, scale);
+            const uint64_t qz = quantise<3>((double)pos[i * 3 + 2], lo2, scale);
+            key = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+        } else {
+            const uint64_t qx = quantise<2>((double)pos[i * 2 + 0], lo0, scale);
+            const uint64_t qy = quantise<2>((double)pos[i * 2 + 1], lo1, scale);
+            key = (spread2(qx) << 1) | spread2(qy);
+        }
+        keys[i] = key;
+        idx[i] = (uint32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------- sort ----
+// Reduce-then-scan LSD radix sort: per tile digit counts, a scan of the
+// counts in digit-major order, then a stable scatter in which each wave
+// ranks its keys with ballot-based digit matching.
+
+__global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                   uint32_t* __restrict__ hist, int64_t tiles) {
+    __shared__ uint32_t cnt[4][256];
+    const int t = threadIdx.x, w = t >> 6;
+    for (int a = 0; a < 4; ++a) cnt[a][t] = 0;
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kSortTile;
+#pragma unroll 4
+    for (int j = 0; j < kSortTile / 256; ++j) {
+        const int64_t i = base + j * 256 + t;
+        if (i < n) atomicAdd(&cnt[w][(unsigned)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)t * tiles + tile] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+}
+
+// Exclusive block scan of one value per thread (256 threads); returns the
+// prefix, writes the block total into *total (shared).
+__device__ __forceinline__ uint32_t block_exscan_u32(uint32_t v, uint32_t* s_w, uint32_t* total) {
+    const int lane = wave_lane(), w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) s_w[w] = x;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int k = 0; k < w; ++k) wbase += s_w[k];
+    if (threadIdx.x == 255) *total = wbase + x;
+    __syncthreads();
+    return wbase + x - v;
+}
+
+__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, int64_t tiles,
+                                                   uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tot;
+    uint32_t* h = hist + (int64_t)blockIdx.x * tiles;
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < tiles; c += 256) {
+        const int64_t i = c + threadIdx.x;
+        const uint32_t v = i < tiles ? h[i] : 0u;
+        const uint32_t ex = block_exscan_u32(v, s_w, &s_tot);
+        if (i < tiles) h[i] = carry + ex;
+        carry += s_tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      int64_t n, int shift, const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ digit_tot, int64_t tiles) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tot;
+    const int t = threadIdx.x, w = t >> 6, lane = wave_lane();
+    const int64_t tile = blockIdx.x;
+    const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
+    s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
+    for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kSortTile / 256; ++r) {
+        const int64_t i = tile * kSortTile + r * 256 + t;
+        const bool valid = i < n;
+        const uint64_t k = valid ? kin[i] : 0ull;
+        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint64_t before = peers & lt;
+        if (valid && before == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t p = s_base[d] + (uint32_t)__popcll(before);
+            for (int a = 0; a < w; ++a) p += s_wcnt[a][d];
+            kout[p] = k;
+            vout[p] = v;
+        }
+        __syncthreads();
+        s_base[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
+        for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------- gather ----
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
+                                                const uint32_t* __restrict__ perm, int64_t n,
+                                                Body* __restrict__ bodies) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm[i];
+        Body b;
+        b.x = (double)pos[o * D + 0];
+        b.y = (double)pos[o * D + 1];
+        b.z = D == 3 ? (double)pos[o * D + 2] : 0.0;
+        b.m = (double)mass[o];
+        bodies[i] = b;
+    }
+}
+
+// ---------------------------------------------------------------- scan ----
+// Exclusive scan of u32 values: out[i] = sum_{j<i} in[j], out[n] = total.
+
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                     uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tot;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int j = 0; j < kScanTile / 256; ++j) {
+        const int64_t i = base + j * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    block_exscan_u32(s, s_w, &s_tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = s_tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_part(uint32_t* __restrict__ part, int64_t tiles,
+                                                   uint32_t* __restrict__ out, int64_t n) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tot;
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < tiles; c += 256) {
+        const int64_t i = c + threadIdx.x;
+        const uint32_t v = i < tiles ? part[i] : 0u;
+        const uint32_t ex = block_exscan_u32(v, s_w, &s_tot);
+        if (i < tiles) part[i] = carry + ex;
+        carry += s_tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                    const uint32_t* __restrict__ part,
+                                                    uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tot;
+    constexpr int kItems = kScanTile / 256;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : 0u;
+        s += v[j];
+    }
+    uint32_t run = part[blockIdx.x] + block_exscan_u32(s, s_w, &s_tot);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+}
+
+// ------------------------------------------------------------ topology ----
+
+// Number of leading Morton digits two keys share (L if equal).
+template <int D>
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+    const uint64_t x = a ^ b;
+    if (x == 0) return D == 3 ? 21 : 31;
+    const int z = __clzll(x);
+    return D == 3 ? (z - 1) / 3 : (z - 2) / 2;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_topo_count(const uint64_t* __restrict__ keys, int64_t n, int leaf_cap,
+                                                    uint32_t* __restrict__ range, uint32_t* __restrict__ nper) {
+    constexpr int L = D == 3 ? 21 : 31;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (i == 0) ? 0 : common_digits<D>(keys[i - 1], keys[i]) + 1;
+        // deepest level whose cell around i holds more than leaf_cap bodies
+        int deep = -1;
+        int64_t j0 = i - leaf_cap;
+        if (j0 < 0) j0 = 0;
+        int64_t j1 = n - 1 - leaf_cap;
+        if (j1 > i) j1 = i;
+        for (int64_t j = j0; j <= j1; ++j) {
+            const int c = common_digits<D>(keys[j], keys[j + leaf_cap]);
+            deep = c > deep ? c : deep;
+        }
+        int lstar = 0;
+        if (deep >= 0) lstar = (deep < L - 1 ? deep : L - 1) + 1;
+        range[i] = (uint32_t)a | ((uint32_t)lstar << 8);
+        nper[i] = lstar >= a ? (uint32_t)(lstar - a + 1) : 0u;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_topo_emit(const uint64_t* __restrict__ keys, int64_t n,
+                                                   const uint32_t* __restrict__ range,
+                                                   const uint32_t* __restrict__ cstart, Cell* __restrict__ cells,
+                                                   int64_t cmax, DevParams* prm) {
+    constexpr int L = D == 3 ? 21 : 31;
+    const uint32_t C = cstart[n];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // C never exceeds the bound (internal cells are disjoint per level
+        // and hold > leaf_cap bodies); clamp anyway so no reader can run off
+        prm->ncells = (int64_t)C > cmax ? (uint32_t)cmax : C;
+        if ((int64_t)C > cmax) atomicOr(&prm->status, kFlagOverflow);
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(range[i] & 255u), lstar = (int)(range[i] >> 8);
+        if (lstar < a) continue;
+        const uint32_t base = cstart[i];
+        const uint64_t key = keys[i];
+        for (int l = a; l <= lstar; ++l) {
+            const int64_t k = (int64_t)base + (l - a);
+            if (k >= cmax) break;
+            const int shift = D * (L - l);
+            const uint64_t prefix = l == 0 ? 0ull : key >> shift;
+            int64_t end = n;
+            if (l > 0) {
+                // first body after i whose level-l prefix differs: gallop, then bisect
+                int64_t lo = i, step = 1, hi = i + 1;
+                while (hi < n && (keys[hi] >> shift) == prefix) {
+                    lo = hi;
+                    step <<= 1;
+                    hi = i + step;
+                }
+                if (hi > n) hi = n;
+                while (hi - lo > 1) {
+                    const int64_t mid = lo + ((hi - lo) >> 1);
+                    if ((keys[mid] >> shift) == prefix) lo = mid; else hi = mid;
+                }
+                end = hi;
+            }
+            Cell c;
+            c.prefix = prefix;
+            c.begin = (int32_t)i;
+            c.count = (int32_t)(end - i);
+            c.skip = (int32_t)cstart[end];
+            c.parent = (l == 0) ? -1 : (l > a ? (int32_t)(k - 1) : -2);
+            c.level = l;
+            c.leaf_nch = (l == lstar) ? (int32_t)0x80000000u : 0;
+            cells[k] = c;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_topo_link(Cell* __restrict__ cells, uint32_t* __restrict__ arrive,
+                                                   const DevParams* __restrict__ prm, int64_t cmax) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        arrive[k] = 0;
+        const Cell c = cells[k];
+        if (c.leaf_nch < 0) continue;          // leaf
+        int nch = 0;
+        int64_t ch = k + 1;
+        const int64_t end = c.skip < C ? c.skip : C;
+        while (ch < end) {
+            cells[ch].parent = (int32_t)k;
+            ++nch;
+            const int64_t nx = cells[ch].skip;
+            ch = nx > ch ? nx : end;           // defensive: the skip chain only moves forward
+        }
+        cells[k].leaf_nch = nch;
+    }
+}
+
+// ------------------------------------------------------------- moments ----
+
+template <int D>
+__device__ void leaf_moments(const Cell& c, const Body* __restrict__ bodies, Moments& mo) {
+    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int32_t j = c.begin; j < c.begin + c.count; ++j) {
+        const Body b = bodies[j];
+        M = M + b.m;
+        S0 = S0 + b.m * b.x;
+        S1 = S1 + b.m * b.y;
+        if (D == 3) S2 = S2 + b.m * b.z;
+    }
+    mo.M = M;
+    mo.S[0] = S0; mo.S[1] = S1; mo.S[2] = S2;
+    mo.com[0] = S0 / M; mo.com[1] = S1 / M; mo.com[2] = D == 3 ? S2 / M : 0.0;
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    if (D == 3) {
+        for (int32_t j = c.begin; j < c.begin + c.count; ++j) {
+            const Body b = bodies[j];
+            const double d0 = b.x - mo.com[0], d1 = b.y - mo.com[1], d2 = b.z - mo.com[2];
+            const double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+            Q[0] = Q[0] + b.m * ((3.0 * d0) * d0 - r2);
+            Q[1] = Q[1] + b.m * ((3.0 * d1) * d1 - r2);
+            Q[2] = Q[2] + b.m * ((3.0 * d2) * d2 - r2);
+            Q[3] = Q[3] + b.m * ((3.0 * d0) * d1);
+            Q[4] = Q[4] + b.m * ((3.0 * d0) * d2);
+            Q[5] = Q[5] + b.m * ((3.0 * d1) * d2);
+        }
+    }
+    for (int q = 0; q < 6; ++q) mo.Q[q] = Q[q];
+    mo.pad = 0.0;
+}
+
+template <int D>
+__device__ void internal_moments(int64_t p, const Cell* __restrict__ cells, const Moments* mom, Moments& mo) {
+    const int64_t end = cells[p].skip;
+    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int64_t ch = p + 1; ch < end; ch = cells[ch].skip) {
+        M = M + mom[ch].M;
+        S0 = S0 + mom[ch].S[0];
+        S1 = S1 + mom[ch].S[1];
+        if (D == 3) S2 = S2 + mom[ch].S[2];
+    }
+    mo.M = M;
+    mo.S[0] = S0; mo.S[1] = S1; mo.S[2] = S2;
+    mo.com[0] = S0 / M; mo.com[1] = S1 / M; mo.com[2] = D == 3 ? S2 / M : 0.0;
+    double Q[6] = {0, 0, 0, 0, 0, 0};
+    if (D == 3) {
+        for (int64_t ch = p + 1; ch < end; ch = cells[ch].skip) {
+            const double s0 = mom[ch].com[0] - mo.com[0];
+            const double s1 = mom[ch].com[1] - mo.com[1];
+            const double s2 = mom[ch].com[2] - mo.com[2];
+            const double r2 = (s0 * s0 + s1 * s1) + s2 * s2;
+            const double Mc = mom[ch].M;
+            Q[0] = Q[0] + (mom[ch].Q[0] + Mc * ((3.0 * s0) * s0 - r2));
+            Q[1] = Q[1] + (mom[ch].Q[1] + Mc * ((3.0 * s1) * s1 - r2));
+            Q[2] = Q[2] + (mom[ch].Q[2] + Mc * ((3.0 * s2) * s2 - r2));
+            Q[3] = Q[3] + (mom[ch].Q[3] + Mc * ((3.0 * s0) * s1));
+            Q[4] = Q[4] + (mom[ch].Q[4] + Mc * ((3.0 * s0) * s2));
+            Q[5] = Q[5] + (mom[ch].Q[5] + Mc * ((3.0 * s1) * s2));
+        }
+    }
+    for (int q = 0; q < 6; ++q) mo.Q[q] = Q[q];
+    mo.pad = 0.0;
+}
+
+__device__ __forceinline__ void store_walk(WalkCell* walk, int64_t k, const Cell& c, const Moments& mo) {
+    WalkCell w;
+    w.cx = mo.com[0];
+    w.cy = mo.com[1];
+    w.cz = mo.com[2];
+    w.rcrit2 = INFINITY;
+    w.m = (float)mo.M;
+    w.skip = c.skip;
+    w.begin = c.begin;
+    w.cnt_leaf = (c.count & 0x7fffffff) | (c.leaf_nch < 0 ? (int32_t)0x80000000u : 0);
+    walk[k] = w;
+}
+
+// One thread per leaf; the last child to arrive at a parent computes it
+// (children in digit order), so results do not depend on arrival order.
+template <int D>
+__global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
+                                                 Moments* mom, WalkCell* __restrict__ walk,
+                                                 uint32_t* arrive, const DevParams* __restrict__ prm,
+                                                 int64_t cmax) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const Cell c = cells[k];
+        if (c.leaf_nch >= 0) continue;
+        Moments mo;
+        leaf_moments<D>(c, bodies, mo);
+        mom[k] = mo;
+        store_walk(walk, k, c, mo);
+        int64_t cur = k;
+        while (true) {
+            const int64_t p = cells[cur].parent;
+            if (p < 0) break;
+            __threadfence();                        // publish this child's moments
+            const uint32_t nch = (uint32_t)(cells[p].leaf_nch & 0x7fffffff);
+            const uint32_t old = atomicAdd(&arrive[p], 1u);
+            if (old + 1 != nch) break;              // a sibling is still missing
+            __threadfence();                        // see every sibling's moments
+            const Cell cp = cells[p];
+            Moments mp;
+            internal_moments<D>(p, cells, mom, mp);
+            mom[p] = mp;
+            store_walk(walk, p, cp, mp);
+            cur = p;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- mac ----
+
+template <int D>
+__global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
+                                             double theta, WalkCell* __restrict__ walk,
+                                             const DevParams* __restrict__ prm, int64_t cmax) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    const double size = prm->size;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (theta == 0.0) {
+            walk[k].rcrit2 = INFINITY;
+            continue;
+        }
+        const Cell c = cells[k];
+        const int l = c.level;
+        const double s = ldexp(size, -l);
+        uint64_t org[3] = {0, 0, 0};
+        for (int j = 1; j <= l; ++j) {
+            const unsigned d = (unsigned)((c.prefix >> (D * (l - j))) & ((1u << D) - 1u));
+#pragma unroll
+            for (int a = 0; a < D; ++a) org[a] = (org[a] << 1) | ((d >> (D - 1 - a)) & 1u);
+        }
+        double dd[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double centre = prm->lo[a] + ((double)org[a] + 0.5) * s;
+            dd[a] = mom[k].com[a] - centre;
+        }
+        double d2 = dd[0] * dd[0] + dd[1] * dd[1];
+        if (D == 3) d2 = d2 + dd[2] * dd[2];
+        const double r = s / theta + sqrt(d2);
+        walk[k].rcrit2 = r * r;
+    }
+}
+
+// -------------------------------------------------------------- export ----
+
+__global__ void __launch_bounds__(256) k_export(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
+                                                int dim, const DevParams* __restrict__ prm, int64_t cmax,
+                                                int32_t* level, uint64_t* prefix, int32_t* begin,
+                                                int32_t* count, int32_t* parent, int32_t* skip,
+                                                int32_t* nch, int32_t* leaf, double* M, double* com,
+                                                double* Q) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const Cell c = cells[k];
+        if (level) level[k] = c.level;
+        if (prefix) prefix[k] = c.prefix;
+        if (begin) begin[k] = c.begin;
+        if (count) count[k] = c.count;
+        if (parent) parent[k] = c.parent;
+        if (skip) skip[k] = c.skip;
+        if (nch) nch[k] = c.leaf_nch < 0 ? 0 : c.leaf_nch;
+        if (leaf) leaf[k] = c.leaf_nch < 0 ? 1 : 0;
+        if (M) M[k] = mom[k].M;
+        if (com)
+            for (int a = 0; a < dim; ++a) com[k * dim + a] = mom[k].com[a];
+        if (Q)
+            for (int q = 0; q < 6; ++q) Q[k * 6 + q] = mom[k].Q[q];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers ----
+
+hipError_t launch_bbox(const void* pos, const void* mass, int64_t n, int dim, int f64,
+                       double* part, DevParams* prm, hipStream_t s) {
+    const unsigned nb = grid_for(n, 1024);
+    if (f64) {
+        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part);
+        else hipLaunchKernelGGL((k_bbox_part<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part);
+    } else {
+        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part);
+        else hipLaunchKernelGGL((k_bbox_part<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part);
+    }
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, (int)nb, dim, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevParams* prm,
+                       uint64_t* keys, uint32_t* idx, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    if (f64) {
+        if (dim == 3) hipLaunchKernelGGL((k_keys<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, n, prm, keys, idx);
+        else hipLaunchKernelGGL((k_keys<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, n, prm, keys, idx);
+    } else {
+        if (dim == 3) hipLaunchKernelGGL((k_keys<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, n, prm, keys, idx);
+        else hipLaunchKernelGGL((k_keys<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, n, prm, keys, idx);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
+                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
+                       int64_t tiles, hipStream_t s) {
+    const int passes = (key_bits + 7) / 8;    // even for 62/63-bit keys: result lands in _a
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const bool even = (p % 2) == 0;
+        const uint64_t* kin = even ? keys_a : keys_b;
+        const uint32_t* vin = even ? idx_a : idx_b;
+        uint64_t* kout = even ? keys_b : keys_a;
+        uint32_t* vout = even ? idx_b : idx_a;
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout, n,
+                           shift, (const uint32_t*)hist, (const uint32_t*)digit_tot, tiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
+                         int dim, int f64, Body* bodies, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    if (f64) {
+        if (dim == 3) hipLaunchKernelGGL((k_gather<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies);
+        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies);
+    } else {
+        if (dim == 3) hipLaunchKernelGGL((k_gather<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies);
+        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
+                           uint32_t* range, uint32_t* nper, uint32_t* cstart,
+                           uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
+                           uint32_t* arrive, int64_t cmax, DevParams* prm, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    if (dim == 3) hipLaunchKernelGGL(k_topo_count<3>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
+    else hipLaunchKernelGGL(k_topo_count<2>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n, scan_part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, cstart, n);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n,
+                       (const uint32_t*)scan_part, cstart);
+    if (dim == 3) hipLaunchKernelGGL(k_topo_emit<3>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
+    else hipLaunchKernelGGL(k_topo_emit<2>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
+    hipLaunchKernelGGL(k_topo_link, dim3(grid_for(cmax)), dim3(256), 0, s, cells, arrive, (const DevParams*)prm, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
+                          Moments* mom, WalkCell* walk, uint32_t* arrive, const DevParams* prm,
+                          hipStream_t s) {
+    const unsigned nb = grid_for(cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_moments<3>, dim3(nb), dim3(256), 0, s, cells, bodies, mom, walk, arrive, prm, cmax);
+    else hipLaunchKernelGGL(k_moments<2>, dim3(nb), dim3(256), 0, s, cells, bodies, mom, walk, arrive, prm, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
+                      WalkCell* walk, const DevParams* prm, hipStream_t s) {
+    const unsigned nb = grid_for(cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_mac<3>, dim3(nb), dim3(256), 0, s, cells, mom, theta, walk, prm, cmax);
+    else hipLaunchKernelGGL(k_mac<2>, dim3(nb), dim3(256), 0, s, cells, mom, theta, walk, prm, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t cmax,
+                         const DevParams* prm, int32_t* level, uint64_t* prefix, int32_t* begin,
+                         int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
+                         int32_t* leaf, double* M, double* com, double* Q, hipStream_t s) {
+    hipLaunchKernelGGL(k_export, dim3(grid_for(cmax)), dim3(256), 0, s, cells, mom, dim, prm, cmax, level,
+                       prefix, begin, count, parent, skip, nch, leaf, M, com, Q);
+    return hipGetLastError();
+}
+
+}  // namespace tc

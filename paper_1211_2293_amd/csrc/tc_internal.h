@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP translation units of libtc.
+// Not part of the public ABI (include/tc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tc {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kGroup = 64;          // bodies per walk group = one wave
+constexpr int kSortTile = 4096;     // keys per radix-sort tile (256 threads x 16)
+constexpr int kScanTile = 4096;     // elements per scan tile
+constexpr int kDiagBlocks = 512;    // fixed partial count of the FP64 diagnostics
+
+// Status bits raised by kernels into the workspace's status word.
+constexpr uint32_t kFlagNonFinite = 1u;
+constexpr uint32_t kFlagOverflow = 2u;   // cell bound exceeded (never expected)
+
+inline int levels_for(int dim) { return dim == 3 ? 21 : 31; }
+
+// A body in key order: FP64 position and mass (z = 0 in 2D).
+struct __align__(32) Body {
+    double x, y, z, m;
+};
+
+// Topology of one cell (pre-order index k).
+struct __align__(16) Cell {
+    uint64_t prefix;   // key prefix: the top level*dim bits of its bodies' keys
+    int32_t begin;     // first sorted body
+    int32_t count;     // number of bodies
+    int32_t skip;      // pre-order index just past the subtree
+    int32_t parent;    // -1 for the root
+    int32_t level;
+    int32_t leaf_nch;  // bit 31: leaf; low bits: number of children
+};
+
+// FP64 moments of one cell: total mass, mass-weighted position sum, centre
+// of mass and traceless quadrupole (xx, yy, zz, xy, xz, yz).
+struct __align__(16) Moments {
+    double M;
+    double S[3];
+    double com[3];
+    double Q[6];
+    double pad;
+};
+
+// What the walk reads per cell: 48 bytes, one lane per cell.
+struct __align__(16) WalkCell {
+    double cx, cy, cz;   // centre of mass (FP64)
+    double rcrit2;       // squared opening radius for the current theta
+    float m;             // total mass, FP32
+    int32_t skip;        // pre-order index past the subtree
+    int32_t begin;       // first sorted body
+    int32_t cnt_leaf;    // bit 31: leaf; low 31 bits: body count
+};
+
+// Device-side scalars computed by the kernels.
+struct DevParams {
+    double lo[3];        // root cube corner
+    double size;         // root cube side (a power of two)
+    double scale;        // 2^L / size
+    uint32_t ncells;
+    uint32_t status;     // kFlag* bits, sticky until the next build
+};
+
+// Carve-up of the caller's workspace.
+struct Layout {
+    int64_t n;
+    int dim, leaf_cap;
+    int64_t cmax;        // cell bound
+    int64_t groups;      // ceil(n / 64)
+    int64_t sort_tiles;
+    int64_t scan_tiles;
+    size_t off_params, off_keys_a, off_keys_b, off_idx_a, off_idx_b, off_bodies, off_range,
+        off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
+        off_walk, off_arrive, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
+        off_diag_out, total;
+};
+
+Layout make_layout(int64_t n, int dim, int leaf_cap);
+
+// ---- launchers (all enqueue on `s`, return hipSuccess or the launch error)
+// build.hip
+hipError_t launch_bbox(const void* pos, const void* mass, int64_t n, int dim, int f64,
+                       double* part, DevParams* prm, hipStream_t s);
+hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevParams* prm,
+                       uint64_t* keys, uint32_t* idx, hipStream_t s);
+hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
+                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
+                       int64_t tiles, hipStream_t s);
+hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
+                         int dim, int f64, Body* bodies, hipStream_t s);
+hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
+                           uint32_t* range, uint32_t* nper, uint32_t* cstart,
+                           uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
+                           uint32_t* arrive, int64_t cmax, DevParams* prm, hipStream_t s);
+hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
+                          Moments* mom, WalkCell* walk, uint32_t* arrive, const DevParams* prm,
+                          hipStream_t s);
+hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
+                      WalkCell* walk, const DevParams* prm, hipStream_t s);
+hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t cmax,
+                         const DevParams* prm, int32_t* level, uint64_t* prefix, int32_t* begin,
+                         int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
+                         int32_t* leaf, double* M, double* com, double* Q, hipStream_t s);
+// force.hip
+hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uint32_t* perm,
+                             int64_t n, int dim, float G, float eps2, const DevParams* prm,
+                             float* acc, float* pot, int64_t* m2p, int64_t* p2p, hipStream_t s);
+// step.hip
+hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,
+                             double dt, hipStream_t s);
+hipError_t launch_kick(void* vel, const float* acc, int64_t n, int dim, int f64, double dt,
+                       hipStream_t s);
+hipError_t launch_diag(const void* mass, const void* vel, const float* acc, const float* pot,
+                       int64_t n, int dim, int f64, double* part, double* out, hipStream_t s);
+
+// Grid size for grid-stride loops over `work` items with 256-thread blocks.
+inline unsigned grid_for(int64_t work, int64_t cap = 16384) {
+    int64_t b = (work + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace tc

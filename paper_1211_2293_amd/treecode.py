@@ -1,0 +1,255 @@
+"""Python binding of libtc (include/tc.h): argument marshalling only.
+
+Every step of the treecode runs in the HIP kernels of ``libtc.so``; PyTorch
+provides device memory (tensors) and the stream.  If the library has not
+been built this module raises on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tc.h")
+
+TC_OK, TC_EINVAL, TC_EWORKSPACE, TC_ESTATE, TC_EHIP, TC_ENONFINITE = 0, -1, -2, -3, -4, -5
+TC_F32, TC_F64 = 0, 1
+GROUP = 64
+
+_LIB = None
+
+
+class TcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tc error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libtc.so (built by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "tc_create": (i32, [C.POINTER(C.c_void_p), i32, P]),
+        "tc_destroy": (None, [P]),
+        "tc_workspace_bytes": (sz, [i64, i32, i32]),
+        "tc_set_workspace": (i32, [P, P, sz]),
+        "tc_build": (i32, [P, P, P, i64, i32, i32, i32]),
+        "tc_moments": (i32, [P]),
+        "tc_walk": (i32, [P, dbl]),
+        "tc_forces": (i32, [P, dbl, dbl, P, P]),
+        "tc_leapfrog": (i32, [P, dbl, P, P]),
+        "tc_diag": (i32, [P, P, P]),
+        "tc_status": (i32, [P]),
+        "tc_strerror": (C.c_char_p, [i32]),
+        "tc_num_cells": (i32, [P, C.POINTER(C.c_int64)]),
+        "tc_get_root": (i32, [P, P, P]),
+        "tc_get_keys": (i32, [P, P, P]),
+        "tc_get_cells": (i32, [P] * 12),
+        "tc_get_counts": (i32, [P, P, P]),
+        "tc_set_timing": (i32, [P, i32]),
+        "tc_get_timing": (i32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/tc.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_]+)\s*\(", text)))
+
+
+def _check(rc: int):
+    if rc != TC_OK:
+        raise TcError(rc, lib().tc_strerror(rc).decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(n: int, dim: int, leaf_cap: int) -> int:
+    return int(lib().tc_workspace_bytes(n, dim, leaf_cap))
+
+
+class Treecode:
+    """One treecode context bound to a stream (default: torch's current).
+
+    ``build(pos, mass)`` -> ``moments()`` -> ``walk(theta)`` ->
+    ``forces(G, eps)`` -> ``leapfrog(dt, pos, vel)``, mirroring the C calls.
+    The workspace is a torch uint8 tensor grown on demand.
+    """
+
+    def __init__(self, dim: int, leaf_cap: int = 16, stream: torch.cuda.Stream | None = None):
+        self.dim = dim
+        self.leaf_cap = leaf_cap
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().tc_create(C.byref(h), dim, C.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+        self._ws = None
+        self._ws_bytes = 0
+        self._keep = ()
+        self.n = 0
+        self.dtype = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.tc_destroy(h)
+            self._h = None
+
+    # -- plumbing ----------------------------------------------------------
+    def _ensure_ws(self, n: int):
+        need = workspace_bytes(n, self.dim, self.leaf_cap)
+        if need == 0:
+            raise TcError(TC_EINVAL, f"unsupported n={n}, dim={self.dim}, leaf_cap={self.leaf_cap}")
+        if need > self._ws_bytes:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.stream.device)
+            self._ws_bytes = need
+            _check(lib().tc_set_workspace(self._h, _ptr(self._ws), need))
+
+    def _dtype_code(self, t: torch.Tensor) -> int:
+        if t.dtype == torch.float32:
+            return TC_F32
+        if t.dtype == torch.float64:
+            return TC_F64
+        raise TypeError(f"positions must be float32 or float64, got {t.dtype}")
+
+    @staticmethod
+    def _dev(t, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA tensor")
+
+    # -- the calls -----------------------------------------------------------
+    def build(self, pos: torch.Tensor, mass: torch.Tensor):
+        self._dev(pos, "pos")
+        self._dev(mass, "mass")
+        if pos.dim() != 2 or pos.shape[1] != self.dim or mass.shape != (pos.shape[0],):
+            raise ValueError("pos must be [n][dim] and mass [n]")
+        if mass.dtype != pos.dtype:
+            raise TypeError("pos and mass must share a dtype")
+        n = pos.shape[0]
+        self._ensure_ws(n)
+        self._keep = (pos, mass)      # the library keeps the mass pointer
+        self.dtype = pos.dtype
+        _check(lib().tc_build(self._h, _ptr(pos), _ptr(mass), n, self.dim, self.leaf_cap,
+                              self._dtype_code(pos)))
+        self.n = n
+
+    def moments(self):
+        _check(lib().tc_moments(self._h))
+
+    def walk(self, theta: float):
+        _check(lib().tc_walk(self._h, float(theta)))
+
+    def forces(self, G: float = 1.0, eps: float = 1e-2, acc=None, pot=None, want_pot=True):
+        if acc is None:
+            acc = torch.empty((self.n, self.dim), dtype=torch.float32, device=self.stream.device)
+        if pot is None and want_pot:
+            pot = torch.empty(self.n, dtype=torch.float32, device=self.stream.device)
+        for t, nm in ((acc, "acc"), (pot, "pot")):
+            if t is not None:
+                self._dev(t, nm)
+                if t.dtype != torch.float32:
+                    raise TypeError(f"{nm} must be float32")
+        _check(lib().tc_forces(self._h, float(G), float(eps), _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def leapfrog(self, dt: float, pos: torch.Tensor, vel: torch.Tensor):
+        self._dev(pos, "pos")
+        self._dev(vel, "vel")
+        if pos.dtype != self.dtype or vel.dtype != self.dtype or pos.shape != vel.shape:
+            raise TypeError("pos and vel must match the build dtype and shape")
+        self._keep = (pos, self._keep[1])
+        _check(lib().tc_leapfrog(self._h, float(dt), _ptr(pos), _ptr(vel)))
+
+    def diag(self, vel: torch.Tensor) -> np.ndarray:
+        self._dev(vel, "vel")
+        out = np.zeros(8)
+        _check(lib().tc_diag(self._h, _ptr(vel), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def status(self) -> int:
+        return int(lib().tc_status(self._h))
+
+    # -- inspection ----------------------------------------------------------
+    def num_cells(self) -> int:
+        c = C.c_int64()
+        _check(lib().tc_num_cells(self._h, C.byref(c)))
+        return int(c.value)
+
+    def root(self):
+        lo = np.zeros(self.dim)
+        size = np.zeros(1)
+        _check(lib().tc_get_root(self._h, lo.ctypes.data_as(C.c_void_p), size.ctypes.data_as(C.c_void_p)))
+        return lo, float(size[0])
+
+    def keys(self):
+        dev = self.stream.device
+        k = torch.empty(self.n, dtype=torch.int64, device=dev)
+        p = torch.empty(self.n, dtype=torch.int32, device=dev)
+        _check(lib().tc_get_keys(self._h, _ptr(k), _ptr(p)))
+        return k, p
+
+    def cells(self, moments: bool = True) -> dict:
+        Cn = self.num_cells()
+        dev = self.stream.device
+        i32 = lambda: torch.empty(Cn, dtype=torch.int32, device=dev)
+        out = {"level": i32(), "prefix": torch.empty(Cn, dtype=torch.int64, device=dev),
+               "begin": i32(), "count": i32(), "parent": i32(), "skip": i32(), "nch": i32(),
+               "leaf": i32()}
+        if moments:
+            out["M"] = torch.empty(Cn, dtype=torch.float64, device=dev)
+            out["com"] = torch.empty((Cn, self.dim), dtype=torch.float64, device=dev)
+            out["Q"] = torch.empty((Cn, 6), dtype=torch.float64, device=dev)
+        o = out
+        _check(lib().tc_get_cells(self._h, _ptr(o["level"]), _ptr(o["prefix"]), _ptr(o["begin"]),
+                                  _ptr(o["count"]), _ptr(o["parent"]), _ptr(o["skip"]),
+                                  _ptr(o["nch"]), _ptr(o["leaf"]), _ptr(o.get("M")),
+                                  _ptr(o.get("com")), _ptr(o.get("Q"))))
+        return out
+
+    def counts(self):
+        G = (self.n + GROUP - 1) // GROUP
+        dev = self.stream.device
+        m2p = torch.empty(G, dtype=torch.int64, device=dev)
+        p2p = torch.empty(G, dtype=torch.int64, device=dev)
+        _check(lib().tc_get_counts(self._h, _ptr(m2p), _ptr(p2p)))
+        return m2p, p2p
+
+    def interactions(self) -> int:
+        """Body-entry interactions of the last force evaluation (self
+        included): sum over groups of list length x bodies in the group."""
+        m2p, p2p = self.counts()
+        per = (m2p + p2p).cpu().numpy()
+        sizes = np.full(len(per), GROUP, np.int64)
+        sizes[-1] = self.n - GROUP * (len(per) - 1)
+        return int((per * sizes).sum())
+
+    def set_timing(self, on: bool):
+        _check(lib().tc_set_timing(self._h, int(bool(on))))
+
+    def timing(self):
+        ms, k = C.c_double(), C.c_int64()
+        _check(lib().tc_get_timing(self._h, C.byref(ms), C.byref(k)))
+        return float(ms.value), int(k.value)

@@ -1,0 +1,85 @@
+"""The C-ABI library loads, exports every function include/tc.h declares,
+and rejects bad arguments and call orders on the host, before any launch
+(so these run without a GPU)."""
+import ctypes as C
+
+import pytest
+
+from paper_1211_2293_amd import treecode as T
+
+
+@pytest.fixture(scope="module")
+def L():
+    return T.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = T.header_functions()
+    assert len(names) >= 19
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_workspace_bytes(L):
+    assert L.tc_workspace_bytes(0, 3, 8) == 0
+    assert L.tc_workspace_bytes(100, 4, 8) == 0
+    assert L.tc_workspace_bytes(100, 3, 0) == 0
+    assert L.tc_workspace_bytes(100, 3, 257) == 0
+    a = L.tc_workspace_bytes(1000, 3, 8)
+    b = L.tc_workspace_bytes(2000, 3, 8)
+    assert 0 < a < b
+    # 2D trees may be deeper (31 levels), so their bound is larger per body
+    assert L.tc_workspace_bytes(1000, 2, 8) > 0
+
+
+def _ctx(L, dim=3):
+    h = C.c_void_p()
+    assert L.tc_create(C.byref(h), dim, None) == T.TC_OK
+    return h
+
+
+def test_create_rejects_bad_dim(L):
+    h = C.c_void_p()
+    assert L.tc_create(C.byref(h), 4, None) == T.TC_EINVAL
+    assert L.tc_create(None, 3, None) == T.TC_EINVAL
+
+
+def test_call_order_and_arguments(L):
+    h = _ctx(L)
+    fake = C.c_void_p(1 << 40)            # never dereferenced: every call below fails its checks
+    # nothing built yet
+    assert L.tc_moments(h) == T.TC_ESTATE
+    assert L.tc_walk(h, 0.5) == T.TC_ESTATE
+    assert L.tc_forces(h, 1.0, 1e-2, None, None) == T.TC_ESTATE
+    assert L.tc_leapfrog(h, 1e-3, fake, fake) == T.TC_ESTATE
+    out = (C.c_double * 8)()
+    assert L.tc_diag(h, fake, out) == T.TC_ESTATE
+    n = C.c_int64()
+    assert L.tc_num_cells(h, C.byref(n)) == T.TC_ESTATE
+    # argument checks come first
+    assert L.tc_walk(h, -0.1) == T.TC_EINVAL
+    assert L.tc_walk(h, float("nan")) == T.TC_EINVAL
+    assert L.tc_walk(h, 1.5) == T.TC_EINVAL
+    assert L.tc_forces(h, 1.0, 0.0, None, None) == T.TC_EINVAL
+    assert L.tc_forces(h, 1.0, float("inf"), None, None) == T.TC_EINVAL
+    assert L.tc_forces(h, float("nan"), 1e-2, None, None) == T.TC_EINVAL
+    assert L.tc_leapfrog(h, float("nan"), fake, fake) == T.TC_EINVAL
+    # workspace: none set, misaligned, too small
+    assert L.tc_build(h, fake, fake, 100, 3, 8, T.TC_F32) == T.TC_EWORKSPACE
+    assert L.tc_set_workspace(h, C.c_void_p((1 << 40) + 4), 1 << 20) == T.TC_EINVAL
+    assert L.tc_set_workspace(h, fake, 1024) == T.TC_OK
+    assert L.tc_build(h, fake, fake, 100, 3, 8, T.TC_F32) == T.TC_EWORKSPACE
+    # bad sizes, dims, dtypes, pointers
+    assert L.tc_build(h, fake, fake, 0, 3, 8, T.TC_F32) == T.TC_EINVAL
+    assert L.tc_build(h, fake, fake, 100, 2, 8, T.TC_F32) == T.TC_EINVAL   # context is 3D
+    assert L.tc_build(h, fake, fake, 100, 3, 0, T.TC_F32) == T.TC_EINVAL
+    assert L.tc_build(h, fake, fake, 100, 3, 8, 7) == T.TC_EINVAL
+    assert L.tc_build(h, None, fake, 100, 3, 8, T.TC_F32) == T.TC_EINVAL
+    assert L.tc_build(h, C.c_void_p((1 << 40) + 4), fake, 100, 3, 8, T.TC_F64) == T.TC_EINVAL
+    L.tc_destroy(h)
+    L.tc_destroy(None)
+
+
+def test_strerror(L):
+    for code in (T.TC_OK, T.TC_EINVAL, T.TC_EWORKSPACE, T.TC_ESTATE, T.TC_EHIP, T.TC_ENONFINITE, 99):
+        assert isinstance(L.tc_strerror(code), bytes) and L.tc_strerror(code)

@@ -1,0 +1,110 @@
+"""GPU walk + force summation vs the oracle at the same theta and grouping:
+interaction counts identical, accelerations and potentials within 1e-5
+relative L2; theta = 0 reproduces the FP64 direct sum; results are
+bit-reproducible run to run (§3.1 force law and walk)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1211_2293_amd import workloads
+from tests.gpu_util import gpu_tree
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _check_against_oracle(pos, mass, lc, theta, eps, G=1.0):
+    g = gpu_tree(pos, mass, lc, theta=theta, G=G, eps=eps)
+    assert g["status"] == 0
+    t = oracle.Tree(pos.astype(np.float64), np.asarray(mass, np.float64), lc)
+    m2p, p2p = t.walk_counts(theta, 64)
+    np.testing.assert_array_equal(g["m2p"], m2p)
+    np.testing.assert_array_equal(g["p2p"], p2p)
+    a, p = t.forces(theta, G=G, eps=eps)
+    ea, ep = oracle.rel_l2(g["acc"], a), oracle.rel_l2(g["pot"], p)
+    print(f"n={len(pos)} theta={theta}: acc {ea:.2e} pot {ep:.2e} "
+          f"interactions/body {((m2p + p2p) * 64).sum() / len(pos):.0f}", flush=True)
+    assert ea < TOL and ep < TOL
+    return g, t
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.8, 1.0])
+def test_uniform_cube_fp64_state(theta):
+    w = workloads.uniform_cube(4096)
+    _check_against_oracle(w.pos, w.mass, w.leaf_cap, theta, w.eps)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7, 0.9])
+def test_plummer(theta):
+    w = workloads.plummer_sphere(30000, seed=60)
+    _check_against_oracle(w.pos, w.mass, 16, theta, 1e-2)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.8])
+def test_disk_2d(theta):
+    w = workloads.gaussian_disk(10000, seed=61)
+    _check_against_oracle(w.pos, w.mass, 16, theta, 1e-2)
+
+
+def test_clustered_pareto_masses():
+    w = workloads.clustered(40000, seed=62)
+    _check_against_oracle(w.pos, w.mass, 16, 0.7, 1e-3)
+
+
+def test_ragged_and_tiny_sizes():
+    rng = np.random.default_rng(63)
+    for n in (1, 2, 63, 64, 65, 130, 1000):
+        pos = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+        mass = rng.uniform(0.5, 1.5, n).astype(np.float32)
+        g = gpu_tree(pos, mass, 8, theta=0.6, eps=1e-2)
+        a, p = oracle.direct(pos, mass, eps=1e-2) if n <= 2 else oracle.Tree(pos, mass, 8).forces(0.6, eps=1e-2)
+        if n == 1:
+            assert np.all(g["acc"] == 0) and np.all(g["pot"] == 0)
+            continue
+        assert oracle.rel_l2(g["acc"], a) < TOL and oracle.rel_l2(g["pot"], p) < TOL
+
+
+def test_theta_zero_is_direct_sum():
+    w = workloads.plummer_sphere(12000, seed=64)
+    g = gpu_tree(w.pos, w.mass, 16, theta=0.0, eps=1e-2)
+    a, p = oracle.direct(w.pos, w.mass, eps=1e-2)
+    assert oracle.rel_l2(g["acc"], a) < TOL
+    assert oracle.rel_l2(g["pot"], p) < TOL
+    # every group's list is all n bodies
+    assert np.all(g["m2p"] == 0) and np.all(g["p2p"] == len(w.pos))
+
+
+def test_coincident_bodies_and_oversized_leaf():
+    # 2000 identical keys: one level-L leaf larger than the LDS list
+    n = 2000
+    pos = np.full((n, 3), 0.25, np.float32)
+    pos[:10] += np.linspace(0.1, 0.5, 10)[:, None].astype(np.float32)
+    mass = np.ones(n, np.float32) / n
+    g = gpu_tree(pos, mass, 8, theta=0.5, eps=1e-3)
+    a, p = oracle.Tree(pos, mass, 8).forces(0.5, eps=1e-3)
+    assert np.abs(g["acc"] - a).max() <= 1e-5 * np.abs(a).max()
+    assert oracle.rel_l2(g["pot"], p) < TOL
+
+
+def test_bodies_on_cell_faces():
+    rng = np.random.default_rng(65)
+    pos = (rng.integers(0, 17, (3000, 3)) / 16.0).astype(np.float32)
+    pos = np.unique(pos, axis=0)
+    mass = np.ones(len(pos), np.float32)
+    _check_against_oracle(pos, mass, 4, 0.5, 1e-2)
+
+
+def test_deterministic():
+    w = workloads.plummer_sphere(50000, seed=66)
+    g1 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2)
+    g2 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2)
+    np.testing.assert_array_equal(g1["acc"], g2["acc"])
+    np.testing.assert_array_equal(g1["pot"], g2["pot"])
+
+
+def test_G_scales_linearly():
+    w = workloads.plummer_sphere(5000, seed=67)
+    g1 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2, G=1.0)
+    g2 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2, G=2.5)
+    np.testing.assert_allclose(g2["acc"], 2.5 * g1["acc"], rtol=1e-6, atol=0)

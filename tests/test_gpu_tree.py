@@ -1,0 +1,74 @@
+"""GPU tree construction vs the oracle, bit for bit: root cube, Morton keys,
+stable sort order, cell topology in pre-order, FP64 moments (§3.1)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1211_2293_amd import workloads
+from tests.gpu_util import assert_tree_equal, gpu_tree
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid_faces(n=512):
+    # bodies exactly on subdivision planes (dyadic coordinates)
+    rng = np.random.default_rng(40)
+    return (rng.integers(0, 9, (n, 3)) / 8.0).astype(np.float32)
+
+
+def _two_clumps(n=3000):
+    rng = np.random.default_rng(41)
+    a = rng.normal(0.2, 1e-4, (n // 2, 3))
+    b = rng.normal(0.8, 1e-5, (n - n // 2, 3))
+    return np.concatenate([a, b]).astype(np.float32)
+
+
+CASES = {
+    "uniform-cube-4096-f64": lambda: (workloads.uniform_cube(4096).pos, np.full(4096, 1 / 4096), 8),
+    "uniform-5000-f32": lambda: (np.random.default_rng(42).uniform(-1, 3, (5000, 3)).astype(np.float32),
+                                 np.random.default_rng(43).uniform(0.5, 2, 5000).astype(np.float32), 16),
+    "plummer-20000": lambda: (workloads.plummer_sphere(20000, seed=44).pos,
+                              workloads.plummer_sphere(20000, seed=44).mass, 16),
+    "disk2d-9000": lambda: (workloads.gaussian_disk(9000, seed=45).pos,
+                            workloads.gaussian_disk(9000, seed=45).mass, 16),
+    "disk2d-lc1": lambda: (workloads.gaussian_disk(700, seed=46).pos,
+                           workloads.gaussian_disk(700, seed=46).mass, 1),
+    "clustered-20000": lambda: (workloads.clustered(20000, seed=47).pos,
+                                workloads.clustered(20000, seed=47).mass, 16),
+    "faces-512": lambda: (_grid_faces(), np.ones(512, np.float32), 4),
+    "two-clumps": lambda: (_two_clumps(), np.ones(3000, np.float32), 8),
+    "coincident-100": lambda: (np.full((100, 3), 0.5, np.float32), np.ones(100, np.float32), 8),
+    "one-body": lambda: (np.array([[0.1, 0.2, 0.3]], np.float32), np.ones(1, np.float32), 8),
+    "leafcap-plus-one": lambda: (np.random.default_rng(48).uniform(0, 1, (17, 3)).astype(np.float32),
+                                 np.ones(17, np.float32), 16),
+    "leafcap-256": lambda: (np.random.default_rng(49).uniform(0, 1, (3000, 3)).astype(np.float32),
+                            np.ones(3000, np.float32), 256),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_tree_bit_exact(name):
+    pos, mass, lc = CASES[name]()
+    print(f"case {name} n={len(pos)} leaf_cap={lc}", flush=True)
+    g = gpu_tree(pos, mass, lc)
+    assert g["status"] == 0
+    t = oracle.Tree(pos.astype(np.float64), np.asarray(mass, np.float64), lc)
+    assert_tree_equal(g, t)
+
+
+def test_nonfinite_is_sticky_until_next_build():
+    from paper_1211_2293_amd import treecode
+    pos = np.random.default_rng(50).uniform(0, 1, (1000, 3)).astype(np.float32)
+    mass = np.ones(1000, np.float32)
+    bad = pos.copy()
+    bad[17, 1] = np.nan
+    g = gpu_tree(bad, mass, 8, theta=0.5, eps=1e-2)
+    assert g["status"] == treecode.TC_ENONFINITE
+    tc = g["tc"]
+    import torch
+    tc.build(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+    assert tc.status() == treecode.TC_OK
+    m = mass.copy()
+    m[3] = -1.0
+    g2 = gpu_tree(pos, m, 8)
+    assert g2["status"] == treecode.TC_ENONFINITE
