@@ -90,8 +90,8 @@ int tc_moments(tc_ctx *ctx);
 
 /* Fix the opening parameter theta (0 <= theta <= 1) and prepare each cell's
  * opening radius r = s/theta + |com - centre| (s the cell side).  A cell is
- * accepted for a group of 64 Morton-consecutive bodies iff the squared
- * distance from its centre of mass to the group's bounding box exceeds r^2;
+ * accepted for a walk group (see tc_num_groups) iff the squared distance
+ * from its centre of mass to the group's bounding box exceeds r^2;
  * theta = 0 accepts nothing (the direct sum).  Requires tc_moments. */
 int tc_walk(tc_ctx *ctx, double theta);
 
@@ -145,8 +145,19 @@ int tc_get_cells(tc_ctx *ctx, int32_t *level, uint64_t *prefix, int32_t *begin,
                  int32_t *count, int32_t *parent, int32_t *skip, int32_t *nch,
                  int32_t *leaf, double *M, double *com, double *Q);
 
+/* Number of walk groups of the current tree.  A walk group is a run of at
+ * most 64 consecutive bodies in key order lying inside one cluster cell (a
+ * maximal cell of at most 1024 bodies, or a deeper leaf); each cluster cell
+ * is cut into such runs in order.  Synchronises.  Requires tc_build. */
+int tc_num_groups(tc_ctx *ctx, int64_t *ngroups);
+
+/* Copy the groups' first sorted body and size (int32 [ngroups] device
+ * buffers; either may be NULL).  Requires tc_build. */
+int tc_get_groups(tc_ctx *ctx, int32_t *begin, int32_t *count);
+
 /* Per-group interaction counts of the last tc_forces (device int64 arrays
- * of ceil(n/64) entries): accepted cells and bodies of opened leaves. */
+ * of tc_num_groups() entries): accepted cells and bodies of opened leaves
+ * (the group's own bodies included).  Synchronises.  Requires tc_forces. */
 int tc_get_counts(tc_ctx *ctx, int64_t *m2p, int64_t *p2p);
 
 /* Time the force kernel with HIP events on the context's stream: when on,

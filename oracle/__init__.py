@@ -58,6 +58,12 @@ def lib():
         L.orc_walk_items.restype = i64
         L.orc_tree_forces.argtypes = [P, dbl, i32, dbl, dbl, i64, P, P, P]
         L.orc_tree_forces.restype = None
+        L.orc_groups.argtypes = [P, i32, i64, P, P]
+        L.orc_groups.restype = i64
+        L.orc_walk_counts_ranges.argtypes = [P, dbl, i64, P, P, P, P]
+        L.orc_walk_counts_ranges.restype = None
+        L.orc_tree_forces_ranges.argtypes = [P, dbl, dbl, dbl, i64, P, P, P, P]
+        L.orc_tree_forces_ranges.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         _LIB = L
@@ -183,6 +189,46 @@ class Tree:
             if k <= cap:
                 return buf[:k]
             cap = k
+
+    def groups(self, gs=64, cluster=512):
+        """Groups of at most gs consecutive sorted bodies that never straddle
+        a cluster cell (a maximal cell of at most `cluster` bodies, or a
+        deeper leaf): returns (first body, size) arrays."""
+        ng = int(lib().orc_groups(self._h, gs, cluster, None, None))
+        gb = np.zeros(ng, np.int64)
+        gc = np.zeros(ng, np.int64)
+        lib().orc_groups(self._h, gs, cluster, _p(gb), _p(gc))
+        return gb, gc
+
+    def walk_counts_groups(self, theta, gbeg, gcnt):
+        gbeg = np.ascontiguousarray(gbeg, np.int64)
+        gcnt = np.ascontiguousarray(gcnt, np.int64)
+        m2p = np.zeros(len(gbeg), np.int64)
+        p2p = np.zeros(len(gbeg), np.int64)
+        lib().orc_walk_counts_ranges(self._h, float(theta), len(gbeg), _p(gbeg), _p(gcnt),
+                                     _p(m2p), _p(p2p))
+        return m2p, p2p
+
+    def forces_groups(self, theta, gbeg, gcnt, G=1.0, eps=1e-3, acc=None, pot=None):
+        """Treecode forces of the bodies of the given groups, original
+        order; bodies outside them keep the values in acc/pot (zeros by
+        default)."""
+        gbeg = np.ascontiguousarray(gbeg, np.int64)
+        gcnt = np.ascontiguousarray(gcnt, np.int64)
+        if acc is None:
+            acc = np.zeros((self.n, self.dim))
+        if pot is None:
+            pot = np.zeros(self.n)
+        lib().orc_tree_forces_ranges(self._h, float(theta), G, eps, len(gbeg), _p(gbeg), _p(gcnt),
+                                     _p(acc), _p(pot))
+        return acc, pot
+
+    def walk_forces(self, theta, G=1.0, eps=1e-3, gs=64, cluster=1024):
+        """Treecode forces with the walk groups of the GPU path: runs of at
+        most gs consecutive sorted bodies inside cluster cells of at most
+        `cluster` bodies."""
+        gb, gc = self.groups(gs, cluster)
+        return self.forces_groups(theta, gb, gc, G=G, eps=eps)
 
     def forces(self, theta, G=1.0, eps=1e-3, gs=64, groups=None):
         """FP64 treecode accelerations and potentials in original order.

@@ -463,12 +463,40 @@ static void walk_rec(const orc_tree *t, int64_t c, const double *rcrit2, const d
     for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) walk_rec(t, ch, rcrit2, lo, hi, w);
 }
 
-static void walk_group(const orc_tree *t, const double *rcrit2, int gs, int64_t g, walk_out *w)
+static void walk_range(const orc_tree *t, const double *rcrit2, int64_t b, int64_t e, walk_out *w)
 {
-    const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
     double lo[ORC_MAXD], hi[ORC_MAXD];
     group_box(t, b, e, lo, hi);
     walk_rec(t, 0, rcrit2, lo, hi, w);
+}
+
+static void walk_group(const orc_tree *t, const double *rcrit2, int gs, int64_t g, walk_out *w)
+{
+    const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
+    walk_range(t, rcrit2, b, e, w);
+}
+
+/* Groups of at most gs consecutive sorted bodies that never straddle a
+ * cluster cell, a maximal cell holding at most kc bodies: the bodies of each
+ * cluster cell, in order, are cut into runs of gs (the last run shorter).
+ * Writes the groups' first body and size (when the arrays are not NULL) and
+ * returns their number. */
+int64_t orc_groups(const orc_tree *t, int gs, int64_t kc, int64_t *gbeg, int64_t *gcnt)
+{
+    int64_t ng = 0;
+    for (int64_t c = 0; c < t->ncells;) {
+        if (t->count[c] <= kc || t->leaf[c]) {
+            for (int64_t o = 0; o < t->count[c]; o += gs) {
+                if (gbeg) gbeg[ng] = t->begin[c] + o;
+                if (gcnt) gcnt[ng] = (t->count[c] - o < gs) ? t->count[c] - o : gs;
+                ++ng;
+            }
+            c = t->skip[c];
+        } else {
+            c = c + 1;
+        }
+    }
+    return ng;
 }
 
 /* Number of accepted cells (m2p) and of bodies from opened leaves (p2p,
@@ -482,6 +510,23 @@ void orc_walk_counts(const orc_tree *t, double theta, int gs, int64_t *m2p, int6
     for (int64_t g = 0; g < G; ++g) {
         walk_out w = {0};
         walk_group(t, rc, gs, g, &w);
+        m2p[g] = w.m2p;
+        p2p[g] = w.p2p;
+    }
+    free(rc);
+}
+
+/* The same for explicit groups: group k holds sorted bodies
+ * [gbeg[k], gbeg[k] + gcnt[k]). */
+void orc_walk_counts_ranges(const orc_tree *t, double theta, int64_t ng, const int64_t *gbeg,
+                            const int64_t *gcnt, int64_t *m2p, int64_t *p2p)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t g = 0; g < ng; ++g) {
+        walk_out w = {0};
+        walk_range(t, rc, gbeg[g], gbeg[g] + gcnt[g], &w);
         m2p[g] = w.m2p;
         p2p[g] = w.p2p;
     }
@@ -505,53 +550,72 @@ int64_t orc_walk_items(const orc_tree *t, double theta, int gs, int64_t g, int32
     return w.nitems;
 }
 
-/* Treecode forces for the bodies of the selected groups (all groups when
- * groups == NULL): the sum over each body's list of the softened point-mass
- * interaction, cells as pseudo-bodies of mass M at their centre of mass.
- * acc [n][dim] and pot [n] are in original body order; only the bodies of
- * the selected groups are written. */
+/* Forces on the bodies of one group (sorted [b, e)): the sum over the
+ * group's list of the softened point-mass interaction, cells as
+ * pseudo-bodies of mass M at their centre of mass (§3.1). */
+static void group_forces(const orc_tree *t, const double *rc, int64_t b, int64_t e, double G,
+                         double e2, double *acc, double *pot)
+{
+    const int D = t->dim;
+    walk_out w = {0};
+    w.items = malloc(256 * sizeof(int32_t));
+    w.cap = 256;
+    walk_range(t, rc, b, e, &w);
+    for (int64_t i = b; i < e; ++i) {
+        double a[ORC_MAXD] = {0, 0, 0}, p = 0.0;
+        const double *xi = t->x + i * D;
+        for (int64_t k = 0; k < w.nitems; ++k) {
+            const int32_t it = w.items[k];
+            int64_t jb, je;
+            const double *src, *ms;
+            if (it >= 0) { jb = it; je = it + 1; src = t->com; ms = t->M; }
+            else { const int64_t c = -1 - it; jb = t->begin[c]; je = jb + t->count[c]; src = t->x; ms = t->m; }
+            for (int64_t j = jb; j < je; ++j) {
+                if (it < 0 && j == i) continue;
+                double d[ORC_MAXD], r2 = e2;
+                for (int q = 0; q < D; ++q) { d[q] = src[j * D + q] - xi[q]; r2 += d[q] * d[q]; }
+                const double inv = 1.0 / sqrt(r2);
+                const double wv = ms[j] * inv;
+                p -= wv;
+                const double w3 = wv * inv * inv;
+                for (int q = 0; q < D; ++q) a[q] += w3 * d[q];
+            }
+        }
+        const int64_t o = t->perm[i];
+        for (int q = 0; q < D; ++q) acc[o * D + q] = G * a[q];
+        if (pot) pot[o] = G * p;
+    }
+    free(w.items);
+}
+
+/* Treecode forces for the bodies of the selected groups of gs consecutive
+ * sorted bodies (all groups when groups == NULL).  acc [n][dim] and pot [n]
+ * are in original body order; only the selected groups' bodies are
+ * written. */
 void orc_tree_forces(const orc_tree *t, double theta, int gs, double G, double eps,
                      int64_t ngsel, const int64_t *groups, double *acc, double *pot)
 {
-    const int D = t->dim;
-    const double e2 = eps * eps;
     double *rc = malloc(t->ncells * sizeof(double));
     orc_mac_radii(t, theta, rc);
     const int64_t NG = groups ? ngsel : (t->n + gs - 1) / gs;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t s = 0; s < NG; ++s) {
         const int64_t g = groups ? groups[s] : s;
-        walk_out w = {0};
-        w.items = malloc(256 * sizeof(int32_t));
-        w.cap = 256;
-        walk_group(t, rc, gs, g, &w);
         const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
-        for (int64_t i = b; i < e; ++i) {
-            double a[ORC_MAXD] = {0, 0, 0}, p = 0.0;
-            const double *xi = t->x + i * D;
-            for (int64_t k = 0; k < w.nitems; ++k) {
-                const int32_t it = w.items[k];
-                int64_t jb, je;
-                const double *src, *ms;
-                if (it >= 0) { jb = it; je = it + 1; src = t->com; ms = t->M; }
-                else { const int64_t c = -1 - it; jb = t->begin[c]; je = jb + t->count[c]; src = t->x; ms = t->m; }
-                for (int64_t j = jb; j < je; ++j) {
-                    if (it < 0 && j == i) continue;
-                    double d[ORC_MAXD], r2 = e2;
-                    for (int q = 0; q < D; ++q) { d[q] = src[j * D + q] - xi[q]; r2 += d[q] * d[q]; }
-                    const double inv = 1.0 / sqrt(r2);
-                    const double wv = ms[j] * inv;
-                    p -= wv;
-                    const double w3 = wv * inv * inv;
-                    for (int q = 0; q < D; ++q) a[q] += w3 * d[q];
-                }
-            }
-            const int64_t o = t->perm[i];
-            for (int q = 0; q < D; ++q) acc[o * D + q] = G * a[q];
-            if (pot) pot[o] = G * p;
-        }
-        free(w.items);
+        group_forces(t, rc, b, e, G, eps * eps, acc, pot);
     }
+    free(rc);
+}
+
+/* The same for explicit groups [gbeg[k], gbeg[k] + gcnt[k]), k < ng. */
+void orc_tree_forces_ranges(const orc_tree *t, double theta, double G, double eps, int64_t ng,
+                            const int64_t *gbeg, const int64_t *gcnt, double *acc, double *pot)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < ng; ++k)
+        group_forces(t, rc, gbeg[k], gbeg[k] + gcnt[k], G, eps * eps, acc, pot);
     free(rc);
 }
 

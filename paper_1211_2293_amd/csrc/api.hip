@@ -60,11 +60,32 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_arrive = take(4 * (size_t)l.cmax);
     l.off_acc = take(4 * (size_t)n * dim);
     l.off_pot = take(4 * (size_t)n);
-    l.off_m2p = take(8 * (size_t)l.groups);
-    l.off_p2p = take(8 * (size_t)l.groups);
+    l.off_m2p = 0;   // placed after the group bound is known
+    l.off_p2p = 0;
     l.off_bbox_part = take(7 * 8 * 1024);
     l.off_diag_part = take(8 * 8 * (size_t)kDiagBlocks);
     l.off_diag_out = take(8 * 8);
+    l.lvl_tiles = (l.cmax + kSortTile - 1) / kSortTile;
+    l.off_lvl_keys_a = take(8 * (size_t)l.cmax);
+    l.off_lvl_keys_b = take(8 * (size_t)l.cmax);
+    l.off_lvl_idx_a = take(4 * (size_t)l.cmax);
+    l.off_lvl_idx_b = take(4 * (size_t)l.cmax);
+    l.off_pre2bfs = take(4 * (size_t)l.cmax);
+    l.off_lvl_hist = take(4 * 256 * (size_t)l.lvl_tiles);
+    // walk groups: at most ceil(n/64) + (number of cluster cells); a cluster
+    // cell's parent holds > kCluster bodies, and such parents are disjoint
+    // within a level
+    const int64_t clusters = (int64_t)(1 << dim) * levels_for(dim) * (n / (kCluster + 1)) + 1;
+    l.gmax = (n + kGroup - 1) / kGroup + (clusters < n ? clusters : n);
+    l.cscan_tiles = (l.cmax + kScanTile - 1) / kScanTile;
+    l.off_gper = take(4 * (size_t)l.cmax);
+    l.off_goff = take(4 * (size_t)(l.cmax + 1));
+    l.off_gscan_part = take(4 * (size_t)l.cscan_tiles);
+    l.off_gbeg = take(4 * (size_t)l.gmax);
+    l.off_gcnt = take(4 * (size_t)l.gmax);
+    l.off_queue = take(4 * 2 * kXcd);
+    l.off_m2p = take(8 * (size_t)l.gmax);
+    l.off_p2p = take(8 * (size_t)l.gmax);
     l.total = off;
     return l;
 }
@@ -116,7 +137,7 @@ bool valid_sizes(int64_t n, int dim, int leaf_cap) {
     if (dim != 2 && dim != 3) return false;
     if (leaf_cap < 1 || leaf_cap > TC_MAX_LEAF_CAP) return false;
     const int64_t cmax = (int64_t)levels_for(dim) * (n / (leaf_cap + 1)) + n + 1;
-    return cmax < ((int64_t)1 << 31);
+    return cmax < ((int64_t)1 << 29);   // level-order indices are packed into 29 bits
 }
 
 hipEvent_t pooled_event(tc_ctx* ctx) {
@@ -152,6 +173,15 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
                                 ctx->at<uint32_t>(l.off_cstart), ctx->at<uint32_t>(l.off_scan_part),
                                 l.scan_tiles, ctx->at<Cell>(l.off_cells), ctx->at<uint32_t>(l.off_arrive),
                                 l.cmax, prm, s));
+    TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
+                                   ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
+                                   ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
+                                   ctx->at<uint32_t>(l.off_digit_tot), l.lvl_tiles,
+                                   ctx->at<uint32_t>(l.off_pre2bfs), s));
+    TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
+                              ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
+                              l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
+                              l.gmax, prm, s));
     ctx->mass = mass;
     ctx->n = n;
     ctx->leaf_cap = leaf_cap;
@@ -163,7 +193,8 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
 int do_moments(tc_ctx* ctx) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
-                               ctx->at<Moments>(l.off_mom), ctx->at<WalkCell>(l.off_walk),
+                               ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<Moments>(l.off_mom),
+                               ctx->at<WalkCell>(l.off_walk),
                                ctx->at<uint32_t>(l.off_arrive), ctx->prm(), ctx->stream));
     ctx->state = kMoments;
     return TC_OK;
@@ -172,7 +203,8 @@ int do_moments(tc_ctx* ctx) {
 int do_walk(tc_ctx* ctx, double theta) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta, l.cmax,
-                           ctx->at<WalkCell>(l.off_walk), ctx->prm(), ctx->stream));
+                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), ctx->prm(),
+                           ctx->stream));
     ctx->theta = theta;
     ctx->state = kWalked;
     return TC_OK;
@@ -188,8 +220,10 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, hipEventRecord(e0, ctx->stream));
     }
     TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
-                                  ctx->at<uint32_t>(l.off_idx_a), ctx->n, ctx->dim, (float)G,
-                                  (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
+                                  ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
+                                  ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
+                                  ctx->n, ctx->dim, ctx->leaf_cap,
+                                  (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
                                   ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
                                   ctx->at<int64_t>(l.off_p2p), ctx->stream));
     if (ctx->timing) {
@@ -382,15 +416,44 @@ int tc_get_cells(tc_ctx* ctx, int32_t* level, uint64_t* prefix, int32_t* begin, 
     return TC_OK;
 }
 
+int tc_num_groups(tc_ctx* ctx, int64_t* ngroups) {
+    if (!ctx || !ngroups) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    DevParams p;
+    TC_HIP(ctx, hipMemcpyAsync(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost, ctx->stream));
+    TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *ngroups = p.ngroups < ctx->lay.gmax ? p.ngroups : ctx->lay.gmax;
+    return TC_OK;
+}
+
+int tc_get_groups(tc_ctx* ctx, int32_t* begin, int32_t* count) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    int64_t ng = 0;
+    int rc = tc_num_groups(ctx, &ng);
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    if (begin)
+        TC_HIP(ctx, hipMemcpyAsync(begin, ctx->at<int32_t>(l.off_gbeg), 4 * (size_t)ng,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (count)
+        TC_HIP(ctx, hipMemcpyAsync(count, ctx->at<int32_t>(l.off_gcnt), 4 * (size_t)ng,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
+}
+
 int tc_get_counts(tc_ctx* ctx, int64_t* m2p, int64_t* p2p) {
     if (!ctx) return TC_EINVAL;
     if (ctx->state < kForced) return TC_ESTATE;
+    int64_t ng = 0;
+    int rc = tc_num_groups(ctx, &ng);
+    if (rc != TC_OK) return rc;
     const Layout& l = ctx->lay;
     if (m2p)
-        TC_HIP(ctx, hipMemcpyAsync(m2p, ctx->at<int64_t>(l.off_m2p), 8 * (size_t)l.groups,
+        TC_HIP(ctx, hipMemcpyAsync(m2p, ctx->at<int64_t>(l.off_m2p), 8 * (size_t)ng,
                                    hipMemcpyDeviceToDevice, ctx->stream));
     if (p2p)
-        TC_HIP(ctx, hipMemcpyAsync(p2p, ctx->at<int64_t>(l.off_p2p), 8 * (size_t)l.groups,
+        TC_HIP(ctx, hipMemcpyAsync(p2p, ctx->at<int64_t>(l.off_p2p), 8 * (size_t)ng,
                                    hipMemcpyDeviceToDevice, ctx->stream));
     return TC_OK;
 }

@@ -532,23 +532,30 @@ __device__ void internal_moments(int64_t p, const Cell* __restrict__ cells, cons
     mo.pad = 0.0;
 }
 
-__device__ __forceinline__ void store_walk(WalkCell* walk, int64_t k, const Cell& c, const Moments& mo) {
+__device__ __forceinline__ void store_walk(WalkCell* walk, const uint32_t* __restrict__ pre2bfs, int64_t k,
+                                           const Cell& c, const Moments& mo) {
     WalkCell w;
     w.cx = mo.com[0];
     w.cy = mo.com[1];
     w.cz = mo.com[2];
     w.rcrit2 = INFINITY;
     w.m = (float)mo.M;
-    w.skip = c.skip;
-    w.begin = c.begin;
-    w.cnt_leaf = (c.count & 0x7fffffff) | (c.leaf_nch < 0 ? (int32_t)0x80000000u : 0);
-    walk[k] = w;
+    if (c.leaf_nch < 0) {
+        w.a = c.begin;
+        w.b = (c.count & 0x7fffffff) | (int32_t)0x80000000u;
+    } else {
+        w.a = (int32_t)pre2bfs[k + 1];           // first child, pre-order k + 1
+        w.b = c.leaf_nch;
+    }
+    w.pad = 0;
+    walk[pre2bfs[k]] = w;
 }
 
 // One thread per leaf; the last child to arrive at a parent computes it
 // (children in digit order), so results do not depend on arrival order.
 template <int D>
 __global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
+                                                 const uint32_t* __restrict__ pre2bfs,
                                                  Moments* mom, WalkCell* __restrict__ walk,
                                                  uint32_t* arrive, const DevParams* __restrict__ prm,
                                                  int64_t cmax) {
@@ -561,7 +568,7 @@ __global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells,
         Moments mo;
         leaf_moments<D>(c, bodies, mo);
         mom[k] = mo;
-        store_walk(walk, k, c, mo);
+        store_walk(walk, pre2bfs, k, c, mo);
         int64_t cur = k;
         while (true) {
             const int64_t p = cells[cur].parent;
@@ -575,7 +582,7 @@ __global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells,
             Moments mp;
             internal_moments<D>(p, cells, mom, mp);
             mom[p] = mp;
-            store_walk(walk, p, cp, mp);
+            store_walk(walk, pre2bfs, p, cp, mp);
             cur = p;
         }
     }
@@ -585,7 +592,8 @@ __global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells,
 
 template <int D>
 __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
-                                             double theta, WalkCell* __restrict__ walk,
+                                             double theta, const uint32_t* __restrict__ pre2bfs,
+                                             WalkCell* __restrict__ walk,
                                              const DevParams* __restrict__ prm, int64_t cmax) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
@@ -593,7 +601,7 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
          k += (int64_t)gridDim.x * blockDim.x) {
         if (theta == 0.0) {
-            walk[k].rcrit2 = INFINITY;
+            walk[pre2bfs[k]].rcrit2 = INFINITY;
             continue;
         }
         const Cell c = cells[k];
@@ -614,7 +622,83 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
         double d2 = dd[0] * dd[0] + dd[1] * dd[1];
         if (D == 3) d2 = d2 + dd[2] * dd[2];
         const double r = s / theta + sqrt(d2);
-        walk[k].rcrit2 = r * r;
+        walk[pre2bfs[k]].rcrit2 = r * r;
+    }
+}
+
+// --------------------------------------------------------- level order ----
+// Level order of the cells: a stable sort of (level, pre-order index), one
+// 8-bit radix pass over all cmax slots (unused slots sort last).  Within a
+// level, pre-order keeps children of one parent adjacent.
+
+__global__ void __launch_bounds__(256) k_level_keys(const Cell* __restrict__ cells, const DevParams* __restrict__ prm,
+                                                    int64_t cmax, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ idx) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cmax;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        keys[k] = k < C ? (uint64_t)cells[k].level : 255ull;
+        idx[k] = (uint32_t)k;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_level_inverse(const uint32_t* __restrict__ bfs2pre,
+                                                       const DevParams* __restrict__ prm, int64_t cmax,
+                                                       uint32_t* __restrict__ pre2bfs) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < C;
+         b += (int64_t)gridDim.x * blockDim.x)
+        pre2bfs[bfs2pre[b]] = (uint32_t)b;
+}
+
+// ---------------------------------------------------------- walk groups ----
+// A walk group is a run of at most 64 consecutive bodies in key order that
+// never straddles a cluster cell (a maximal cell holding at most kCluster
+// bodies, or a leaf deeper than that): the group's bounding box then stays
+// inside one compact region even where the Morton curve jumps across empty
+// space.  Cluster cells are found in pre-order, so groups come out in body
+// order.
+
+__device__ __forceinline__ bool small_cell(const Cell& c) { return c.count <= kCluster || c.leaf_nch < 0; }
+
+__global__ void __launch_bounds__(256) k_group_count(const Cell* __restrict__ cells, const DevParams* __restrict__ prm,
+                                                     int64_t cmax, uint32_t* __restrict__ gper) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cmax;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+        if (k < C) {
+            const Cell c = cells[k];
+            const bool cluster = small_cell(c) && (k == 0 || !small_cell(cells[c.parent]));
+            if (cluster) v = (uint32_t)((c.count + kGroup - 1) / kGroup);
+        }
+        gper[k] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_group_emit(const Cell* __restrict__ cells, const uint32_t* __restrict__ goff,
+                                                    DevParams* prm, int64_t cmax, int32_t* __restrict__ gbeg,
+                                                    int32_t* __restrict__ gcnt, int64_t gmax) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t G = goff[cmax];
+        prm->ngroups = (int64_t)G > gmax ? (uint32_t)gmax : G;
+        if ((int64_t)G > gmax) atomicOr(&prm->status, kFlagOverflow);
+    }
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t g0 = goff[k], g1 = goff[k + 1];
+        if (g1 == g0) continue;
+        const Cell c = cells[k];
+        for (uint32_t g = g0; g < g1 && (int64_t)g < gmax; ++g) {
+            const int32_t o = (int32_t)(g - g0) * kGroup;
+            gbeg[g] = c.begin + o;
+            gcnt[g] = min(kGroup, c.count - o);
+        }
     }
 }
 
@@ -727,20 +811,50 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
-                          Moments* mom, WalkCell* walk, uint32_t* arrive, const DevParams* prm,
-                          hipStream_t s) {
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, const DevParams* prm, uint64_t* keys_a,
+                              uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
+                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_keys, dim3(grid_for(cmax)), dim3(256), 0, s, cells, prm, cmax, keys_a, idx_a);
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)tiles), dim3(256), 0, s, (const uint64_t*)keys_a, cmax, 0,
+                       hist, tiles);
+    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)tiles), dim3(256), 0, s, (const uint64_t*)keys_a,
+                       (const uint32_t*)idx_a, keys_b, idx_b, cmax, 0, (const uint32_t*)hist,
+                       (const uint32_t*)digit_tot, tiles);
+    hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
+                       pre2bfs);
+    return hipGetLastError();
+}
+
+hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
+                         int64_t scan_tiles, int32_t* gbeg, int32_t* gcnt, int64_t gmax, DevParams* prm,
+                         hipStream_t s) {
     const unsigned nb = grid_for(cmax);
-    if (dim == 3) hipLaunchKernelGGL(k_moments<3>, dim3(nb), dim3(256), 0, s, cells, bodies, mom, walk, arrive, prm, cmax);
-    else hipLaunchKernelGGL(k_moments<2>, dim3(nb), dim3(256), 0, s, cells, bodies, mom, walk, arrive, prm, cmax);
+    hipLaunchKernelGGL(k_group_count, dim3(nb), dim3(256), 0, s, cells, (const DevParams*)prm, cmax, gper);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax,
+                       scan_part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, goff, cmax);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax,
+                       (const uint32_t*)scan_part, goff);
+    hipLaunchKernelGGL(k_group_emit, dim3(nb), dim3(256), 0, s, cells, (const uint32_t*)goff, prm, cmax, gbeg,
+                       gcnt, gmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
+                          const uint32_t* pre2bfs, Moments* mom, WalkCell* walk, uint32_t* arrive,
+                          const DevParams* prm, hipStream_t s) {
+    const unsigned nb = grid_for(cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_moments<3>, dim3(nb), dim3(256), 0, s, cells, bodies, pre2bfs, mom, walk, arrive, prm, cmax);
+    else hipLaunchKernelGGL(k_moments<2>, dim3(nb), dim3(256), 0, s, cells, bodies, pre2bfs, mom, walk, arrive, prm, cmax);
     return hipGetLastError();
 }
 
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
-                      WalkCell* walk, const DevParams* prm, hipStream_t s) {
+                      const uint32_t* pre2bfs, WalkCell* walk, const DevParams* prm, hipStream_t s) {
     const unsigned nb = grid_for(cmax);
-    if (dim == 3) hipLaunchKernelGGL(k_mac<3>, dim3(nb), dim3(256), 0, s, cells, mom, theta, walk, prm, cmax);
-    else hipLaunchKernelGGL(k_mac<2>, dim3(nb), dim3(256), 0, s, cells, mom, theta, walk, prm, cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_mac<3>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, prm, cmax);
+    else hipLaunchKernelGGL(k_mac<2>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, prm, cmax);
     return hipGetLastError();
 }
 

@@ -4,19 +4,23 @@
 // per-body sums are independent of each other).
 //
 // One wavefront per group of 64 consecutive bodies in key order, one lane
-// per body.  The walk is stackless: cells are in depth-first pre-order, so
-// the traversal state is a single cursor that only moves forward (to c+1
-// when a cell is opened, to skip[c] when it is accepted or is a leaf).  Each
-// step the wave evaluates the opening test for the 64 cells
-// [cursor, cursor+64) at once, one per lane, in FP64; the visited chain
-// inside that window is then followed with scalar bit operations (only the
-// terminal cells, accepted or leaf, need a jump), and their entries are
-// appended to a per-wave list in LDS.  When the list is full it is flushed:
-// every lane sums the whole list for its own body in FP32, reading each entry
-// as an LDS broadcast.  Coordinates are relative to the group's box centre
-// (computed in FP64, then rounded) so FP32 keeps the digits that matter.
-// Chunks of 64 entries are summed plainly and folded into Neumaier-
-// compensated totals.
+// per body.  The walk tests whole batches of cells at once: a per-wave LDS
+// stack holds ranges of sibling cells (the children of one opened cell are
+// contiguous in level order), and each round pops up to 8 ranges (4 in 2D),
+// gives every lane one cell, and runs the opening test for all of them in
+// FP64.  Accepted cells become list entries, leaves that are not accepted
+// contribute their bodies (copied by all lanes together, 16 bodies per leaf
+// side by side), opened cells push the range of their children.  The list
+// lives in LDS; when it is full it is flushed: every lane sums it for its
+// own body in FP32, reading each entry as an LDS broadcast.  Coordinates are
+// relative to the group's box centre (FP64 difference, then rounded) so FP32
+// keeps the significant digits; chunks of 64 entries are summed plainly and
+// folded into Neumaier-compensated totals.
+//
+// Stack bound: a round pushes at most 64 ranges; popping a single range at a
+// time is a depth-first descent that adds at most (R-1) ranges per level
+// plus R (R = cells per range, 8 in 3D, 4 in 2D), so full batches are popped
+// only while that reserve is free and the stack can never overflow.
 #include "tc_internal.h"
 
 #include <math.h>
@@ -24,21 +28,16 @@
 namespace tc {
 namespace {
 
-constexpr int kCap = 512;        // LDS list entries per wave (8 KiB)
+constexpr int kListCap = 512;     // LDS list entries per wave (16 B each)
+constexpr int kStackCap = 512;    // LDS range-stack entries per wave (4 B each)
 constexpr int kWavesPerBlock = 4;
 
-__device__ __forceinline__ void lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
-    }
-    return x;
+// Order LDS accesses of the lanes of one wave (a wave's LDS operations are
+// performed in program order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -53,6 +52,13 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// A value equal in every lane, made visibly uniform (scalar registers).
+__device__ __forceinline__ double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Neumaier compensated accumulation of x into (s, c).
 __device__ __forceinline__ void comp_add(float& s, float& c, float x) {
     const float t = s + x;
@@ -65,21 +71,23 @@ struct Acc {
     float sx, sy, sz, sp, cx, cy, cz, cp;
 };
 
-// Sum `cnt` list entries (padded to a multiple of 8 with massless entries)
-// for this lane's body.
+// Sum the first `cnt` list entries for this lane's body.  cnt is padded up
+// to a multiple of 8 with massless entries, which add exactly zero.
 template <int D>
-__device__ __forceinline__ void flush(const float4* L, int cnt, float xi, float yi, float zi,
-                                      float eps2, Acc& a) {
-    for (int e = 0; e < cnt; e += kWave) {
-        const int lim = min(kWave, cnt - e);
+__device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, float zi, float eps2, Acc& a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int padded = (cnt + 7) & ~7;
+    for (int j = cnt + lane; j < padded; j += kWave) L[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_lds_sync();
+    for (int e = 0; e < padded; e += kWave) {
+        const int lim = min(kWave, padded - e);
         float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
         for (int k = 0; k < lim; k += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const float4 p = L[e + k + u];
                 const float dx = p.x - xi, dy = p.y - yi;
-                float r2;
-                float dz = 0.f;
+                float r2, dz = 0.f;
                 if (D == 3) {
                     dz = p.z - zi;
                     r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
@@ -101,17 +109,7 @@ __device__ __forceinline__ void flush(const float4* L, int cnt, float xi, float 
         if (D == 3) comp_add(a.sz, a.cz, az);
         comp_add(a.sp, a.cp, ap);
     }
-}
-
-template <int D>
-__device__ __forceinline__ void pad_and_flush(float4* L, int cnt, float xi, float yi, float zi,
-                                              float eps2, Acc& a) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int padded = (cnt + 7) & ~7;
-    for (int j = cnt + lane; j < padded; j += kWave) L[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    lds_fence();
-    flush<D>(L, padded, xi, yi, zi, eps2, a);
-    lds_fence();
+    wave_lds_sync();
 }
 
 __device__ __forceinline__ float4 rel_entry(const Body& b, double rx, double ry, double rz) {
@@ -121,169 +119,234 @@ __device__ __forceinline__ float4 rel_entry(const Body& b, double rx, double ry,
 template <int D>
 __global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__ walk,
                                                     const Body* __restrict__ bodies,
-                                                    const uint32_t* __restrict__ perm, int64_t n,
-                                                    int64_t ngroups, float G, float eps2,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ gbeg,
+                                                    const int32_t* __restrict__ gcnt, uint32_t* queue,
+                                                    int lpl_log2, float G, float eps2,
                                                     const DevParams* __restrict__ prm,
                                                     float* __restrict__ acc, float* __restrict__ pot,
                                                     int64_t* __restrict__ m2p_out,
                                                     int64_t* __restrict__ p2p_out) {
-    __shared__ float4 s_list[kWavesPerBlock][kCap];
+    constexpr int R = D == 3 ? 8 : 4;                    // lanes (cells) per popped range
+    constexpr int RP = kWave / R;                        // ranges per full round
+    constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
+    static_assert(kStackCap >= kWave + kReserve + kWave, "stack too small for its bound");
+
+    __shared__ float4 s_list[kWavesPerBlock][kListCap];
+    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-
-    // XCD-aware order: hardware deals blocks round-robin over the 8 XCDs; give
-    // each XCD a contiguous range of groups so neighbouring groups, which walk
-    // nearly the same cells, share one L2.
-    const unsigned B = gridDim.x, b = blockIdx.x;
-    const unsigned q = B / 8, r = B % 8, x = b % 8;
-    const unsigned lb = x * q + (x < r ? x : r) + b / 8;
-    const int64_t g = (int64_t)lb * kWavesPerBlock + wv;
-    if (g >= ngroups) return;
-
-    const int64_t i0 = g * kGroup;
-    const int64_t i = i0 + lane;
-    const bool valid = i < n;
-    const Body me = bodies[valid ? i : i0];
-
-    // group bounding box (exact) and its centre, the group's FP32 origin
-    const double lox = wave_min(me.x), hix = wave_max(me.x);
-    const double loy = wave_min(me.y), hiy = wave_max(me.y);
-    const double loz = D == 3 ? wave_min(me.z) : 0.0, hiz = D == 3 ? wave_max(me.z) : 0.0;
-    const double rx = (lox + hix) * 0.5, ry = (loy + hiy) * 0.5, rz = (loz + hiz) * 0.5;
-    const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
-
+    const uint64_t lanes_below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     float4* L = s_list[wv];
-    Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int len = 0;
-    int64_t nm2p = 0, np2p = 0;
-    const uint32_t C = prm->ncells;
-    uint32_t cursor = 0;
+    uint32_t* S = s_stack[wv];
+    const int lpl = 1 << lpl_log2;                       // lanes per leaf in a copy batch
+    const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
 
-    while (cursor < C) {
-        const uint32_t c = cursor + lane;
-        const bool vc = c < C;
-        WalkCell wc;
-        if (vc) {
-            wc = walk[c];
-        } else {
-            wc.cx = wc.cy = wc.cz = 0.0;
-            wc.rcrit2 = INFINITY;
-            wc.m = 0.f;
-            wc.skip = (int32_t)C;
-            wc.begin = 0;
-            wc.cnt_leaf = 0;
-        }
-        // opening test: squared distance from the centre of mass to the box
-        const double dxm = fmax(fmax(lox - wc.cx, 0.0), wc.cx - hix);
-        const double dym = fmax(fmax(loy - wc.cy, 0.0), wc.cy - hiy);
-        double d2 = dxm * dxm + dym * dym;
-        if (D == 3) {
-            const double dzm = fmax(fmax(loz - wc.cz, 0.0), wc.cz - hiz);
-            d2 = d2 + dzm * dzm;
-        }
-        const bool accept = vc && d2 > wc.rcrit2;
-        const bool leaf = vc && wc.cnt_leaf < 0;
-        const bool opened = vc && !accept && !leaf;
-        const uint64_t O = __ballot(opened);
-        const uint64_t V = __ballot(vc);
+    // Persistent waves.  The groups are split into one contiguous share per
+    // XCD (blocks are dealt round-robin over the 8 XCDs, so block b runs on
+    // XCD b mod 8): neighbouring groups walk nearly the same cells and then
+    // share one L2.  A wave takes the next group of its home share, then
+    // helps the other shares; every pop advances a counter, so every wave
+    // exits once all shares are drained.
+    const uint32_t NG = prm->ngroups;
+    const int home = (int)(blockIdx.x % kXcd);
+    for (int hop = 0; hop < kXcd; ++hop) {
+        const int xq = (home + hop) % kXcd;
+        const uint32_t g_lo = (uint32_t)(((uint64_t)NG * xq) / kXcd);
+        const uint32_t g_hi = (uint32_t)(((uint64_t)NG * (xq + 1)) / kXcd);
+        // every lane takes part in the pop (lane 0 adds 1, the others 0), so
+        // the loop stays uniform; lane 0's result is the counter before its
+        // own increment whatever order the lanes are served in
+        uint32_t g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
+                                (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+        while (g < g_hi) {
 
-        // follow the visited chain inside the window
-        uint64_t T = 0;
-        int v = 0;
-        uint32_t next;
-        while (true) {
-            if (v >= kWave || !((V >> v) & 1ull)) {
-                next = cursor + (uint32_t)v;
-                break;
-            }
-            const uint64_t rest = ~O & V & (~0ull << v);
-            if (rest == 0) {
-                next = cursor + (uint32_t)__popcll(V);
-                break;
-            }
-            const int t = __builtin_ctzll(rest);
-            T |= 1ull << t;
-            v = __builtin_amdgcn_readlane(wc.skip, t) - (int)cursor;
-        }
+            const int64_t i0 = gbeg[g];
+            const int gn = gcnt[g];
+            const int64_t i = i0 + lane;
+            const bool valid = lane < gn;
+            const Body me = bodies[valid ? i : i0];
 
-        bool term = (T >> lane) & 1ull;
-        const int cnt = wc.cnt_leaf & 0x7fffffff;
-        int ne = term ? (accept ? 1 : cnt) : 0;
-        int incl = wave_incl_scan(ne);
-        int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-        if (len + total > kCap) {
-            pad_and_flush<D>(L, len, xi, yi, zi, eps2, a);
-            len = 0;
-            if (total > kCap) {
-                const uint64_t keep = __ballot(term && incl <= kCap);
-                const int t0 = __builtin_ctzll(T & ~keep);
-                if (keep == 0) {
-                    // the first terminal is a leaf too large for the list
-                    // (only bodies with identical keys): stream it through
-                    const int bcount = __builtin_amdgcn_readlane(cnt, t0);
-                    const int bbeg = __builtin_amdgcn_readlane(wc.begin, t0);
-                    for (int off = 0; off < bcount; off += kCap) {
-                        const int m = min(kCap, bcount - off);
-                        for (int j = lane; j < m; j += kWave) L[j] = rel_entry(bodies[bbeg + off + j], rx, ry, rz);
-                        pad_and_flush<D>(L, m, xi, yi, zi, eps2, a);
-                    }
-                    np2p += bcount;
-                    cursor = (uint32_t)__builtin_amdgcn_readlane(wc.skip, t0);
-                    continue;
+            // group bounding box (exact) and its centre, the group's FP32 origin
+            const double lox = uniform(wave_min(me.x)), hix = uniform(wave_max(me.x));
+            const double loy = uniform(wave_min(me.y)), hiy = uniform(wave_max(me.y));
+            const double loz = D == 3 ? uniform(wave_min(me.z)) : 0.0;
+            const double hiz = D == 3 ? uniform(wave_max(me.z)) : 0.0;
+            const double rx = (lox + hix) * 0.5, ry = (loy + hiy) * 0.5, rz = (loz + hiz) * 0.5;
+            const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
+
+            Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            int len = 0;
+            int64_t nm2p = 0, np2p = 0;
+
+            if (lane == 0) S[0] = 0u;                            // the root: first cell 0, one cell
+            wave_lds_sync();
+            int top = 1;
+            while (top > 0) {
+                // pop: full batches only while the depth-first reserve is free
+                const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
+                const int rr = lane / R, j = lane % R;
+                uint32_t packed = 0;
+                if (rr < nr) packed = S[top - 1 - rr];
+                top -= nr;
+                const uint32_t first = packed >> 3;
+                const int rlen = (int)(packed & 7u) + 1;
+                const bool vc = rr < nr && j < rlen;
+                wave_lds_sync();
+
+                WalkCell wc;
+                if (vc) {
+                    wc = walk[first + j];
+                } else {
+                    wc.cx = wc.cy = wc.cz = 0.0;
+                    wc.rcrit2 = INFINITY;
+                    wc.m = 0.f;
+                    wc.a = 0;
+                    wc.b = 0;
                 }
-                T = keep;
-                term = (T >> lane) & 1ull;
-                total = __builtin_amdgcn_readlane(incl, 63 - __builtin_clzll(keep));
-                next = cursor + (uint32_t)t0;
-            }
-        }
-        if (term) {
-            const int off = len + incl - ne;
-            if (accept) {
-                L[off] = make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
-            } else {
-                for (int j = 0; j < ne; ++j) L[off + j] = rel_entry(bodies[wc.begin + j], rx, ry, rz);
-            }
-        }
-        const int nacc = __popcll(__ballot(term && accept));
-        nm2p += nacc;
-        np2p += total - nacc;
-        len += total;
-        cursor = next;
-    }
-    pad_and_flush<D>(L, len, xi, yi, zi, eps2, a);
+                // opening test: squared distance from the centre of mass to the box
+                const double dxm = fmax(fmax(lox - wc.cx, 0.0), wc.cx - hix);
+                const double dym = fmax(fmax(loy - wc.cy, 0.0), wc.cy - hiy);
+                double d2 = dxm * dxm + dym * dym;
+                if (D == 3) {
+                    const double dzm = fmax(fmax(loz - wc.cz, 0.0), wc.cz - hiz);
+                    d2 = d2 + dzm * dzm;
+                }
+                const bool leaf = vc && wc.b < 0;
+                const bool accept = vc && d2 > wc.rcrit2;
+                const bool opened = vc && !accept && !leaf;
+                const bool direct = leaf && !accept;
 
-    if (valid) {
-        // the body met itself once as a direct entry: no force (zero
-        // displacement) but a -m/eps potential term, removed here exactly as
-        // it was formed
-        const float mself = (float)me.m;
-        const float sself = __builtin_amdgcn_rsqf(eps2);
-        const float ph = (a.sp + a.cp) + mself * sself;
-        const int64_t o = perm[i];
-        acc[o * D + 0] = G * (a.sx + a.cx);
-        acc[o * D + 1] = G * (a.sy + a.cy);
-        if (D == 3) acc[o * D + 2] = G * (a.sz + a.cz);
-        pot[o] = G * ph;
+                // push the children ranges of opened cells
+                const uint64_t O = __ballot(opened);
+                if (opened) S[top + __popcll(O & lanes_below)] = ((uint32_t)wc.a << 3) | (uint32_t)(wc.b - 1);
+                top += __popcll(O);
+
+                // accepted cells: one entry each, at their centre of mass
+                const uint64_t A = __ballot(accept);
+                const int na = __popcll(A);
+                if (na) {
+                    if (len + na > kListCap) {
+                        flush<D>(L, len, xi, yi, zi, eps2, a);
+                        len = 0;
+                    }
+                    if (accept)
+                        L[len + __popcll(A & lanes_below)] =
+                            make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
+                    len += na;
+                    nm2p += na;
+                }
+
+                // leaves that are not accepted: their bodies, copied cooperatively
+                const int cnt = direct ? (wc.b & 0x7fffffff) : 0;
+                const uint64_t P = __ballot(direct);
+                if (P) {
+                    const uint64_t big = __ballot(direct && cnt > lpl);
+                    uint64_t small = P & ~big;
+                    while (small) {
+                        int my_begin = 0, my_cnt = 0, my_off = 0, tot = 0;
+                        for (int s = 0; s < (kWave >> lpl_log2) && small; ++s) {
+                            const int l = __builtin_ctzll(small);
+                            small &= small - 1;
+                            const int cl = __builtin_amdgcn_readlane(cnt, l);
+                            const int bl = __builtin_amdgcn_readlane(wc.a, l);
+                            if (slot == s) {
+                                my_begin = bl;
+                                my_cnt = cl;
+                                my_off = tot;
+                            }
+                            tot += cl;
+                        }
+                        if (len + tot > kListCap) {
+                            flush<D>(L, len, xi, yi, zi, eps2, a);
+                            len = 0;
+                        }
+                        if (jj < my_cnt) L[len + my_off + jj] = rel_entry(bodies[my_begin + jj], rx, ry, rz);
+                        len += tot;
+                        np2p += tot;
+                    }
+                    uint64_t bg = big;
+                    while (bg) {                                   // leaves larger than a batch slot
+                        const int l = __builtin_ctzll(bg);
+                        bg &= bg - 1;
+                        const int cl = __builtin_amdgcn_readlane(cnt, l);
+                        const int bl = __builtin_amdgcn_readlane(wc.a, l);
+                        for (int o = 0; o < cl; o += kWave) {
+                            const int m = min(kWave, cl - o);
+                            if (len + m > kListCap) {
+                                flush<D>(L, len, xi, yi, zi, eps2, a);
+                                len = 0;
+                            }
+                            if (lane < m) L[len + lane] = rel_entry(bodies[bl + o + lane], rx, ry, rz);
+                            len += m;
+                        }
+                        np2p += cl;
+                    }
+                }
+                wave_lds_sync();
+            }
+            flush<D>(L, len, xi, yi, zi, eps2, a);
+
+            if (valid) {
+                // the body met itself once as a direct entry: no force (zero
+                // displacement) but a -m/eps potential term, removed here exactly as
+                // it was formed
+                const float mself = (float)me.m;
+                const float sself = __builtin_amdgcn_rsqf(eps2);
+                const float ph = (a.sp + a.cp) + mself * sself;
+                const int64_t o = perm[i];
+                acc[o * D + 0] = G * (a.sx + a.cx);
+                acc[o * D + 1] = G * (a.sy + a.cy);
+                if (D == 3) acc[o * D + 2] = G * (a.sz + a.cz);
+                pot[o] = G * ph;
+            }
+            if (lane == 0) {
+                m2p_out[g] = nm2p;
+                p2p_out[g] = np2p;
+            }
+            g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
+                           (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+        }
     }
-    if (lane == 0) {
-        m2p_out[g] = nm2p;
-        p2p_out[g] = np2p;
-    }
+}
+
+__global__ void k_reset_queue(uint32_t* queue) {
+    if (threadIdx.x < kXcd) queue[threadIdx.x] = 0u;
 }
 
 }  // namespace
 
 hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uint32_t* perm,
-                             int64_t n, int dim, float G, float eps2, const DevParams* prm,
-                             float* acc, float* pot, int64_t* m2p, int64_t* p2p, hipStream_t s) {
-    const int64_t ngroups = (n + kGroup - 1) / kGroup;
-    const unsigned nb = (unsigned)((ngroups + kWavesPerBlock - 1) / kWavesPerBlock);
+                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
+                             int64_t n, int dim, int leaf_cap, float G, float eps2,
+                             const DevParams* prm, float* acc, float* pot, int64_t* m2p,
+                             int64_t* p2p, hipStream_t s) {
+    (void)n;
+    // as many blocks as can be resident at once (the waves are persistent)
+    static int resident[2] = {0, 0};
+    int& res = resident[dim == 3];
+    if (res == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3>, 256, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2>, 256, 0);
+        if (e != hipSuccess) return e;
+        res = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    int64_t want = (gmax + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (want > res) want = res;
+    if (want < kXcd) want = kXcd;
+    const unsigned nb = (unsigned)want;
+    int lpl_log2 = 0;                                   // lanes per leaf: next power of two, <= 64
+    while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
     if (dim == 3)
-        hipLaunchKernelGGL(k_walk_force<3>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, n, ngroups, G, eps2,
-                           prm, acc, pot, m2p, p2p);
+        hipLaunchKernelGGL(k_walk_force<3>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, gbeg, gcnt, queue,
+                           lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
     else
-        hipLaunchKernelGGL(k_walk_force<2>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, n, ngroups, G, eps2,
-                           prm, acc, pot, m2p, p2p);
+        hipLaunchKernelGGL(k_walk_force<2>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, gbeg, gcnt, queue,
+                           lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
     return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ constexpr int kGroup = 64;          // bodies per walk group = one wave
 constexpr int kSortTile = 4096;     // keys per radix-sort tile (256 threads x 16)
 constexpr int kScanTile = 4096;     // elements per scan tile
 constexpr int kDiagBlocks = 512;    // fixed partial count of the FP64 diagnostics
+constexpr int kCluster = 1024;      // walk groups never straddle a cell of <= kCluster bodies
+constexpr int kXcd = 8;             // XCDs per MI355X: one work queue each
 
 // Status bits raised by kernels into the workspace's status word.
 constexpr uint32_t kFlagNonFinite = 1u;
@@ -46,14 +48,18 @@ struct __align__(16) Moments {
     double pad;
 };
 
-// What the walk reads per cell: 48 bytes, one lane per cell.
+// What the walk reads per cell, in level order (breadth-first: all cells of
+// level 0, then level 1, ...; within a level in pre-order), so that the
+// children of every cell are contiguous.  48 bytes, one lane per cell.
+//   a = leaf ? first sorted body : level-order index of the first child
+//   b = leaf ? (body count | 0x80000000) : number of children
 struct __align__(16) WalkCell {
     double cx, cy, cz;   // centre of mass (FP64)
     double rcrit2;       // squared opening radius for the current theta
     float m;             // total mass, FP32
-    int32_t skip;        // pre-order index past the subtree
-    int32_t begin;       // first sorted body
-    int32_t cnt_leaf;    // bit 31: leaf; low 31 bits: body count
+    int32_t a;
+    int32_t b;
+    int32_t pad;
 };
 
 // Device-side scalars computed by the kernels.
@@ -63,6 +69,8 @@ struct DevParams {
     double scale;        // 2^L / size
     uint32_t ncells;
     uint32_t status;     // kFlag* bits, sticky until the next build
+    uint32_t ngroups;    // walk groups of the current tree
+    uint32_t pad;
 };
 
 // Carve-up of the caller's workspace.
@@ -76,7 +84,11 @@ struct Layout {
     size_t off_params, off_keys_a, off_keys_b, off_idx_a, off_idx_b, off_bodies, off_range,
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
         off_walk, off_arrive, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
-        off_diag_out, total;
+        off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
+        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, total;
+    int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
+    int64_t gmax;        // bound on walk groups
+    int64_t cscan_tiles; // scan tiles over cmax cells
 };
 
 Layout make_layout(int64_t n, int dim, int leaf_cap);
@@ -96,19 +108,27 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
                            uint32_t* arrive, int64_t cmax, DevParams* prm, hipStream_t s);
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, const DevParams* prm, uint64_t* keys_a,
+                              uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
+                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, hipStream_t s);
+hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
+                         int64_t scan_tiles, int32_t* gbeg, int32_t* gcnt, int64_t gmax, DevParams* prm,
+                         hipStream_t s);
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
-                          Moments* mom, WalkCell* walk, uint32_t* arrive, const DevParams* prm,
-                          hipStream_t s);
+                          const uint32_t* pre2bfs, Moments* mom, WalkCell* walk, uint32_t* arrive,
+                          const DevParams* prm, hipStream_t s);
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
-                      WalkCell* walk, const DevParams* prm, hipStream_t s);
+                      const uint32_t* pre2bfs, WalkCell* walk, const DevParams* prm, hipStream_t s);
 hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t cmax,
                          const DevParams* prm, int32_t* level, uint64_t* prefix, int32_t* begin,
                          int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
                          int32_t* leaf, double* M, double* com, double* Q, hipStream_t s);
 // force.hip
 hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uint32_t* perm,
-                             int64_t n, int dim, float G, float eps2, const DevParams* prm,
-                             float* acc, float* pot, int64_t* m2p, int64_t* p2p, hipStream_t s);
+                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
+                             int64_t n, int dim, int leaf_cap, float G, float eps2,
+                             const DevParams* prm, float* acc, float* pot, int64_t* m2p,
+                             int64_t* p2p, hipStream_t s);
 // step.hip
 hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,
                              double dt, hipStream_t s);

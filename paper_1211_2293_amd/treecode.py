@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "tc.h")
 TC_OK, TC_EINVAL, TC_EWORKSPACE, TC_ESTATE, TC_EHIP, TC_ENONFINITE = 0, -1, -2, -3, -4, -5
 TC_F32, TC_F64 = 0, 1
 GROUP = 64
+CLUSTER = 1024
 
 _LIB = None
 
@@ -58,6 +59,8 @@ def lib():
         "tc_get_keys": (i32, [P, P, P]),
         "tc_get_cells": (i32, [P] * 12),
         "tc_get_counts": (i32, [P, P, P]),
+        "tc_num_groups": (i32, [P, C.POINTER(C.c_int64)]),
+        "tc_get_groups": (i32, [P, P, P]),
         "tc_set_timing": (i32, [P, i32]),
         "tc_get_timing": (i32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
@@ -229,8 +232,22 @@ class Treecode:
                                   _ptr(o.get("com")), _ptr(o.get("Q"))))
         return out
 
+    def num_groups(self) -> int:
+        c = C.c_int64()
+        _check(lib().tc_num_groups(self._h, C.byref(c)))
+        return int(c.value)
+
+    def groups(self):
+        """First sorted body and size of every walk group (int32 tensors)."""
+        G = self.num_groups()
+        dev = self.stream.device
+        gb = torch.empty(G, dtype=torch.int32, device=dev)
+        gc = torch.empty(G, dtype=torch.int32, device=dev)
+        _check(lib().tc_get_groups(self._h, _ptr(gb), _ptr(gc)))
+        return gb, gc
+
     def counts(self):
-        G = (self.n + GROUP - 1) // GROUP
+        G = self.num_groups()
         dev = self.stream.device
         m2p = torch.empty(G, dtype=torch.int64, device=dev)
         p2p = torch.empty(G, dtype=torch.int64, device=dev)
@@ -241,10 +258,9 @@ class Treecode:
         """Body-entry interactions of the last force evaluation (self
         included): sum over groups of list length x bodies in the group."""
         m2p, p2p = self.counts()
+        _, gc = self.groups()
         per = (m2p + p2p).cpu().numpy()
-        sizes = np.full(len(per), GROUP, np.int64)
-        sizes[-1] = self.n - GROUP * (len(per) - 1)
-        return int((per * sizes).sum())
+        return int((per * gc.cpu().numpy().astype(np.int64)).sum())
 
     def set_timing(self, on: bool):
         _check(lib().tc_set_timing(self._h, int(bool(on))))

@@ -33,6 +33,8 @@ def gpu_tree(pos, mass, leaf_cap, theta=None, G=1.0, eps=None, moments=True):
         m2p, p2p = tc.counts()
         out.update(acc=acc.cpu().numpy(), pot=pot.cpu().numpy(), m2p=m2p.cpu().numpy(),
                    p2p=p2p.cpu().numpy())
+    gb, gc = tc.groups()
+    out["gbeg"], out["gcnt"] = gb.cpu().numpy(), gc.cpu().numpy()
     torch.cuda.synchronize()
     k, perm = tc.keys()
     out["key"] = k.cpu().numpy().view(np.uint64)
@@ -60,6 +62,9 @@ def assert_tree_equal(g, t):
     for f in ("level", "prefix", "begin", "count", "parent", "skip", "nch", "leaf"):
         np.testing.assert_array_equal(gc[f].astype(np.int64) if f != "prefix" else gc[f],
                                       c[f].astype(np.int64) if f != "prefix" else c[f], err_msg=f)
+    obeg, ocnt = t.groups(64, 1024)
+    np.testing.assert_array_equal(g["gbeg"], obeg)
+    np.testing.assert_array_equal(g["gcnt"], ocnt)
     if "M" in gc:
         np.testing.assert_array_equal(gc["M"], c["M"])
         np.testing.assert_array_equal(gc["com"], c["com"])

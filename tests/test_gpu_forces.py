@@ -18,13 +18,16 @@ def _check_against_oracle(pos, mass, lc, theta, eps, G=1.0):
     g = gpu_tree(pos, mass, lc, theta=theta, G=G, eps=eps)
     assert g["status"] == 0
     t = oracle.Tree(pos.astype(np.float64), np.asarray(mass, np.float64), lc)
-    m2p, p2p = t.walk_counts(theta, 64)
+    gb, gc = t.groups(64, 1024)
+    np.testing.assert_array_equal(g["gbeg"], gb)
+    np.testing.assert_array_equal(g["gcnt"], gc)
+    m2p, p2p = t.walk_counts_groups(theta, gb, gc)
     np.testing.assert_array_equal(g["m2p"], m2p)
     np.testing.assert_array_equal(g["p2p"], p2p)
-    a, p = t.forces(theta, G=G, eps=eps)
+    a, p = t.forces_groups(theta, gb, gc, G=G, eps=eps)
     ea, ep = oracle.rel_l2(g["acc"], a), oracle.rel_l2(g["pot"], p)
     print(f"n={len(pos)} theta={theta}: acc {ea:.2e} pot {ep:.2e} "
-          f"interactions/body {((m2p + p2p) * 64).sum() / len(pos):.0f}", flush=True)
+          f"interactions/body {((m2p + p2p) * gc).sum() / len(pos):.0f}", flush=True)
     assert ea < TOL and ep < TOL
     return g, t
 
@@ -58,7 +61,7 @@ def test_ragged_and_tiny_sizes():
         pos = rng.uniform(0, 1, (n, 3)).astype(np.float32)
         mass = rng.uniform(0.5, 1.5, n).astype(np.float32)
         g = gpu_tree(pos, mass, 8, theta=0.6, eps=1e-2)
-        a, p = oracle.direct(pos, mass, eps=1e-2) if n <= 2 else oracle.Tree(pos, mass, 8).forces(0.6, eps=1e-2)
+        a, p = oracle.direct(pos, mass, eps=1e-2) if n <= 2 else oracle.Tree(pos, mass, 8).walk_forces(0.6, eps=1e-2)
         if n == 1:
             assert np.all(g["acc"] == 0) and np.all(g["pot"] == 0)
             continue
@@ -73,6 +76,7 @@ def test_theta_zero_is_direct_sum():
     assert oracle.rel_l2(g["pot"], p) < TOL
     # every group's list is all n bodies
     assert np.all(g["m2p"] == 0) and np.all(g["p2p"] == len(w.pos))
+    assert g["gcnt"].sum() == len(w.pos)
 
 
 def test_coincident_bodies_and_oversized_leaf():
@@ -82,7 +86,7 @@ def test_coincident_bodies_and_oversized_leaf():
     pos[:10] += np.linspace(0.1, 0.5, 10)[:, None].astype(np.float32)
     mass = np.ones(n, np.float32) / n
     g = gpu_tree(pos, mass, 8, theta=0.5, eps=1e-3)
-    a, p = oracle.Tree(pos, mass, 8).forces(0.5, eps=1e-3)
+    a, p = oracle.Tree(pos, mass, 8).walk_forces(0.5, eps=1e-3)
     assert np.abs(g["acc"] - a).max() <= 1e-5 * np.abs(a).max()
     assert oracle.rel_l2(g["pot"], p) < TOL
 

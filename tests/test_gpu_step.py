@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _tree_force(mass, lc, theta, eps, G=1.0):
-    return lambda x: oracle.Tree(x, mass, lc).forces(theta, G=G, eps=eps)[0]
+    return lambda x: oracle.Tree(x, mass, lc).walk_forces(theta, G=G, eps=eps)[0]
 
 
 def test_uniform_cube_one_force_and_one_step():
@@ -28,7 +28,7 @@ def test_uniform_cube_one_force_and_one_step():
     acc0, pot0 = tc.forces(w.G, w.eps)
     a0 = acc0.cpu().numpy()
     t0 = oracle.Tree(w.pos, w.mass, w.leaf_cap)
-    ra0, rp0 = t0.forces(w.theta, eps=w.eps)
+    ra0, rp0 = t0.walk_forces(w.theta, eps=w.eps)
     d0, _ = oracle.direct(w.pos, w.mass, eps=w.eps)
     e_tree, e_direct = oracle.rel_l2(a0, ra0), oracle.rel_l2(a0, d0)
     print(f"force vs same-theta oracle {e_tree:.2e}, vs direct sum {e_direct:.2e}, "
