@@ -48,6 +48,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_idx_a = take(4 * (size_t)n);
     l.off_idx_b = take(4 * (size_t)n);
     l.off_bodies = take(sizeof(Body) * (size_t)n);
+    l.off_bodies32 = take(16 * (size_t)n);
     l.off_range = take(4 * (size_t)n);
     l.off_nper = take(4 * (size_t)n);
     l.off_cstart = take(4 * (size_t)(n + 1));
@@ -57,7 +58,6 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_cells = take(sizeof(Cell) * (size_t)l.cmax);
     l.off_mom = take(sizeof(Moments) * (size_t)l.cmax);
     l.off_walk = take(sizeof(WalkCell) * (size_t)l.cmax);
-    l.off_arrive = take(4 * (size_t)l.cmax);
     l.off_acc = take(4 * (size_t)n * dim);
     l.off_pot = take(4 * (size_t)n);
     l.off_m2p = 0;   // placed after the group bound is known
@@ -84,6 +84,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_gbeg = take(4 * (size_t)l.gmax);
     l.off_gcnt = take(4 * (size_t)l.gmax);
     l.off_queue = take(4 * 2 * kXcd);
+    l.off_lvl_off = take(4 * 64);
     l.off_m2p = take(8 * (size_t)l.gmax);
     l.off_p2p = take(8 * (size_t)l.gmax);
     l.total = off;
@@ -167,17 +168,17 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
                             dim * levels_for(dim), ctx->at<uint32_t>(l.off_hist),
                             ctx->at<uint32_t>(l.off_digit_tot), l.sort_tiles, s));
     TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
-                              ctx->at<Body>(l.off_bodies), s));
+                              ctx->at<Body>(l.off_bodies), ctx->at<float4>(l.off_bodies32), s));
     TC_HIP(ctx, launch_topology(ctx->at<uint64_t>(l.off_keys_a), n, dim, leaf_cap,
                                 ctx->at<uint32_t>(l.off_range), ctx->at<uint32_t>(l.off_nper),
                                 ctx->at<uint32_t>(l.off_cstart), ctx->at<uint32_t>(l.off_scan_part),
-                                l.scan_tiles, ctx->at<Cell>(l.off_cells), ctx->at<uint32_t>(l.off_arrive),
+                                l.scan_tiles, ctx->at<Cell>(l.off_cells),
                                 l.cmax, prm, s));
-    TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
+    TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
                                    ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
                                    ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
                                    ctx->at<uint32_t>(l.off_digit_tot), l.lvl_tiles,
-                                   ctx->at<uint32_t>(l.off_pre2bfs), s));
+                                   ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<uint32_t>(l.off_lvl_off), s));
     TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
                               ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
                               l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
@@ -193,9 +194,9 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
 int do_moments(tc_ctx* ctx) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
-                               ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<Moments>(l.off_mom),
-                               ctx->at<WalkCell>(l.off_walk),
-                               ctx->at<uint32_t>(l.off_arrive), ctx->prm(), ctx->stream));
+                               ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
+                               ctx->at<uint32_t>(l.off_lvl_off), ctx->at<Moments>(l.off_mom),
+                               ctx->at<WalkCell>(l.off_walk), ctx->stream));
     ctx->state = kMoments;
     return TC_OK;
 }
@@ -220,6 +221,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, hipEventRecord(e0, ctx->stream));
     }
     TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
+                                  ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                   ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
                                   ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
                                   ctx->n, ctx->dim, ctx->leaf_cap,

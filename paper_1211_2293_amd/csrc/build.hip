@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
                                                 const uint32_t* __restrict__ perm, int64_t n,
-                                                Body* __restrict__ bodies) {
+                                                Body* __restrict__ bodies, float4* __restrict__ bodies32) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t o = perm[i];
@@ -298,6 +298,8 @@ __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ pos, const
         b.z = D == 3 ? (double)pos[o * D + 2] : 0.0;
         b.m = (double)mass[o];
         bodies[i] = b;
+        // FP32 inputs also get a compact copy (exactly the input values)
+        if (bodies32) bodies32[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.m);
     }
 }
 
@@ -444,13 +446,12 @@ __global__ void __launch_bounds__(256) k_topo_emit(const uint64_t* __restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(256) k_topo_link(Cell* __restrict__ cells, uint32_t* __restrict__ arrive,
+__global__ void __launch_bounds__(256) k_topo_link(Cell* __restrict__ cells,
                                                    const DevParams* __restrict__ prm, int64_t cmax) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
          k += (int64_t)gridDim.x * blockDim.x) {
-        arrive[k] = 0;
         const Cell c = cells[k];
         if (c.leaf_nch < 0) continue;          // leaf
         int nch = 0;
@@ -551,40 +552,40 @@ __device__ __forceinline__ void store_walk(WalkCell* walk, const uint32_t* __res
     walk[pre2bfs[k]] = w;
 }
 
-// One thread per leaf; the last child to arrive at a parent computes it
-// (children in digit order), so results do not depend on arrival order.
+// One launch per level, deepest first: a cell's children sit one level
+// below it and were finished by the previous launch, so no cross-block
+// synchronisation is needed.  Cells of a level are contiguous in level
+// order.  Leaves sum their bodies in order, internal cells their children
+// in digit order: the result does not depend on scheduling.
 template <int D>
-__global__ void __launch_bounds__(256) k_moments(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
-                                                 const uint32_t* __restrict__ pre2bfs,
-                                                 Moments* mom, WalkCell* __restrict__ walk,
-                                                 uint32_t* arrive, const DevParams* __restrict__ prm,
-                                                 int64_t cmax) {
-    int64_t C = prm->ncells;
-    if (C > cmax) C = cmax;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
-         k += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(256) k_moments_level(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
+                                                       const uint32_t* __restrict__ bfs2pre,
+                                                       const uint32_t* __restrict__ pre2bfs,
+                                                       const uint32_t* __restrict__ lvl_off, int level,
+                                                       Moments* mom, WalkCell* __restrict__ walk) {
+    const int64_t b0 = lvl_off[level], b1 = lvl_off[level + 1];
+    for (int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < b1;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = bfs2pre[b];
         const Cell c = cells[k];
-        if (c.leaf_nch >= 0) continue;
         Moments mo;
-        leaf_moments<D>(c, bodies, mo);
+        if (c.leaf_nch < 0) leaf_moments<D>(c, bodies, mo);
+        else internal_moments<D>(k, cells, mom, mo);
         mom[k] = mo;
         store_walk(walk, pre2bfs, k, c, mo);
-        int64_t cur = k;
-        while (true) {
-            const int64_t p = cells[cur].parent;
-            if (p < 0) break;
-            __threadfence();                        // publish this child's moments
-            const uint32_t nch = (uint32_t)(cells[p].leaf_nch & 0x7fffffff);
-            const uint32_t old = atomicAdd(&arrive[p], 1u);
-            if (old + 1 != nch) break;              // a sibling is still missing
-            __threadfence();                        // see every sibling's moments
-            const Cell cp = cells[p];
-            Moments mp;
-            internal_moments<D>(p, cells, mom, mp);
-            mom[p] = mp;
-            store_walk(walk, pre2bfs, p, cp, mp);
-            cur = p;
+    }
+}
+
+// Start of each level in level order (levels 0..L, plus the end), from the
+// per-level counts the level sort produced.
+__global__ void k_level_offsets(const uint32_t* __restrict__ digit_tot, int L, uint32_t* __restrict__ lvl_off) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t run = 0;
+        for (int l = 0; l <= L; ++l) {
+            lvl_off[l] = run;
+            run += digit_tot[l];
         }
+        lvl_off[L + 1] = run;
     }
 }
 
@@ -782,14 +783,14 @@ hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint
 }
 
 hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
-                         int dim, int f64, Body* bodies, hipStream_t s) {
+                         int dim, int f64, Body* bodies, float4* bodies32, hipStream_t s) {
     const unsigned nb = grid_for(n);
     if (f64) {
-        if (dim == 3) hipLaunchKernelGGL((k_gather<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies);
-        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies);
+        if (dim == 3) hipLaunchKernelGGL((k_gather<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies, (float4*)nullptr);
+        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies, (float4*)nullptr);
     } else {
-        if (dim == 3) hipLaunchKernelGGL((k_gather<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies);
-        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies);
+        if (dim == 3) hipLaunchKernelGGL((k_gather<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies, bodies32);
+        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies, bodies32);
     }
     return hipGetLastError();
 }
@@ -797,7 +798,7 @@ hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm
 hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
-                           uint32_t* arrive, int64_t cmax, DevParams* prm, hipStream_t s) {
+                           int64_t cmax, DevParams* prm, hipStream_t s) {
     const unsigned nb = grid_for(n);
     if (dim == 3) hipLaunchKernelGGL(k_topo_count<3>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
     else hipLaunchKernelGGL(k_topo_count<2>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
@@ -807,13 +808,14 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
                        (const uint32_t*)scan_part, cstart);
     if (dim == 3) hipLaunchKernelGGL(k_topo_emit<3>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
     else hipLaunchKernelGGL(k_topo_emit<2>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
-    hipLaunchKernelGGL(k_topo_link, dim3(grid_for(cmax)), dim3(256), 0, s, cells, arrive, (const DevParams*)prm, cmax);
+    hipLaunchKernelGGL(k_topo_link, dim3(grid_for(cmax)), dim3(256), 0, s, cells, (const DevParams*)prm, cmax);
     return hipGetLastError();
 }
 
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, const DevParams* prm, uint64_t* keys_a,
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
                               uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, hipStream_t s) {
+                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, uint32_t* lvl_off,
+                              hipStream_t s) {
     hipLaunchKernelGGL(k_level_keys, dim3(grid_for(cmax)), dim3(256), 0, s, cells, prm, cmax, keys_a, idx_a);
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)tiles), dim3(256), 0, s, (const uint64_t*)keys_a, cmax, 0,
                        hist, tiles);
@@ -823,6 +825,8 @@ hipError_t launch_level_order(const Cell* cells, int64_t cmax, const DevParams* 
                        (const uint32_t*)digit_tot, tiles);
     hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
                        pre2bfs);
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, (const uint32_t*)digit_tot, levels_for(dim),
+                       lvl_off);
     return hipGetLastError();
 }
 
@@ -842,11 +846,17 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
 }
 
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
-                          const uint32_t* pre2bfs, Moments* mom, WalkCell* walk, uint32_t* arrive,
-                          const DevParams* prm, hipStream_t s) {
-    const unsigned nb = grid_for(cmax);
-    if (dim == 3) hipLaunchKernelGGL(k_moments<3>, dim3(nb), dim3(256), 0, s, cells, bodies, pre2bfs, mom, walk, arrive, prm, cmax);
-    else hipLaunchKernelGGL(k_moments<2>, dim3(nb), dim3(256), 0, s, cells, bodies, pre2bfs, mom, walk, arrive, prm, cmax);
+                          const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
+                          Moments* mom, WalkCell* walk, hipStream_t s) {
+    const unsigned nb = grid_for(cmax, 2048);
+    for (int l = levels_for(dim); l >= 0; --l) {
+        if (dim == 3)
+            hipLaunchKernelGGL(k_moments_level<3>, dim3(nb), dim3(256), 0, s, cells, bodies, bfs2pre, pre2bfs,
+                               lvl_off, l, mom, walk);
+        else
+            hipLaunchKernelGGL(k_moments_level<2>, dim3(nb), dim3(256), 0, s, cells, bodies, bfs2pre, pre2bfs,
+                               lvl_off, l, mom, walk);
+    }
     return hipGetLastError();
 }
 

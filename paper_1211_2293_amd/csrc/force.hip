@@ -28,8 +28,8 @@
 namespace tc {
 namespace {
 
-constexpr int kListCap = 512;     // LDS list entries per wave (16 B each)
-constexpr int kStackCap = 512;    // LDS range-stack entries per wave (4 B each)
+constexpr int kListCap = 256;     // LDS list entries per wave (16 B each)
+constexpr int kStackCap = 320;    // LDS range-stack entries per wave (4 B each)
 constexpr int kWavesPerBlock = 4;
 
 // Order LDS accesses of the lanes of one wave (a wave's LDS operations are
@@ -112,13 +112,38 @@ __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, fl
     wave_lds_sync();
 }
 
-__device__ __forceinline__ float4 rel_entry(const Body& b, double rx, double ry, double rz) {
+// List entry of a body relative to the group origin.  FP32 inputs keep a
+// 16-byte FP32 copy of the sorted bodies (exact: it is the input itself);
+// the FP64 difference is the same either way.
+__device__ __forceinline__ float4 body_entry(const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
+                                             int64_t j, double rx, double ry, double rz) {
+    if (bodies32) {
+        const float4 b = bodies32[j];
+        return make_float4((float)((double)b.x - rx), (float)((double)b.y - ry), (float)((double)b.z - rz), b.w);
+    }
+    const Body b = bodies[j];
     return make_float4((float)(b.x - rx), (float)(b.y - ry), (float)(b.z - rz), (float)b.m);
 }
 
+__device__ __forceinline__ WalkCell load_cell(const WalkCell* __restrict__ walk, uint32_t c, bool v) {
+    WalkCell wc;
+    if (v) {
+        wc = walk[c];
+    } else {
+        wc.cx = wc.cy = wc.cz = 0.0;
+        wc.rcrit2 = INFINITY;
+        wc.m = 0.f;
+        wc.a = 0;
+        wc.b = 0;
+        wc.pad = 0;
+    }
+    return wc;
+}
+
 template <int D>
-__global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__ walk,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
                                                     const Body* __restrict__ bodies,
+                                                    const float4* __restrict__ bodies32,
                                                     const uint32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ gbeg,
                                                     const int32_t* __restrict__ gcnt, uint32_t* queue,
@@ -178,31 +203,15 @@ __global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__
             int len = 0;
             int64_t nm2p = 0, np2p = 0;
 
-            if (lane == 0) S[0] = 0u;                            // the root: first cell 0, one cell
-            wave_lds_sync();
-            int top = 1;
-            while (top > 0) {
-                // pop: full batches only while the depth-first reserve is free
-                const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
-                const int rr = lane / R, j = lane % R;
-                uint32_t packed = 0;
-                if (rr < nr) packed = S[top - 1 - rr];
-                top -= nr;
-                const uint32_t first = packed >> 3;
-                const int rlen = (int)(packed & 7u) + 1;
-                const bool vc = rr < nr && j < rlen;
-                wave_lds_sync();
-
-                WalkCell wc;
-                if (vc) {
-                    wc = walk[first + j];
-                } else {
-                    wc.cx = wc.cy = wc.cz = 0.0;
-                    wc.rcrit2 = INFINITY;
-                    wc.m = 0.f;
-                    wc.a = 0;
-                    wc.b = 0;
-                }
+            // The root is the first batch.  Each round: opening tests, pushes,
+            // then the NEXT batch is popped and its cell loads issued before
+            // this round's entries and leaf bodies are staged, so the two
+            // memory round trips of a round overlap.
+            int top = 0;
+            bool vc = lane == 0;
+            WalkCell wc = load_cell(walk, 0u, vc);
+            bool more = true;
+            while (more) {
                 // opening test: squared distance from the centre of mass to the box
                 const double dxm = fmax(fmax(lox - wc.cx, 0.0), wc.cx - hix);
                 const double dym = fmax(fmax(loy - wc.cy, 0.0), wc.cy - hiy);
@@ -220,6 +229,24 @@ __global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__
                 const uint64_t O = __ballot(opened);
                 if (opened) S[top + __popcll(O & lanes_below)] = ((uint32_t)wc.a << 3) | (uint32_t)(wc.b - 1);
                 top += __popcll(O);
+                wave_lds_sync();
+
+                // pop the next batch (full batches only while the depth-first
+                // reserve is free) and start loading its cells
+                more = top > 0;
+                bool vcn = false;
+                WalkCell wcn;
+                if (more) {
+                    const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
+                    const int rr = lane / R, j = lane % R;
+                    uint32_t packed = 0;
+                    if (rr < nr) packed = S[top - 1 - rr];
+                    top -= nr;
+                    const int rlen = (int)(packed & 7u) + 1;
+                    vcn = rr < nr && j < rlen;
+                    wcn = load_cell(walk, (packed >> 3) + j, vcn);
+                }
+                wave_lds_sync();
 
                 // accepted cells: one entry each, at their centre of mass
                 const uint64_t A = __ballot(accept);
@@ -260,7 +287,8 @@ __global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__
                             flush<D>(L, len, xi, yi, zi, eps2, a);
                             len = 0;
                         }
-                        if (jj < my_cnt) L[len + my_off + jj] = rel_entry(bodies[my_begin + jj], rx, ry, rz);
+                        if (jj < my_cnt)
+                            L[len + my_off + jj] = body_entry(bodies, bodies32, my_begin + jj, rx, ry, rz);
                         len += tot;
                         np2p += tot;
                     }
@@ -276,13 +304,15 @@ __global__ void __launch_bounds__(256) k_walk_force(const WalkCell* __restrict__
                                 flush<D>(L, len, xi, yi, zi, eps2, a);
                                 len = 0;
                             }
-                            if (lane < m) L[len + lane] = rel_entry(bodies[bl + o + lane], rx, ry, rz);
+                            if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
                             len += m;
                         }
                         np2p += cl;
                     }
                 }
                 wave_lds_sync();
+                wc = wcn;
+                vc = vcn;
             }
             flush<D>(L, len, xi, yi, zi, eps2, a);
 
@@ -315,7 +345,8 @@ __global__ void k_reset_queue(uint32_t* queue) {
 
 }  // namespace
 
-hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uint32_t* perm,
+hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const float4* bodies32,
+                             const uint32_t* perm,
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
@@ -342,10 +373,10 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uin
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
     if (dim == 3)
-        hipLaunchKernelGGL(k_walk_force<3>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, gbeg, gcnt, queue,
+        hipLaunchKernelGGL(k_walk_force<3>, dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, queue,
                            lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
     else
-        hipLaunchKernelGGL(k_walk_force<2>, dim3(nb), dim3(256), 0, s, walk, bodies, perm, gbeg, gcnt, queue,
+        hipLaunchKernelGGL(k_walk_force<2>, dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, queue,
                            lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
     return hipGetLastError();
 }

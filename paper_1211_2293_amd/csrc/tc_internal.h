@@ -83,9 +83,9 @@ struct Layout {
     int64_t scan_tiles;
     size_t off_params, off_keys_a, off_keys_b, off_idx_a, off_idx_b, off_bodies, off_range,
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
-        off_walk, off_arrive, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
+        off_walk, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
-        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, total;
+        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_lvl_off, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
     int64_t gmax;        // bound on walk groups
     int64_t cscan_tiles; // scan tiles over cmax cells
@@ -103,20 +103,21 @@ hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint
                        int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
                        int64_t tiles, hipStream_t s);
 hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
-                         int dim, int f64, Body* bodies, hipStream_t s);
+                         int dim, int f64, Body* bodies, float4* bodies32, hipStream_t s);
 hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
-                           uint32_t* arrive, int64_t cmax, DevParams* prm, hipStream_t s);
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, const DevParams* prm, uint64_t* keys_a,
+                           int64_t cmax, DevParams* prm, hipStream_t s);
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
                               uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, hipStream_t s);
+                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, uint32_t* lvl_off,
+                              hipStream_t s);
 hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
                          int64_t scan_tiles, int32_t* gbeg, int32_t* gcnt, int64_t gmax, DevParams* prm,
                          hipStream_t s);
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
-                          const uint32_t* pre2bfs, Moments* mom, WalkCell* walk, uint32_t* arrive,
-                          const DevParams* prm, hipStream_t s);
+                          const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
+                          Moments* mom, WalkCell* walk, hipStream_t s);
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
                       const uint32_t* pre2bfs, WalkCell* walk, const DevParams* prm, hipStream_t s);
 hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t cmax,
@@ -124,7 +125,8 @@ hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t
                          int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
                          int32_t* leaf, double* M, double* com, double* Q, hipStream_t s);
 // force.hip
-hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const uint32_t* perm,
+hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const float4* bodies32,
+                             const uint32_t* perm,
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
