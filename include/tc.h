@@ -124,6 +124,77 @@ int tc_status(tc_ctx *ctx);
 /* Static message for a status code (TC_EHIP includes the last HIP error). */
 const char *tc_strerror(int code);
 
+/* ---- learned closure ---------------------------------------------------
+ * An extension of the paper's monopole cells (§3.1): for a body x and an
+ * accepted cell (centre of mass C, mass M, side s, traceless quadrupole Q)
+ * a network predicts the normalised residual
+ *     y = (a_exact - a_mono) |x - C|^2 / M      (G = 1)
+ * between the exact sum over the cell's bodies and its monopole, from the
+ * features f = [(x - C)/s (3), Q/(M s^2) (6: xx yy zz xy xz yz),
+ * ln(M / mbar) (1)], mbar = total mass / n.  The network is 10-64-64-3
+ * with GELU (erf form), BF16 matrix-core products with FP32 accumulation and
+ * FP32 master weights.  Parameters (canonical order, 5059 FP32): W1 [10][64],
+ * b1 [64], W2 [64][64], b2 [64], W3 [64][3], b3 [3]; y = gelu(gelu(f W1 +
+ * b1) W2 + b2) W3 + b3.  3D only. */
+
+#define TC_MLP_NPARAM 5059
+#define TC_MLP_BATCH_MAX 65536
+#define TC_RESID_MAX_TARGETS 65536
+
+/* Training pairs for nt target bodies (device int32 original indices,
+ * 1 <= nt <= TC_RESID_MAX_TARGETS): each target walks alone (its box is the
+ * body itself) at theta (0 < theta <= 1), and every accepted cell gives one
+ * pair: feat [.][10] FP32, y [.][3] FP32 (exact sum in FP64), cell [.] the
+ * cell's pre-order index.  Pairs are in target order.  At most cap pairs are
+ * written (device buffers); *n_out (host) receives the total.  Prepares the
+ * opening radii for theta as tc_walk does.  Synchronises.  Requires
+ * tc_moments. */
+int tc_residuals(tc_ctx *ctx, double theta, double eps, const int32_t *targets, int nt, float *feat,
+                 float *y, int32_t *cell, int64_t cap, int64_t *n_out);
+
+/* Load network parameters (device, TC_MLP_NPARAM FP32, canonical order) and
+ * reset the Adam state.  Requires a workspace and tc_build. */
+int tc_mlp_load(tc_ctx *ctx, const float *params);
+
+/* Copy the FP32 master parameters out (device buffer).  Requires tc_mlp_load. */
+int tc_mlp_get(tc_ctx *ctx, float *params);
+
+/* Network outputs yhat [nb][3] (device) for feature rows feat[idx[k]]
+ * (idx: device int32 [nb], or NULL for rows 0..nb-1). */
+int tc_mlp_forward(tc_ctx *ctx, const float *feat, const int32_t *idx, int64_t nb, float *yhat);
+
+/* One training step on the batch feat[idx[k]], y[idx[k]] (k < nb <=
+ * TC_MLP_BATCH_MAX; idx may be NULL): forward, mean squared error over the
+ * nb x 3 outputs, backward, gradients summed in a fixed order, one Adam
+ * step (beta 0.9/0.999, epsilon 1e-8) with learning rate lr >= 0.  *loss
+ * (host, may be NULL: then nothing synchronises) gets the batch loss before
+ * the update, grad (device, may be NULL) the gradient in canonical order. */
+int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, const int32_t *idx, int64_t nb, double lr,
+                float *loss, float *grad);
+
+/* Forces with the learned closure (3D only).  The walk of tc_forces with
+ * two opening parameters theta_p < theta_l <= 1 (the opening test of §3.1
+ * evaluated with each): a cell accepted at theta_l and at theta_p is a
+ * monopole entry; a cell accepted at theta_l but opened at theta_p is a
+ * learned cell.  For a learned cell the network loaded by tc_mlp_load
+ * predicts, for each body of the walk group, the normalised residual yhat
+ * (features as tc_residuals); if max |yhat| over the group exceeds tau the
+ * cell falls back to the plain walk of its subtree at theta_p, otherwise it
+ * is a monopole entry plus G M yhat / |x - C|^2 per body (no softening).
+ * tau = 0 gives exactly the plain walk at theta_p; tau = +inf gives the
+ * plain walk at theta_l plus every correction.  The potential keeps the
+ * monopoles.  acc/pot as tc_forces (device, FP32, either may be NULL).
+ * Requires tc_moments and tc_mlp_load; TC_EINVAL for parameters outside
+ * the ranges above or dim != 3.  Synchronises once (root mass). */
+int tc_forces_learned(tc_ctx *ctx, double G, double eps, double theta_l, double theta_p, double tau,
+                      void *acc, void *pot);
+
+/* Per walk group, the learned cells of the last tc_forces_learned that
+ * were kept (learned) and that fell back (fallback): device int64 buffers
+ * of tc_num_groups() entries, either may be NULL.  Requires
+ * tc_forces_learned (after a plain tc_forces the contents are stale). */
+int tc_get_learned_counts(tc_ctx *ctx, int64_t *learned, int64_t *fallback);
+
 /* ---- inspection (tests and benchmarks) -------------------------------- */
 
 /* Number of cells of the current tree.  Synchronises.  Requires tc_build. */

@@ -64,6 +64,12 @@ def lib():
         L.orc_walk_counts_ranges.restype = None
         L.orc_tree_forces_ranges.argtypes = [P, dbl, dbl, dbl, i64, P, P, P, P]
         L.orc_tree_forces_ranges.restype = None
+        L.orc_residuals.argtypes = [P, dbl, dbl, i64, P, i64, P, P, P, P, P]
+        L.orc_residuals.restype = i64
+        L.orc_sorted_positions.argtypes = [P, i64, P, P]
+        L.orc_sorted_positions.restype = None
+        L.orc_walk_items_range.argtypes = [P, dbl, i64, i64, P, i64]
+        L.orc_walk_items_range.restype = i64
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         _LIB = L
@@ -229,6 +235,38 @@ class Tree:
         `cluster` bodies."""
         gb, gc = self.groups(gs, cluster)
         return self.forces_groups(theta, gb, gc, G=G, eps=eps)
+
+    def walk_items_range(self, theta, b, e):
+        cap = 1 << 16
+        while True:
+            buf = np.zeros(cap, np.int32)
+            k = int(lib().orc_walk_items_range(self._h, float(theta), int(b), int(e), _p(buf), cap))
+            if k <= cap:
+                return buf[:k]
+            cap = k
+
+    def sorted_positions(self, orig):
+        orig = np.ascontiguousarray(orig, np.int64)
+        pos = np.zeros(len(orig), np.int64)
+        lib().orc_sorted_positions(self._h, len(orig), _p(orig), _p(pos))
+        return pos
+
+    def residuals(self, theta, eps, targets):
+        """Training pairs of the learned closure for the given original
+        body indices: dict with feat [P][10] (FP32), y [P][3] (FP64), target
+        (index into targets), cell (pre-order index), count per target."""
+        tpos = self.sorted_positions(targets)
+        nt = len(tpos)
+        cnt = np.zeros(nt, np.int64)
+        total = int(lib().orc_residuals(self._h, float(theta), float(eps), nt, _p(tpos), 0, None,
+                                        None, None, None, _p(cnt)))
+        feat = np.zeros((total, 10), np.float32)
+        y = np.zeros((total, 3))
+        tg = np.zeros(total, np.int64)
+        cl = np.zeros(total, np.int32)
+        lib().orc_residuals(self._h, float(theta), float(eps), nt, _p(tpos), total, _p(feat), _p(y),
+                            _p(tg), _p(cl), _p(cnt))
+        return {"feat": feat, "y": y, "target": tg, "cell": cl, "count": cnt}
 
     def forces(self, theta, G=1.0, eps=1e-3, gs=64, groups=None):
         """FP64 treecode accelerations and potentials in original order.

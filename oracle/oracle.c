@@ -588,6 +588,23 @@ static void group_forces(const orc_tree *t, const double *rc, int64_t b, int64_t
     free(w.items);
 }
 
+/* The terminal items of the walk of sorted bodies [b, e), in walk order
+ * (c >= 0 accepted cell, -1-c opened leaf c).  Returns the item count;
+ * writes at most cap items. */
+int64_t orc_walk_items_range(const orc_tree *t, double theta, int64_t b, int64_t e, int32_t *out, int64_t cap)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+    walk_out w = {0};
+    w.items = malloc(256 * sizeof(int32_t));
+    w.cap = 256;
+    walk_range(t, rc, b, e, &w);
+    for (int64_t k = 0; k < w.nitems && k < cap; ++k) out[k] = w.items[k];
+    free(w.items);
+    free(rc);
+    return w.nitems;
+}
+
 /* Treecode forces for the bodies of the selected groups of gs consecutive
  * sorted bodies (all groups when groups == NULL).  acc [n][dim] and pot [n]
  * are in original body order; only the selected groups' bodies are
@@ -617,6 +634,94 @@ void orc_tree_forces_ranges(const orc_tree *t, double theta, double G, double ep
     for (int64_t k = 0; k < ng; ++k)
         group_forces(t, rc, gbeg[k], gbeg[k] + gcnt[k], G, eps * eps, acc, pot);
     free(rc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned closure: training pairs (features and normalised residuals).      */
+/* ------------------------------------------------------------------------ */
+
+/* For each target (a sorted body position p) the walk of the one-body group
+ * [p, p+1) at theta gives the accepted cells.  For each accepted cell c with
+ * centre of mass C, mass M, side s, traceless quadrupole Q:
+ *   features  (x - C)/s (3), Q/(M s^2) (6: xx yy zz xy xz yz), ln(M / mbar)
+ *             with mbar = (total mass)/n,
+ *   residual  y = (a_exact - a_mono) |x - C|^2 / M, where a_exact is the
+ *             softened sum over the cell's bodies and a_mono = M (C - x) /
+ *             (|C - x|^2 + eps^2)^{3/2} (G = 1).
+ * Pairs are in target order, then in walk order.  Writes at most cap pairs
+ * (feat [cap][10] FP32, y [cap][3] FP64, target index and cell), count[t]
+ * per target; returns the total number of pairs.  3D only. */
+int64_t orc_residuals(const orc_tree *t, double theta, double eps, int64_t nt, const int64_t *tpos,
+                      int64_t cap, float *feat, double *y, int64_t *tgt, int32_t *cell, int64_t *count)
+{
+    if (t->dim != 3) return -1;
+    const double e2 = eps * eps;
+    const double mbar = t->M[0] / (double)t->n;
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+    int64_t *off = malloc((nt + 1) * sizeof(int64_t));
+    walk_out *ws = calloc(nt, sizeof(walk_out));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nt; ++k) {
+        ws[k].items = malloc(256 * sizeof(int32_t));
+        ws[k].cap = 256;
+        walk_range(t, rc, tpos[k], tpos[k] + 1, &ws[k]);
+    }
+    off[0] = 0;
+    for (int64_t k = 0; k < nt; ++k) {
+        count[k] = ws[k].m2p;
+        off[k + 1] = off[k] + ws[k].m2p;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t p = tpos[k];
+        const double *x = t->x + p * 3;
+        int64_t o = off[k];
+        for (int64_t it = 0; it < ws[k].nitems; ++it) {
+            const int32_t c = ws[k].items[it];
+            if (c < 0) continue;
+            if (o < cap) {
+                const double *C = t->com + (int64_t)c * 3;
+                const double M = t->M[c];
+                const double s = ldexp(t->size, -t->level[c]);
+                double ex[3] = {0, 0, 0};
+                for (int64_t j = t->begin[c]; j < t->begin[c] + t->count[c]; ++j) {
+                    double d[3], r2 = e2;
+                    for (int q = 0; q < 3; ++q) { d[q] = t->x[j * 3 + q] - x[q]; r2 += d[q] * d[q]; }
+                    const double inv = 1.0 / sqrt(r2);
+                    const double w3 = t->m[j] * inv * inv * inv;
+                    for (int q = 0; q < 3; ++q) ex[q] += w3 * d[q];
+                }
+                double dc[3], d2 = 0.0;
+                for (int q = 0; q < 3; ++q) { dc[q] = C[q] - x[q]; d2 += dc[q] * dc[q]; }
+                const double inv = 1.0 / sqrt(d2 + e2);
+                const double w3 = M * inv * inv * inv;
+                for (int q = 0; q < 3; ++q) y[o * 3 + q] = (ex[q] - w3 * dc[q]) * d2 / M;
+                for (int q = 0; q < 3; ++q) feat[o * 10 + q] = (float)((x[q] - C[q]) / s);
+                const double qs = M * s * s;
+                for (int q = 0; q < 6; ++q) feat[o * 10 + 3 + q] = (float)(t->Q[(int64_t)c * 6 + q] / qs);
+                feat[o * 10 + 9] = (float)log(M / mbar);
+                tgt[o] = k;
+                cell[o] = c;
+            }
+            ++o;
+        }
+        free(ws[k].items);
+    }
+    const int64_t total = off[nt];
+    free(ws);
+    free(off);
+    free(rc);
+    return total;
+}
+
+/* Sorted position of each of the given original body indices. */
+void orc_sorted_positions(const orc_tree *t, int64_t k, const int64_t *orig, int64_t *pos)
+{
+    int64_t *inv = malloc(t->n * sizeof(int64_t));
+    for (int64_t i = 0; i < t->n; ++i) inv[t->perm[i]] = i;
+    for (int64_t j = 0; j < k; ++j) pos[j] = inv[orig[j]];
+    free(inv);
 }
 
 int orc_num_threads(void)

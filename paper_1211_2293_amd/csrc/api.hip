@@ -5,6 +5,7 @@
 // move the bodies).
 #include "tc.h"
 #include "tc_internal.h"
+#include "closure.h"
 
 #include <math.h>
 #include <stdio.h>
@@ -85,8 +86,16 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_gcnt = take(4 * (size_t)l.gmax);
     l.off_queue = take(4 * 2 * kXcd);
     l.off_lvl_off = take(4 * 64);
+    l.off_inv_perm = take(4 * (size_t)n);
+    l.off_rcount = take(4 * (size_t)kResidMaxTargets);
+    l.off_roffs = take(4 * (size_t)(kResidMaxTargets + 1));
+    l.off_rscan_part = take(4 * (size_t)((kResidMaxTargets + kScanTile - 1) / kScanTile));
+    l.off_mlp = take(sizeof(MlpState));
+    l.off_rcp2 = take(8 * (size_t)l.cmax);
     l.off_m2p = take(8 * (size_t)l.gmax);
     l.off_p2p = take(8 * (size_t)l.gmax);
+    l.off_nlearn = take(8 * (size_t)l.gmax);
+    l.off_nfall = take(8 * (size_t)l.gmax);
     l.total = off;
     return l;
 }
@@ -111,6 +120,8 @@ struct tc_ctx {
     double t_total_ms = 0.0;
     int64_t t_launches = 0;
     hipError_t last_hip = hipSuccess;
+    int mlp_step = 0;          // Adam steps since the last tc_mlp_load
+    bool mlp_loaded = false;
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -138,7 +149,7 @@ bool valid_sizes(int64_t n, int dim, int leaf_cap) {
     if (dim != 2 && dim != 3) return false;
     if (leaf_cap < 1 || leaf_cap > TC_MAX_LEAF_CAP) return false;
     const int64_t cmax = (int64_t)levels_for(dim) * (n / (leaf_cap + 1)) + n + 1;
-    return cmax < ((int64_t)1 << 29);   // level-order indices are packed into 29 bits
+    return cmax < ((int64_t)1 << 28);   // level-order indices are packed into 28 bits
 }
 
 hipEvent_t pooled_event(tc_ctx* ctx) {
@@ -204,7 +215,7 @@ int do_moments(tc_ctx* ctx) {
 int do_walk(tc_ctx* ctx, double theta) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta, l.cmax,
-                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), ctx->prm(),
+                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), nullptr, ctx->prm(),
                            ctx->stream));
     ctx->theta = theta;
     ctx->state = kWalked;
@@ -369,6 +380,135 @@ const char* tc_strerror(int code) {
         case TC_ENONFINITE: return "non-finite position or mass, or non-positive mass";
         default: return "unknown status";
     }
+}
+
+/* ---- learned closure ---------------------------------------------------- */
+
+int tc_residuals(tc_ctx* ctx, double theta, double eps, const int32_t* targets, int nt, float* feat,
+                 float* y, int32_t* cell, int64_t cap, int64_t* n_out) {
+    if (!ctx || !targets || !n_out || nt < 1 || nt > kResidMaxTargets || cap < 0) return TC_EINVAL;
+    if (cap > 0 && (!feat || !y || !cell)) return TC_EINVAL;
+    if (!(theta > 0.0 && theta <= 1.0) || !(eps > 0.0) || !isfinite(eps)) return TC_EINVAL;
+    if (ctx->dim != 3) return TC_EINVAL;
+    if (ctx->state < kMoments) return TC_ESTATE;
+    int rc = do_walk(ctx, theta);
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    uint32_t* inv = ctx->at<uint32_t>(l.off_inv_perm);
+    uint32_t* cnt = ctx->at<uint32_t>(l.off_rcount);
+    uint32_t* off = ctx->at<uint32_t>(l.off_roffs);
+    TC_HIP(ctx, launch_inverse_perm(ctx->at<uint32_t>(l.off_idx_a), ctx->n, inv, s));
+    for (int pass = 0; pass < 2; ++pass) {
+        TC_HIP(ctx, launch_residuals(pass == 1, ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
+                                     ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom),
+                                     ctx->at<uint32_t>(l.off_lvl_idx_b), inv, ctx->prm(), ctx->n, targets, nt,
+                                     eps * eps, cnt, off, cap, feat, y, cell, s));
+        if (pass == 0)
+            TC_HIP(ctx, launch_scan_u32(cnt, nt, off, ctx->at<uint32_t>(l.off_rscan_part),
+                                        (nt + kScanTile - 1) / kScanTile, s));
+    }
+    uint32_t total = 0;
+    TC_HIP(ctx, hipMemcpyAsync(&total, off + nt, sizeof(total), hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    *n_out = total;
+    return TC_OK;
+}
+
+int tc_mlp_load(tc_ctx* ctx, const float* params) {
+    if (!ctx || !params || !aligned(params, 4)) return TC_EINVAL;
+    if (!ctx->ws || ctx->state < kBuilt) return TC_ESTATE;
+    TC_HIP(ctx, launch_mlp_load(ctx->at<MlpState>(ctx->lay.off_mlp), params, ctx->stream));
+    ctx->mlp_step = 0;
+    ctx->mlp_loaded = true;
+    return TC_OK;
+}
+
+int tc_mlp_get(tc_ctx* ctx, float* params) {
+    if (!ctx || !params || !aligned(params, 4)) return TC_EINVAL;
+    if (!ctx->mlp_loaded) return TC_ESTATE;
+    TC_HIP(ctx, launch_mlp_get(ctx->at<MlpState>(ctx->lay.off_mlp), params, ctx->stream));
+    return TC_OK;
+}
+
+int tc_mlp_forward(tc_ctx* ctx, const float* feat, const int32_t* idx, int64_t nb, float* yhat) {
+    if (!ctx || !feat || !yhat || nb < 1) return TC_EINVAL;
+    if (!ctx->mlp_loaded) return TC_ESTATE;
+    TC_HIP(ctx, launch_mlp_forward(ctx->at<MlpState>(ctx->lay.off_mlp), feat, idx, nb, yhat, ctx->stream));
+    return TC_OK;
+}
+
+int tc_mlp_step(tc_ctx* ctx, const float* feat, const float* y, const int32_t* idx, int64_t nb, double lr,
+                float* loss, float* grad) {
+    if (!ctx || !feat || !y || nb < 1 || nb > kMlpBatchMax || !(lr >= 0.0) || !isfinite(lr)) return TC_EINVAL;
+    if (!ctx->mlp_loaded) return TC_ESTATE;
+    MlpState* st = ctx->at<MlpState>(ctx->lay.off_mlp);
+    ctx->mlp_step += 1;
+    TC_HIP(ctx, launch_mlp_step(st, feat, y, idx, nb, (float)lr, ctx->mlp_step, grad, ctx->stream));
+    if (loss) {
+        TC_HIP(ctx, hipMemcpyAsync(loss, &st->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return TC_OK;
+}
+
+int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double theta_p, double tau, void* acc,
+                      void* pot) {
+    if (!ctx) return TC_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if (!(theta_l > 0.0 && theta_l <= 1.0) || !(theta_p >= 0.0 && theta_p < theta_l) || !(tau >= 0.0))
+        return TC_EINVAL;
+    if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
+    if (ctx->dim != 3) return TC_EINVAL;
+    if (ctx->state < kMoments || !ctx->mlp_loaded) return TC_ESTATE;
+    int rc = do_walk(ctx, theta_l);
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta_p, l.cmax,
+                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk),
+                           ctx->at<double>(l.off_rcp2), ctx->prm(), s));
+    // total mass (root) over n, for the log-mass feature
+    Moments root;
+    TC_HIP(ctx, hipMemcpyAsync(&root, ctx->at<Moments>(l.off_mom), sizeof(root), hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    const double mbar = root.M / (double)ctx->n;
+    const float tauf = isinf(tau) ? INFINITY : (float)tau;
+    TC_HIP(ctx, launch_walk_force_learned(
+                    ctx->at<WalkCell>(l.off_walk), ctx->at<double>(l.off_rcp2), ctx->at<Body>(l.off_bodies),
+                    ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr, ctx->at<Cell>(l.off_cells),
+                    ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_idx_a),
+                    ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt), l.gmax,
+                    ctx->at<uint32_t>(l.off_queue), ctx->at<MlpState>(l.off_mlp), ctx->leaf_cap, (float)G,
+                    (float)(eps * eps), tauf, mbar, ctx->prm(), ctx->at<float>(l.off_acc),
+                    ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p),
+                    ctx->at<int64_t>(l.off_nlearn), ctx->at<int64_t>(l.off_nfall), s));
+    ctx->G = G;
+    ctx->eps = eps;
+    ctx->state = kForced;
+    if (acc)
+        TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * 3,
+                                   hipMemcpyDeviceToDevice, s));
+    if (pot)
+        TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n,
+                                   hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+int tc_get_learned_counts(tc_ctx* ctx, int64_t* learned, int64_t* fallback) {
+    if (!ctx) return TC_EINVAL;
+    if (ctx->state < kForced) return TC_ESTATE;
+    int64_t ng = 0;
+    int rc = tc_num_groups(ctx, &ng);
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    if (learned)
+        TC_HIP(ctx, hipMemcpyAsync(learned, ctx->at<int64_t>(l.off_nlearn), 8 * (size_t)ng,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (fallback)
+        TC_HIP(ctx, hipMemcpyAsync(fallback, ctx->at<int64_t>(l.off_nfall), 8 * (size_t)ng,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
 }
 
 int tc_num_cells(tc_ctx* ctx, int64_t* ncells) {

@@ -594,7 +594,7 @@ __global__ void k_level_offsets(const uint32_t* __restrict__ digit_tot, int L, u
 template <int D>
 __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
                                              double theta, const uint32_t* __restrict__ pre2bfs,
-                                             WalkCell* __restrict__ walk,
+                                             WalkCell* __restrict__ walk, double* __restrict__ rc_out,
                                              const DevParams* __restrict__ prm, int64_t cmax) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
@@ -602,7 +602,8 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
          k += (int64_t)gridDim.x * blockDim.x) {
         if (theta == 0.0) {
-            walk[pre2bfs[k]].rcrit2 = INFINITY;
+            if (rc_out) rc_out[pre2bfs[k]] = INFINITY;
+            else walk[pre2bfs[k]].rcrit2 = INFINITY;
             continue;
         }
         const Cell c = cells[k];
@@ -623,7 +624,8 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
         double d2 = dd[0] * dd[0] + dd[1] * dd[1];
         if (D == 3) d2 = d2 + dd[2] * dd[2];
         const double r = s / theta + sqrt(d2);
-        walk[pre2bfs[k]].rcrit2 = r * r;
+        if (rc_out) rc_out[pre2bfs[k]] = r * r;
+        else walk[pre2bfs[k]].rcrit2 = r * r;
     }
 }
 
@@ -795,6 +797,14 @@ hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm
     return hipGetLastError();
 }
 
+hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)part, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
@@ -861,10 +871,11 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
 }
 
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
-                      const uint32_t* pre2bfs, WalkCell* walk, const DevParams* prm, hipStream_t s) {
+                      const uint32_t* pre2bfs, WalkCell* walk, double* rc_out, const DevParams* prm,
+                      hipStream_t s) {
     const unsigned nb = grid_for(cmax);
-    if (dim == 3) hipLaunchKernelGGL(k_mac<3>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, prm, cmax);
-    else hipLaunchKernelGGL(k_mac<2>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, prm, cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_mac<3>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, rc_out, prm, cmax);
+    else hipLaunchKernelGGL(k_mac<2>, dim3(nb), dim3(256), 0, s, cells, mom, theta, pre2bfs, walk, rc_out, prm, cmax);
     return hipGetLastError();
 }
 

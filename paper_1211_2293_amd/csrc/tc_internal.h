@@ -85,7 +85,8 @@ struct Layout {
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
         off_walk, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
-        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_lvl_off, total;
+        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
+        off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
     int64_t gmax;        // bound on walk groups
     int64_t cscan_tiles; // scan tiles over cmax cells
@@ -119,7 +120,8 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
                           Moments* mom, WalkCell* walk, hipStream_t s);
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
-                      const uint32_t* pre2bfs, WalkCell* walk, const DevParams* prm, hipStream_t s);
+                      const uint32_t* pre2bfs, WalkCell* walk, double* rc_out, const DevParams* prm,
+                      hipStream_t s);
 hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t cmax,
                          const DevParams* prm, int32_t* level, uint64_t* prefix, int32_t* begin,
                          int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
@@ -131,6 +133,30 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
                              int64_t* p2p, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
+                           hipStream_t s);
+// closure.hip
+struct MlpState;
+hipError_t launch_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t s);
+hipError_t launch_residuals(bool write, const WalkCell* walk, const Body* bodies, const Cell* cells,
+                            const Moments* mom, const uint32_t* bfs2pre, const uint32_t* inv_perm,
+                            const DevParams* prm, int64_t n, const int32_t* targets, int nt, double eps2,
+                            uint32_t* counts, const uint32_t* offs, int64_t cap, float* feat, float* y,
+                            int32_t* cell_out, hipStream_t s);
+hipError_t launch_mlp_load(MlpState* st, const float* params, hipStream_t s);
+hipError_t launch_mlp_get(const MlpState* st, float* params, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpState* st, const float* feat, const int32_t* idx, int64_t nb, float* yhat,
+                              hipStream_t s);
+hipError_t launch_mlp_step(MlpState* st, const float* feat, const float* y, const int32_t* idx, int64_t nb, float lr,
+                           int step, float* grad_out, hipStream_t s);
+// learned.hip
+hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, const Body* bodies,
+                                     const float4* bodies32, const Cell* cells, const Moments* mom,
+                                     const uint32_t* bfs2pre, const uint32_t* perm, const int32_t* gbeg,
+                                     const int32_t* gcnt, int64_t gmax, uint32_t* queue, const MlpState* st,
+                                     int leaf_cap, float G, float eps2, float tau, double mbar,
+                                     const DevParams* prm, float* acc, float* pot, int64_t* m2p, int64_t* p2p,
+                                     int64_t* learned, int64_t* fallback, hipStream_t s);
 // step.hip
 hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,
                              double dt, hipStream_t s);

@@ -1,0 +1,125 @@
+// Device helpers shared by the walk kernels (plain and learned).
+// Internal to libtc.
+#pragma once
+
+#include "tc_internal.h"
+
+#include <math.h>
+
+namespace tc {
+namespace walk {
+
+constexpr int kListCap = 256;     // LDS list entries per wave (16 B each)
+constexpr int kStackCap = 320;    // LDS range-stack entries per wave (4 B each)
+
+// Order LDS accesses of the lanes of one wave (a wave's LDS operations are
+// performed in program order; this keeps the compiler from reordering them).
+static __device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+static __device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+static __device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// A value equal in every lane, made visibly uniform (scalar registers).
+static __device__ __forceinline__ double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Neumaier compensated accumulation of x into (s, c).
+static __device__ __forceinline__ void comp_add(float& s, float& c, float x) {
+    const float t = s + x;
+    if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+struct Acc {
+    float sx, sy, sz, sp, cx, cy, cz, cp;
+};
+
+// Sum the first `cnt` list entries for this lane's body.  cnt is padded up
+// to a multiple of 8 with massless entries, which add exactly zero.
+template <int D>
+static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, float zi, float eps2, Acc& a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int padded = (cnt + 7) & ~7;
+    for (int j = cnt + lane; j < padded; j += kWave) L[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_lds_sync();
+    for (int e = 0; e < padded; e += kWave) {
+        const int lim = min(kWave, padded - e);
+        float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+        for (int k = 0; k < lim; k += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float4 p = L[e + k + u];
+                const float dx = p.x - xi, dy = p.y - yi;
+                float r2, dz = 0.f;
+                if (D == 3) {
+                    dz = p.z - zi;
+                    r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                } else {
+                    r2 = fmaf(dx, dx, fmaf(dy, dy, eps2));
+                }
+                const float s = __builtin_amdgcn_rsqf(r2);
+                const float ms = p.w * s;
+                const float s2 = s * s;
+                const float ms3 = ms * s2;
+                ap -= ms;
+                ax = fmaf(ms3, dx, ax);
+                ay = fmaf(ms3, dy, ay);
+                if (D == 3) az = fmaf(ms3, dz, az);
+            }
+        }
+        comp_add(a.sx, a.cx, ax);
+        comp_add(a.sy, a.cy, ay);
+        if (D == 3) comp_add(a.sz, a.cz, az);
+        comp_add(a.sp, a.cp, ap);
+    }
+    wave_lds_sync();
+}
+
+// List entry of a body relative to the group origin.  FP32 inputs keep a
+// 16-byte FP32 copy of the sorted bodies (exact: it is the input itself);
+// the FP64 difference is the same either way.
+static __device__ __forceinline__ float4 body_entry(const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
+                                             int64_t j, double rx, double ry, double rz) {
+    if (bodies32) {
+        const float4 b = bodies32[j];
+        return make_float4((float)((double)b.x - rx), (float)((double)b.y - ry), (float)((double)b.z - rz), b.w);
+    }
+    const Body b = bodies[j];
+    return make_float4((float)(b.x - rx), (float)(b.y - ry), (float)(b.z - rz), (float)b.m);
+}
+
+static __device__ __forceinline__ WalkCell load_cell(const WalkCell* __restrict__ walk, uint32_t c, bool v) {
+    WalkCell wc;
+    if (v) {
+        wc = walk[c];
+    } else {
+        wc.cx = wc.cy = wc.cz = 0.0;
+        wc.rcrit2 = INFINITY;
+        wc.m = 0.f;
+        wc.a = 0;
+        wc.b = 0;
+        wc.pad = 0;
+    }
+    return wc;
+}
+
+
+}  // namespace walk
+}  // namespace tc

@@ -21,6 +21,7 @@ TC_OK, TC_EINVAL, TC_EWORKSPACE, TC_ESTATE, TC_EHIP, TC_ENONFINITE = 0, -1, -2, 
 TC_F32, TC_F64 = 0, 1
 GROUP = 64
 CLUSTER = 1024
+MLP_NPARAM = 5059
 
 _LIB = None
 
@@ -63,6 +64,13 @@ def lib():
         "tc_get_groups": (i32, [P, P, P]),
         "tc_set_timing": (i32, [P, i32]),
         "tc_get_timing": (i32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tc_forces_learned": (i32, [P, dbl, dbl, dbl, dbl, dbl, P, P]),
+        "tc_get_learned_counts": (i32, [P, P, P]),
+        "tc_residuals": (i32, [P, dbl, dbl, P, i32, P, P, P, i64, C.POINTER(C.c_int64)]),
+        "tc_mlp_load": (i32, [P, P]),
+        "tc_mlp_get": (i32, [P, P]),
+        "tc_mlp_forward": (i32, [P, P, P, i64, P]),
+        "tc_mlp_step": (i32, [P, P, P, P, i64, dbl, C.POINTER(C.c_float), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -261,6 +269,80 @@ class Treecode:
         _, gc = self.groups()
         per = (m2p + p2p).cpu().numpy()
         return int((per * gc.cpu().numpy().astype(np.int64)).sum())
+
+    # -- learned closure -------------------------------------------------
+    def residuals(self, theta: float, eps: float, targets: torch.Tensor, cap: int | None = None):
+        """Training pairs for the given original body indices (int32 CUDA
+        tensor): (feat [P][10], y [P][3], cell [P]) as CUDA tensors."""
+        self._dev(targets, "targets")
+        if targets.dtype != torch.int32:
+            raise TypeError("targets must be int32")
+        dev = self.stream.device
+        total = C.c_int64()
+        if cap is None:
+            _check(lib().tc_residuals(self._h, float(theta), float(eps), _ptr(targets), len(targets),
+                                      None, None, None, 0, C.byref(total)))
+            cap = int(total.value)
+        feat = torch.empty((max(cap, 1), 10), dtype=torch.float32, device=dev)
+        y = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        cell = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        _check(lib().tc_residuals(self._h, float(theta), float(eps), _ptr(targets), len(targets),
+                                  _ptr(feat), _ptr(y), _ptr(cell), cap, C.byref(total)))
+        k = min(cap, int(total.value))
+        return feat[:k], y[:k], cell[:k]
+
+    def forces_learned(self, theta_l: float, theta_p: float, tau: float, G: float = 1.0, eps: float = 1e-2,
+                       acc=None, pot=None, want_pot=True):
+        """Forces with the learned closure (network from mlp_load)."""
+        if acc is None:
+            acc = torch.empty((self.n, self.dim), dtype=torch.float32, device=self.stream.device)
+        if pot is None and want_pot:
+            pot = torch.empty(self.n, dtype=torch.float32, device=self.stream.device)
+        for t, nm in ((acc, "acc"), (pot, "pot")):
+            if t is not None:
+                self._dev(t, nm)
+                if t.dtype != torch.float32:
+                    raise TypeError(f"{nm} must be float32")
+        _check(lib().tc_forces_learned(self._h, float(G), float(eps), float(theta_l), float(theta_p),
+                                       float(tau), _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def learned_counts(self):
+        """Per walk group: (learned cells kept, learned cells that fell back)."""
+        G = self.num_groups()
+        dev = self.stream.device
+        kept = torch.empty(G, dtype=torch.int64, device=dev)
+        fell = torch.empty(G, dtype=torch.int64, device=dev)
+        _check(lib().tc_get_learned_counts(self._h, _ptr(kept), _ptr(fell)))
+        return kept, fell
+
+    def mlp_load(self, params: torch.Tensor):
+        self._dev(params, "params")
+        if params.dtype != torch.float32 or params.numel() != MLP_NPARAM:
+            raise TypeError("params must be float32 with 5059 entries")
+        self._mlp_params = params
+        _check(lib().tc_mlp_load(self._h, _ptr(params)))
+
+    def mlp_get(self) -> torch.Tensor:
+        out = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.stream.device)
+        _check(lib().tc_mlp_get(self._h, _ptr(out)))
+        return out
+
+    def mlp_forward(self, feat: torch.Tensor, idx: torch.Tensor | None = None) -> torch.Tensor:
+        self._dev(feat, "feat")
+        nb = feat.shape[0] if idx is None else idx.shape[0]
+        out = torch.empty((nb, 3), dtype=torch.float32, device=self.stream.device)
+        _check(lib().tc_mlp_forward(self._h, _ptr(feat), _ptr(idx), nb, _ptr(out)))
+        return out
+
+    def mlp_step(self, feat, y, idx=None, lr=1e-3, want_loss=True, grad=None):
+        self._dev(feat, "feat")
+        self._dev(y, "y")
+        nb = feat.shape[0] if idx is None else idx.shape[0]
+        loss = C.c_float(0.0)
+        _check(lib().tc_mlp_step(self._h, _ptr(feat), _ptr(y), _ptr(idx), nb, float(lr),
+                                 C.byref(loss) if want_loss else None, _ptr(grad)))
+        return float(loss.value) if want_loss else None
 
     def set_timing(self, on: bool):
         _check(lib().tc_set_timing(self._h, int(bool(on))))
