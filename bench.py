@@ -8,6 +8,18 @@ step holds exactly one force evaluation, so force-evals/s = steps/s.
 Default workload: 3D Plummer sphere, N = 1,048,576, a = 1, M = 1, G = 1,
 eps = 1e-2, theta = 0.5, leaf_cap = 16, dt = 1e-3; FP32 state and forces.
 
+After the timed steps (outside the timed region):
+  * the relative force error E = sqrt(sum |a - a_ref|^2 / sum |a_ref|^2) of
+    a fresh evaluation against the FP64 direct sum (computed on the GPU by
+    tc_direct) on 8,192 seeded sample bodies;
+  * for 3D workloads, the learned-vs-plain study on the initial positions:
+    plain evaluations over a theta sweep (time per evaluation and E), the
+    closure network trained on residuals generated at theta = 0.9 for 4,096
+    training and 1,024 validation targets, then learned evaluations at
+    theta_L = 0.8 over theta_P = 0.5, and the plain evaluation rate at the
+    learned E interpolated from the sweep;
+  * the CPU oracle timed on whole force evaluations of the same workload.
+
 Prints ONE JSON line on stdout.  Extra progress goes to stderr.
 """
 from __future__ import annotations
@@ -60,31 +72,149 @@ def traffic_from_profile(per_launch_interactions: int):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, sample_groups: int):
-    """The FP64 oracle timed on this host: full tree build plus the walk and
-    forces of a seeded sample of groups, scaled to one force evaluation."""
+def cpu_baseline(w, theta: float, min_seconds: float):
+    """The FP64 oracle timed on this host: whole force evaluations of the
+    same workload (tree build, walk groups, walk and forces of every body),
+    repeated until min_seconds have passed."""
     import oracle
     n = w.n
-    t0 = time.perf_counter()
-    tree = oracle.Tree(w.pos, w.mass, w.leaf_cap)
-    t_build = time.perf_counter() - t0
-    G = (n + 63) // 64
-    rng = np.random.default_rng(1234)
-    k = min(sample_groups, G)
-    sel = np.sort(rng.choice(G, size=k, replace=False))
-    t1 = time.perf_counter()
-    tree.forces(w.theta, G=w.G, eps=w.eps, gs=64, groups=sel)
-    t_force = time.perf_counter() - t1
-    t_eval = t_build + t_force * (G / k)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        tree = oracle.Tree(w.pos, w.mass, w.leaf_cap)
+        tree.walk_forces(theta, G=w.G, eps=w.eps)
+        times.append(time.perf_counter() - t0)
+        del tree
+        if time.perf_counter() - t_start >= min_seconds or len(times) >= 50:
+            break
+    t_eval = float(np.median(times))
     return {
         "value": 1.0 / t_eval,
         "unit": "force-evals/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 oracle: full tree build of all {n} bodies ({t_build:.2f} s) + walk and "
-                   f"forces of {k} of {G} seeded 64-body groups ({t_force:.2f} s), scaled to one "
-                   f"force evaluation ({t_eval:.2f} s)"),
+        "sample": (f"FP64 oracle, {len(times)} whole force evaluation(s) of all {n} bodies (build + walk + "
+                   f"forces, theta={theta}, OpenMP over walk groups), median {t_eval:.2f} s each"),
     }
+
+
+def rel_error(acc, ref):
+    """E = sqrt(sum |a - a_ref|^2 / sum |a_ref|^2) with the median and 99th
+    percentile of the per-body |a - a_ref| / |a_ref|."""
+    acc = np.asarray(acc, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = np.linalg.norm(acc - ref, axis=1)
+    r = np.linalg.norm(ref, axis=1)
+    per = d / np.where(r > 0, r, 1.0)
+    return {"E": float(np.sqrt((d * d).sum() / (r * r).sum())), "median": float(np.median(per)),
+            "p99": float(np.percentile(per, 99))}
+
+
+def time_evals(fn, reps=5, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)) * 1e3
+
+
+def interp_ms_at_error(sweep, E):
+    """Plain ms/eval at error E, piecewise linear in (log E, log ms) over
+    the theta sweep; None outside the swept range."""
+    pts = sorted((r["E"], r["ms_per_eval"]) for r in sweep)
+    for (e0, m0), (e1, m1) in zip(pts, pts[1:]):
+        if e0 <= E <= e1 and e1 > e0:
+            f = (np.log(E) - np.log(e0)) / (np.log(e1) - np.log(e0))
+            return float(np.exp(np.log(m0) + f * (np.log(m1) - np.log(m0))))
+    return None
+
+
+def learned_study(w, args):
+    """Plain theta sweep vs the learned closure at matched error, on the
+    workload's initial positions; every timed evaluation includes the tree
+    build.  Errors are against the FP64 direct sum on the seeded sample."""
+    import torch
+
+    from paper_1211_2293_amd import closure, treecode, workloads
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(w.pos).to(dev)
+    mass = torch.from_numpy(w.mass).to(dev)
+    tc = treecode.Treecode(w.dim, leaf_cap=w.leaf_cap)
+    tc.build(pos, mass)
+    tc.moments()
+    sample = workloads.sample_indices(w.n, args.sample, seed=104)
+    ref, _ = tc.direct(torch.from_numpy(sample.astype(np.int32)).to(dev), G=w.G, eps=w.eps)
+    ref = ref.cpu().numpy()[:, :w.dim]
+
+    def plain(theta):
+        tc.build(pos, mass)
+        tc.moments()
+        tc.walk(theta)
+        return tc.forces(w.G, w.eps, want_pot=False)[0]
+
+    sweep = []
+    for th in args.sweep:
+        ms = time_evals(lambda: plain(th))
+        acc = plain(th).cpu().numpy()[sample]
+        e = rel_error(acc, ref)
+        inter = tc.interactions()
+        sweep.append({"theta": th, "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "E": e["E"],
+                      "p99": e["p99"], "interactions_per_body": inter / w.n})
+        log(f"  plain theta={th}: {ms:.3f} ms/eval, E={e['E']:.3e}, {inter / w.n:.0f} interactions/body")
+    out = {"sample": f"{len(sample)} seeded bodies (seed 104), FP64 direct sum on the GPU", "plain": sweep}
+    if w.dim != 3:
+        return out
+
+    t0 = time.perf_counter()
+    tr = workloads.sample_indices(w.n, args.train_targets, seed=203)
+    va = workloads.sample_indices(w.n, args.val_targets, seed=204)
+    f_tr, y_tr = closure.residual_pairs(tc, 0.9, w.eps, tr)
+    f_va, y_va = closure.residual_pairs(tc, 0.9, w.eps, va)
+    torch.cuda.synchronize()
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    stats = closure.train(tc, f_tr, y_tr, epochs=args.epochs, batch=4096, lr=args.lr, lr_final=args.lr / 10,
+                          val=(f_va, y_va), log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    stats.update({"residual_seconds": t_res, "train_seconds": t_train, "theta": 0.9,
+                  "targets": [len(tr), len(va)]})
+    log(f"  closure: {stats['pairs']} pairs in {t_res:.2f} s; {stats['steps']} steps in {t_train:.2f} s; "
+        f"validation MSE {stats['val_mse']:.3e} vs {stats['val_mse_zero']:.3e} predicting zero")
+    del f_tr, y_tr, f_va, y_va
+
+    learned = []
+    for th_l, th_p, tau in args.learned:
+        def run():
+            tc.build(pos, mass)
+            tc.moments()
+            return tc.forces_learned(th_l, th_p, tau, G=w.G, eps=w.eps, want_pot=False)[0]
+        ms = time_evals(run)
+        acc = run().cpu().numpy()[sample]
+        e = rel_error(acc, ref)
+        kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
+        inter = tc.interactions()
+        plain_ms = interp_ms_at_error(sweep, e["E"])
+        row = {"theta_l": th_l, "theta_p": th_p, "tau": tau if np.isfinite(tau) else "inf",
+               "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "E": e["E"], "p99": e["p99"],
+               "interactions_per_body": inter / w.n, "learned_cells": int(kept.sum()),
+               "fallback_cells": int(fell.sum()),
+               "plain_evals_per_s_at_same_E": None if plain_ms is None else 1e3 / plain_ms,
+               "speedup_vs_plain_at_same_E": None if plain_ms is None else plain_ms / ms}
+        learned.append(row)
+        log(f"  learned theta_l={th_l} theta_p={th_p} tau={tau}: {ms:.3f} ms/eval, E={e['E']:.3e}, "
+            f"kept {row['learned_cells']} fell back {row['fallback_cells']}, speedup at same E "
+            f"{row['speedup_vs_plain_at_same_E']}")
+    out["closure_training"] = stats
+    out["learned"] = learned
+    return out
 
 
 def main():
@@ -96,7 +226,18 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-groups", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="least wall time of whole oracle evaluations for the CPU baseline")
+    ap.add_argument("--no-study", action="store_true", help="skip the error and learned-vs-plain study")
+    ap.add_argument("--sample", type=int, default=8192)
+    ap.add_argument("--sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
+    ap.add_argument("--train-targets", type=int, default=4096)
+    ap.add_argument("--val-targets", type=int, default=1024)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--learned", type=lambda v: tuple(float(x) for x in v.split(",")), nargs="*",
+                    default=[(0.8, 0.5, float("inf")), (0.8, 0.5, 1e-3), (0.7, 0.5, float("inf"))],
+                    help="theta_l,theta_p,tau triples")
     ap.add_argument("--no-diag", action="store_true", help="leave the diagnostics out of the step")
     args = ap.parse_args()
 
@@ -107,7 +248,7 @@ def main():
 
     import torch
 
-    from paper_1211_2293_amd import treecode
+    from paper_1211_2293_amd import treecode, workloads
 
     w = make_workload(args.workload, args.n)
     theta = w.theta if args.theta is None else args.theta
@@ -193,9 +334,23 @@ def main():
             "flops_per_interaction": FLOPS_PER_INTERACTION[w.dim],
         },
     }
+    if not args.no_study:
+        # error of a fresh evaluation at the final positions
+        sample = workloads.sample_indices(w.n, args.sample, seed=104)
+        st = torch.from_numpy(sample.astype(np.int32)).to(dev)
+        tc.build(pos, mass)
+        tc.moments()
+        tc.walk(theta)
+        acc, _ = tc.forces(w.G, w.eps, want_pot=False)
+        ref, _ = tc.direct(st, G=w.G, eps=w.eps)
+        result["rel_force_error"] = dict(rel_error(acc.cpu().numpy()[sample], ref.cpu().numpy()[:, :w.dim]),
+                                         sample=f"{len(sample)} seeded bodies vs the FP64 direct sum")
+        log(f"relative force error E = {result['rel_force_error']['E']:.3e}")
+        log("learned-vs-plain study ...")
+        result["study"] = learned_study(w, args)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample ...")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_groups)
+        log("timing the CPU oracle on whole force evaluations ...")
+        result["cpu_baseline"] = cpu_baseline(w, theta, args.cpu_seconds)
         log(result["cpu_baseline"]["sample"])
     print(json.dumps(result), flush=True)
 

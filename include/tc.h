@@ -124,6 +124,19 @@ int tc_status(tc_ctx *ctx);
 /* Static message for a status code (TC_EHIP includes the last HIP error). */
 const char *tc_strerror(int code);
 
+/* ---- reference sums ------------------------------------------------------ */
+
+/* FP64 direct sum for nt sample bodies (device int32 original indices,
+ * 1 <= nt <= TC_RESID_MAX_TARGETS): acc[t][3] = G sum_{j != i} m_j d /
+ * (|d|^2 + eps^2)^(3/2), d = x_j - x_i, and pot[t] = -G sum_{j != i} m_j /
+ * (|d|^2 + eps^2)^(1/2) over all n bodies (the force law of §3.1 summed
+ * exactly; positions and masses as held after tc_build, i.e. the input
+ * values widened to FP64).  acc, pot: device FP64, either may be NULL.
+ * eps >= 0 (eps = 0 needs distinct positions).  Summation order is fixed,
+ * so results are reproducible.  A target outside [0, n) yields NaN and makes
+ * tc_status report TC_EINVAL.  Requires tc_build. */
+int tc_direct(tc_ctx *ctx, const int32_t *targets, int nt, double G, double eps, double *acc, double *pot);
+
 /* ---- learned closure ---------------------------------------------------
  * An extension of the paper's monopole cells (§3.1): for a body x and an
  * accepted cell (centre of mass C, mass M, side s, traceless quadrupole Q)
@@ -148,7 +161,8 @@ const char *tc_strerror(int code);
  * cell's pre-order index.  Pairs are in target order.  At most cap pairs are
  * written (device buffers); *n_out (host) receives the total.  Prepares the
  * opening radii for theta as tc_walk does.  Synchronises.  Requires
- * tc_moments. */
+ * tc_moments.  A target outside [0, n) gets no pairs and makes tc_status
+ * report TC_EINVAL. */
 int tc_residuals(tc_ctx *ctx, double theta, double eps, const int32_t *targets, int nt, float *feat,
                  float *y, int32_t *cell, int64_t cap, int64_t *n_out);
 
@@ -159,18 +173,22 @@ int tc_mlp_load(tc_ctx *ctx, const float *params);
 /* Copy the FP32 master parameters out (device buffer).  Requires tc_mlp_load. */
 int tc_mlp_get(tc_ctx *ctx, float *params);
 
-/* Network outputs yhat [nb][3] (device) for feature rows feat[idx[k]]
- * (idx: device int32 [nb], or NULL for rows 0..nb-1). */
-int tc_mlp_forward(tc_ctx *ctx, const float *feat, const int32_t *idx, int64_t nb, float *yhat);
+/* Network outputs yhat [nb][3] (device) for feature rows feat[idx[k]] of
+ * feat [nrows][10] (idx: device int32 [nb], or NULL for rows 0..nb-1, then
+ * nb <= nrows).  A device index outside [0, nrows) leaves that output
+ * unwritten and makes tc_status report TC_EINVAL. */
+int tc_mlp_forward(tc_ctx *ctx, const float *feat, int64_t nrows, const int32_t *idx, int64_t nb, float *yhat);
 
 /* One training step on the batch feat[idx[k]], y[idx[k]] (k < nb <=
- * TC_MLP_BATCH_MAX; idx may be NULL): forward, mean squared error over the
+ * TC_MLP_BATCH_MAX; feat [nrows][10], y [nrows][3]; idx may be NULL, then
+ * nb <= nrows; a device index outside [0, nrows) drops that sample and
+ * makes tc_status report TC_EINVAL): forward, mean squared error over the
  * nb x 3 outputs, backward, gradients summed in a fixed order, one Adam
  * step (beta 0.9/0.999, epsilon 1e-8) with learning rate lr >= 0.  *loss
  * (host, may be NULL: then nothing synchronises) gets the batch loss before
  * the update, grad (device, may be NULL) the gradient in canonical order. */
-int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, const int32_t *idx, int64_t nb, double lr,
-                float *loss, float *grad);
+int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, int64_t nrows, const int32_t *idx, int64_t nb,
+                double lr, float *loss, float *grad);
 
 /* Forces with the learned closure (3D only).  The walk of tc_forces with
  * two opening parameters theta_p < theta_l <= 1 (the opening test of §3.1
@@ -185,7 +203,7 @@ int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, const int32_t *i
  * plain walk at theta_l plus every correction.  The potential keeps the
  * monopoles.  acc/pot as tc_forces (device, FP32, either may be NULL).
  * Requires tc_moments and tc_mlp_load; TC_EINVAL for parameters outside
- * the ranges above or dim != 3.  Synchronises once (root mass). */
+ * the ranges above or dim != 3. */
 int tc_forces_learned(tc_ctx *ctx, double G, double eps, double theta_l, double theta_p, double tau,
                       void *acc, void *pot);
 

@@ -42,17 +42,10 @@ def flatten(p):
 
 
 def init_params(seed=0):
-    """Seeded initial parameters: weights uniform in +-1/sqrt(fan_in),
-    biases zero."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for name, shape in SHAPES:
-        if name.startswith("W"):
-            bound = 1.0 / math.sqrt(shape[0])
-            p[name] = rng.uniform(-bound, bound, shape)
-        else:
-            p[name] = np.zeros(shape)
-    return flatten(p).astype(np.float32)
+    """Seeded initial parameters (the shared input generator's draw):
+    weights uniform in +-1/sqrt(fan_in), biases zero."""
+    from paper_1211_2293_amd import workloads
+    return workloads.mlp_params(seed)
 
 
 def bf16(x):

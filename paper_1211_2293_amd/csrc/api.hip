@@ -367,6 +367,7 @@ int tc_status(tc_ctx* ctx) {
     TC_HIP(ctx, hipMemcpy(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost));
     if (p.status & kFlagNonFinite) return TC_ENONFINITE;
     if (p.status & kFlagOverflow) return TC_EWORKSPACE;
+    if (p.status & kFlagBadIndex) return TC_EINVAL;
     return TC_OK;
 }
 
@@ -415,6 +416,20 @@ int tc_residuals(tc_ctx* ctx, double theta, double eps, const int32_t* targets, 
     return TC_OK;
 }
 
+int tc_direct(tc_ctx* ctx, const int32_t* targets, int nt, double G, double eps, double* acc, double* pot) {
+    if (!ctx || !targets || nt < 1 || nt > kResidMaxTargets) return TC_EINVAL;
+    if (!(eps >= 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if ((acc && !aligned(acc, 8)) || (pot && !aligned(pot, 8))) return TC_EINVAL;
+    if (ctx->state < kBuilt) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    uint32_t* inv = ctx->at<uint32_t>(l.off_inv_perm);
+    TC_HIP(ctx, launch_inverse_perm(ctx->at<uint32_t>(l.off_idx_a), ctx->n, inv, s));
+    TC_HIP(ctx, launch_direct64(ctx->at<Body>(l.off_bodies), inv, ctx->n, targets, nt, eps * eps, G, ctx->prm(), acc,
+                                pot, s));
+    return TC_OK;
+}
+
 int tc_mlp_load(tc_ctx* ctx, const float* params) {
     if (!ctx || !params || !aligned(params, 4)) return TC_EINVAL;
     if (!ctx->ws || ctx->state < kBuilt) return TC_ESTATE;
@@ -431,20 +446,23 @@ int tc_mlp_get(tc_ctx* ctx, float* params) {
     return TC_OK;
 }
 
-int tc_mlp_forward(tc_ctx* ctx, const float* feat, const int32_t* idx, int64_t nb, float* yhat) {
-    if (!ctx || !feat || !yhat || nb < 1) return TC_EINVAL;
+int tc_mlp_forward(tc_ctx* ctx, const float* feat, int64_t nrows, const int32_t* idx, int64_t nb, float* yhat) {
+    if (!ctx || !feat || !yhat || nb < 1 || nrows < 1 || (!idx && nb > nrows)) return TC_EINVAL;
     if (!ctx->mlp_loaded) return TC_ESTATE;
-    TC_HIP(ctx, launch_mlp_forward(ctx->at<MlpState>(ctx->lay.off_mlp), feat, idx, nb, yhat, ctx->stream));
+    TC_HIP(ctx, launch_mlp_forward(ctx->at<MlpState>(ctx->lay.off_mlp), feat, nrows, idx, nb, yhat,
+                                   &ctx->prm()->status, ctx->stream));
     return TC_OK;
 }
 
-int tc_mlp_step(tc_ctx* ctx, const float* feat, const float* y, const int32_t* idx, int64_t nb, double lr,
-                float* loss, float* grad) {
+int tc_mlp_step(tc_ctx* ctx, const float* feat, const float* y, int64_t nrows, const int32_t* idx, int64_t nb,
+                double lr, float* loss, float* grad) {
     if (!ctx || !feat || !y || nb < 1 || nb > kMlpBatchMax || !(lr >= 0.0) || !isfinite(lr)) return TC_EINVAL;
+    if (nrows < 1 || (!idx && nb > nrows)) return TC_EINVAL;
     if (!ctx->mlp_loaded) return TC_ESTATE;
     MlpState* st = ctx->at<MlpState>(ctx->lay.off_mlp);
     ctx->mlp_step += 1;
-    TC_HIP(ctx, launch_mlp_step(st, feat, y, idx, nb, (float)lr, ctx->mlp_step, grad, ctx->stream));
+    TC_HIP(ctx, launch_mlp_step(st, feat, y, nrows, idx, nb, (float)lr, ctx->mlp_step, grad, &ctx->prm()->status,
+                                ctx->stream));
     if (loss) {
         TC_HIP(ctx, hipMemcpyAsync(loss, &st->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
         TC_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -468,11 +486,6 @@ int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double 
     TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta_p, l.cmax,
                            ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk),
                            ctx->at<double>(l.off_rcp2), ctx->prm(), s));
-    // total mass (root) over n, for the log-mass feature
-    Moments root;
-    TC_HIP(ctx, hipMemcpyAsync(&root, ctx->at<Moments>(l.off_mom), sizeof(root), hipMemcpyDeviceToHost, s));
-    TC_HIP(ctx, hipStreamSynchronize(s));
-    const double mbar = root.M / (double)ctx->n;
     const float tauf = isinf(tau) ? INFINITY : (float)tau;
     TC_HIP(ctx, launch_walk_force_learned(
                     ctx->at<WalkCell>(l.off_walk), ctx->at<double>(l.off_rcp2), ctx->at<Body>(l.off_bodies),
@@ -480,7 +493,7 @@ int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double 
                     ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_idx_a),
                     ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt), l.gmax,
                     ctx->at<uint32_t>(l.off_queue), ctx->at<MlpState>(l.off_mlp), ctx->leaf_cap, (float)G,
-                    (float)(eps * eps), tauf, mbar, ctx->prm(), ctx->at<float>(l.off_acc),
+                    (float)(eps * eps), tauf, ctx->n, ctx->prm(), ctx->at<float>(l.off_acc),
                     ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p),
                     ctx->at<int64_t>(l.off_nlearn), ctx->at<int64_t>(l.off_nfall), s));
     ctx->G = G;

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_residuals(const WalkCell* __restrict__ 
                                                    const Cell* __restrict__ cells, const Moments* __restrict__ mom,
                                                    const uint32_t* __restrict__ bfs2pre,
                                                    const uint32_t* __restrict__ inv_perm,
-                                                   const DevParams* __restrict__ prm, int64_t n,
+                                                   DevParams* __restrict__ prm, int64_t n,
                                                    const int32_t* __restrict__ targets, int nt, double eps2,
                                                    uint32_t* __restrict__ counts, const uint32_t* __restrict__ offs,
                                                    int64_t cap, float* __restrict__ feat, float* __restrict__ yout,
@@ -112,7 +112,15 @@ __global__ void __launch_bounds__(256) k_residuals(const WalkCell* __restrict__ 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     const int t = blockIdx.x * 4 + wv;
     if (t >= nt) return;
-    const int64_t p = inv_perm[targets[t]];
+    const int64_t o = targets[t];
+    if (o < 0 || o >= n) {                     // no pairs for an index outside the bodies
+        if (lane == 0) {
+            atomicOr(&prm->status, kFlagBadIndex);
+            if (!WRITE) counts[t] = 0u;
+        }
+        return;
+    }
+    const int64_t p = inv_perm[o];
     const Body me = bodies[p];
     const double mbar = mom[0].M / (double)n;
     const double size = prm->size;
@@ -258,25 +266,31 @@ __device__ void net_forward(NetLds& L) {
     __syncthreads();
 }
 
-__device__ void load_features(const float* __restrict__ feat, const int32_t* __restrict__ idx, int64_t nb,
-                              int64_t s0, NetLds& L, int64_t& src, bool& valid) {
+__device__ void load_features(const float* __restrict__ feat, int64_t nrows, const int32_t* __restrict__ idx,
+                              int64_t nb, int64_t s0, NetLds& L, int64_t& src, bool& valid, uint32_t* status) {
     const int l = threadIdx.x;
     const int64_t s = s0 + l;
     valid = s < nb;
     src = valid ? (idx ? (int64_t)idx[s] : s) : 0;
+    if (valid && (src < 0 || src >= nrows)) {  // a row outside feat: left out, flagged
+        atomicOr(status, kFlagBadIndex);
+        valid = false;
+        src = 0;
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) L.x[l * 16 + q] = (valid && q < kNIn) ? f2bf(feat[src * kNIn + q]) : (uint16_t)0;
 }
 
-__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ feat, const int32_t* __restrict__ idx,
-                                                    int64_t nb, const MlpState* __restrict__ st,
-                                                    float* __restrict__ yhat) {
+__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ feat, int64_t nrows,
+                                                    const int32_t* __restrict__ idx, int64_t nb,
+                                                    const MlpState* __restrict__ st, float* __restrict__ yhat,
+                                                    uint32_t* status) {
     __shared__ NetLds L;
     load_net(st, L);
     int64_t src;
     bool valid;
     const int64_t s0 = (int64_t)blockIdx.x * kMlpBlock;
-    load_features(feat, idx, nb, s0, L, src, valid);
+    load_features(feat, nrows, idx, nb, s0, L, src, valid, status);
     __syncthreads();
     net_forward(L);
     const int l = threadIdx.x;
@@ -287,15 +301,15 @@ __global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ fe
 // One training block: forward, squared error, backward for 64 samples;
 // writes this block's gradient sums (canonical order) and squared error.
 __global__ void __launch_bounds__(64) k_mlp_train(const float* __restrict__ feat, const float* __restrict__ ytrue,
-                                                  const int32_t* __restrict__ idx, int64_t nb,
-                                                  MlpState* __restrict__ st) {
+                                                  int64_t nrows, const int32_t* __restrict__ idx, int64_t nb,
+                                                  MlpState* __restrict__ st, uint32_t* status) {
     __shared__ NetLds L;
     __shared__ uint16_t dy[kMlpBlock * 16], dz2[kMlpBlock * kNHid], dz1[kMlpBlock * kNHid];
     load_net(st, L);
     int64_t src;
     bool valid;
     const int64_t s0 = (int64_t)blockIdx.x * kMlpBlock;
-    load_features(feat, idx, nb, s0, L, src, valid);
+    load_features(feat, nrows, idx, nb, s0, L, src, valid, status);
     __syncthreads();
     net_forward(L);
     const int l = threadIdx.x;
@@ -460,7 +474,7 @@ hipError_t launch_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, h
 
 hipError_t launch_residuals(bool write, const WalkCell* walk, const Body* bodies, const Cell* cells,
                             const Moments* mom, const uint32_t* bfs2pre, const uint32_t* inv_perm,
-                            const DevParams* prm, int64_t n, const int32_t* targets, int nt, double eps2,
+                            DevParams* prm, int64_t n, const int32_t* targets, int nt, double eps2,
                             uint32_t* counts, const uint32_t* offs, int64_t cap, float* feat, float* y,
                             int32_t* cell_out, hipStream_t s) {
     const unsigned nb = (unsigned)((nt + 3) / 4);
@@ -483,17 +497,17 @@ hipError_t launch_mlp_get(const MlpState* st, float* params, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const MlpState* st, const float* feat, const int32_t* idx, int64_t nb, float* yhat,
-                              hipStream_t s) {
+hipError_t launch_mlp_forward(const MlpState* st, const float* feat, int64_t nrows, const int32_t* idx, int64_t nb,
+                              float* yhat, uint32_t* status, hipStream_t s) {
     const unsigned blocks = (unsigned)((nb + kMlpBlock - 1) / kMlpBlock);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(kMlpBlock), 0, s, feat, idx, nb, st, yhat);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(kMlpBlock), 0, s, feat, nrows, idx, nb, st, yhat, status);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_step(MlpState* st, const float* feat, const float* y, const int32_t* idx, int64_t nb, float lr,
-                           int step, float* grad_out, hipStream_t s) {
+hipError_t launch_mlp_step(MlpState* st, const float* feat, const float* y, int64_t nrows, const int32_t* idx,
+                           int64_t nb, float lr, int step, float* grad_out, uint32_t* status, hipStream_t s) {
     const int blocks = (int)((nb + kMlpBlock - 1) / kMlpBlock);
-    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(kMlpBlock), 0, s, feat, y, idx, nb, st);
+    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(kMlpBlock), 0, s, feat, y, nrows, idx, nb, st, status);
     hipLaunchKernelGGL(k_mlp_adam, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, s, st, blocks, nb, lr, step,
                        grad_out);
     return hipGetLastError();

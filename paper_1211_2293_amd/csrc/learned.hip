@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
     const float4* __restrict__ bodies32, const Cell* __restrict__ cells, const Moments* __restrict__ mom,
     const uint32_t* __restrict__ bfs2pre, const uint32_t* __restrict__ perm, const int32_t* __restrict__ gbeg,
     const int32_t* __restrict__ gcnt, uint32_t* queue, const MlpState* __restrict__ st, int lpl_log2, float G,
-    float eps2, float tau, double mbar, const DevParams* __restrict__ prm, float* __restrict__ acc,
+    float eps2, float tau, int64_t n, const DevParams* __restrict__ prm, float* __restrict__ acc,
     float* __restrict__ pot, int64_t* __restrict__ m2p_out, int64_t* __restrict__ p2p_out,
     int64_t* __restrict__ learned_out, int64_t* __restrict__ fallback_out) {
     constexpr int R = 8, RP = kWave / R;
@@ -160,6 +160,7 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
     const int lpl = 1 << lpl_log2;
     const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
     const double size = prm->size;
+    const double mbar = mom[0].M / (double)n;          // mean body mass (root cell)
 
     const uint32_t NG = prm->ngroups;
     const int home = (int)(blockIdx.x % kXcd);
@@ -391,7 +392,7 @@ hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, c
                                      const float4* bodies32, const Cell* cells, const Moments* mom,
                                      const uint32_t* bfs2pre, const uint32_t* perm, const int32_t* gbeg,
                                      const int32_t* gcnt, int64_t gmax, uint32_t* queue, const MlpState* st,
-                                     int leaf_cap, float G, float eps2, float tau, double mbar,
+                                     int leaf_cap, float G, float eps2, float tau, int64_t n,
                                      const DevParams* prm, float* acc, float* pot, int64_t* m2p, int64_t* p2p,
                                      int64_t* learned, int64_t* fallback, hipStream_t s) {
     static int resident = 0;
@@ -410,7 +411,7 @@ hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, c
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     hipLaunchKernelGGL(k_reset_queue_l, dim3(1), dim3(64), 0, s, queue);
     hipLaunchKernelGGL(k_walk_force_learned, dim3((unsigned)want), dim3(256), 0, s, walk, rcp2, bodies, bodies32, cells,
-                       mom, bfs2pre, perm, gbeg, gcnt, queue, st, lpl_log2, G, eps2, tau, mbar, prm, acc, pot, m2p,
+                       mom, bfs2pre, perm, gbeg, gcnt, queue, st, lpl_log2, G, eps2, tau, n, prm, acc, pot, m2p,
                        p2p, learned, fallback);
     return hipGetLastError();
 }

@@ -19,6 +19,7 @@ constexpr int kXcd = 8;             // XCDs per MI355X: one work queue each
 // Status bits raised by kernels into the workspace's status word.
 constexpr uint32_t kFlagNonFinite = 1u;
 constexpr uint32_t kFlagOverflow = 2u;   // cell bound exceeded (never expected)
+constexpr uint32_t kFlagBadIndex = 4u;   // an index argument outside its array
 
 inline int levels_for(int dim) { return dim == 3 ? 21 : 31; }
 
@@ -137,24 +138,26 @@ hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_
                            hipStream_t s);
 // closure.hip
 struct MlpState;
+hipError_t launch_direct64(const Body* bodies, const uint32_t* inv_perm, int64_t n, const int32_t* targets, int nt,
+                           double eps2, double G, DevParams* prm, double* acc, double* pot, hipStream_t s);
 hipError_t launch_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t s);
 hipError_t launch_residuals(bool write, const WalkCell* walk, const Body* bodies, const Cell* cells,
                             const Moments* mom, const uint32_t* bfs2pre, const uint32_t* inv_perm,
-                            const DevParams* prm, int64_t n, const int32_t* targets, int nt, double eps2,
+                            DevParams* prm, int64_t n, const int32_t* targets, int nt, double eps2,
                             uint32_t* counts, const uint32_t* offs, int64_t cap, float* feat, float* y,
                             int32_t* cell_out, hipStream_t s);
 hipError_t launch_mlp_load(MlpState* st, const float* params, hipStream_t s);
 hipError_t launch_mlp_get(const MlpState* st, float* params, hipStream_t s);
-hipError_t launch_mlp_forward(const MlpState* st, const float* feat, const int32_t* idx, int64_t nb, float* yhat,
-                              hipStream_t s);
-hipError_t launch_mlp_step(MlpState* st, const float* feat, const float* y, const int32_t* idx, int64_t nb, float lr,
-                           int step, float* grad_out, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpState* st, const float* feat, int64_t nrows, const int32_t* idx, int64_t nb,
+                              float* yhat, uint32_t* status, hipStream_t s);
+hipError_t launch_mlp_step(MlpState* st, const float* feat, const float* y, int64_t nrows, const int32_t* idx,
+                           int64_t nb, float lr, int step, float* grad_out, uint32_t* status, hipStream_t s);
 // learned.hip
 hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, const Body* bodies,
                                      const float4* bodies32, const Cell* cells, const Moments* mom,
                                      const uint32_t* bfs2pre, const uint32_t* perm, const int32_t* gbeg,
                                      const int32_t* gcnt, int64_t gmax, uint32_t* queue, const MlpState* st,
-                                     int leaf_cap, float G, float eps2, float tau, double mbar,
+                                     int leaf_cap, float G, float eps2, float tau, int64_t n,
                                      const DevParams* prm, float* acc, float* pot, int64_t* m2p, int64_t* p2p,
                                      int64_t* learned, int64_t* fallback, hipStream_t s);
 // step.hip

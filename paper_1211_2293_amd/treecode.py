@@ -69,8 +69,9 @@ def lib():
         "tc_residuals": (i32, [P, dbl, dbl, P, i32, P, P, P, i64, C.POINTER(C.c_int64)]),
         "tc_mlp_load": (i32, [P, P]),
         "tc_mlp_get": (i32, [P, P]),
-        "tc_mlp_forward": (i32, [P, P, P, i64, P]),
-        "tc_mlp_step": (i32, [P, P, P, P, i64, dbl, C.POINTER(C.c_float), P]),
+        "tc_mlp_forward": (i32, [P, P, i64, P, i64, P]),
+        "tc_mlp_step": (i32, [P, P, P, i64, P, i64, dbl, C.POINTER(C.c_float), P]),
+        "tc_direct": (i32, [P, P, i32, dbl, dbl, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -328,21 +329,45 @@ class Treecode:
         _check(lib().tc_mlp_get(self._h, _ptr(out)))
         return out
 
-    def mlp_forward(self, feat: torch.Tensor, idx: torch.Tensor | None = None) -> torch.Tensor:
+    def _batch(self, feat, y, idx):
         self._dev(feat, "feat")
-        nb = feat.shape[0] if idx is None else idx.shape[0]
+        if feat.dtype != torch.float32 or feat.dim() != 2 or feat.shape[1] != 10:
+            raise TypeError("feat must be float32 [rows][10]")
+        if y is not None:
+            self._dev(y, "y")
+            if y.dtype != torch.float32 or tuple(y.shape) != (feat.shape[0], 3):
+                raise TypeError("y must be float32 [rows][3] with the rows of feat")
+        if idx is not None:
+            self._dev(idx, "idx")
+            if idx.dtype != torch.int32 or idx.dim() != 1:
+                raise TypeError("idx must be a 1-D int32 tensor")
+        return feat.shape[0] if idx is None else idx.shape[0]
+
+    def mlp_forward(self, feat: torch.Tensor, idx: torch.Tensor | None = None) -> torch.Tensor:
+        nb = self._batch(feat, None, idx)
         out = torch.empty((nb, 3), dtype=torch.float32, device=self.stream.device)
-        _check(lib().tc_mlp_forward(self._h, _ptr(feat), _ptr(idx), nb, _ptr(out)))
+        _check(lib().tc_mlp_forward(self._h, _ptr(feat), feat.shape[0], _ptr(idx), nb, _ptr(out)))
         return out
 
     def mlp_step(self, feat, y, idx=None, lr=1e-3, want_loss=True, grad=None):
-        self._dev(feat, "feat")
-        self._dev(y, "y")
-        nb = feat.shape[0] if idx is None else idx.shape[0]
+        nb = self._batch(feat, y, idx)
         loss = C.c_float(0.0)
-        _check(lib().tc_mlp_step(self._h, _ptr(feat), _ptr(y), _ptr(idx), nb, float(lr),
+        _check(lib().tc_mlp_step(self._h, _ptr(feat), _ptr(y), feat.shape[0], _ptr(idx), nb, float(lr),
                                  C.byref(loss) if want_loss else None, _ptr(grad)))
         return float(loss.value) if want_loss else None
+
+    # -- reference sums --------------------------------------------------
+    def direct(self, targets: torch.Tensor, G: float = 1.0, eps: float = 1e-2):
+        """FP64 direct sum for the given original body indices (int32 CUDA
+        tensor): (acc [nt][3], pot [nt]) FP64 CUDA tensors."""
+        self._dev(targets, "targets")
+        if targets.dtype != torch.int32 or targets.dim() != 1:
+            raise TypeError("targets must be a 1-D int32 tensor")
+        dev = self.stream.device
+        acc = torch.empty((len(targets), 3), dtype=torch.float64, device=dev)
+        pot = torch.empty(len(targets), dtype=torch.float64, device=dev)
+        _check(lib().tc_direct(self._h, _ptr(targets), len(targets), float(G), float(eps), _ptr(acc), _ptr(pot)))
+        return acc, pot
 
     def set_timing(self, on: bool):
         _check(lib().tc_set_timing(self._h, int(bool(on))))

@@ -162,6 +162,33 @@ def sample_indices(n, count=8192, seed=104):
     return np.sort(rng.choice(n, size=min(count, n), replace=False)).astype(np.int64)
 
 
+# closure network shapes in the library's canonical parameter order
+MLP_SHAPES = [(10, 64), (64,), (64, 64), (64,), (64, 3), (3,)]
+
+
+def mlp_params(seed=0):
+    """Seeded initial network parameters, FP32, canonical order (W1 [10][64],
+    b1, W2 [64][64], b2, W3 [64][3], b3): weights uniform in +-1/sqrt(fan_in),
+    biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            bound = 1.0 / np.sqrt(shape[0])
+            parts.append(rng.uniform(-bound, bound, shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def batch_order(npairs, steps, batch, seed=0):
+    """Seeded sample order for minibatch training: concatenated random
+    permutations of range(npairs), at least steps * batch entries, int32."""
+    rng = np.random.default_rng(seed)
+    reps = (steps * batch) // max(npairs, 1) + 1
+    return np.concatenate([rng.permutation(npairs) for _ in range(reps)]).astype(np.int32)
+
+
 BY_NAME = {
     "uniform-cube": uniform_cube,
     "gaussian-disk-2d": gaussian_disk,
