@@ -53,7 +53,7 @@ def make_workload(name: str, n: int | None):
 
 def force_kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("force.hip", "tc_internal.h"):
+    for f in ("force.hip", "walk_common.h", "tc_internal.h"):
         with open(os.path.join(ROOT, "paper_1211_2293_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -180,7 +180,7 @@ def learned_study(w, args):
     torch.cuda.synchronize()
     t_res = time.perf_counter() - t0
     t0 = time.perf_counter()
-    stats = closure.train(tc, f_tr, y_tr, epochs=args.epochs, batch=4096, lr=args.lr, lr_final=args.lr / 10,
+    stats = closure.train(tc, f_tr, y_tr, epochs=args.epochs, batch=4096, lr=args.lr, lr_final=args.lr / 100,
                           val=(f_va, y_va), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -229,12 +229,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="least wall time of whole oracle evaluations for the CPU baseline")
     ap.add_argument("--no-study", action="store_true", help="skip the error and learned-vs-plain study")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run 3 plain device copies of MIB MiB (a known-size reference for "
+                         "hardware byte counters)")
     ap.add_argument("--sample", type=int, default=8192)
     ap.add_argument("--sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--learned", type=lambda v: tuple(float(x) for x in v.split(",")), nargs="*",
                     default=[(0.8, 0.5, float("inf")), (0.8, 0.5, 1e-3), (0.7, 0.5, float("inf"))],
                     help="theta_l,theta_p,tau triples")
@@ -249,6 +252,15 @@ def main():
     import torch
 
     from paper_1211_2293_amd import treecode, workloads
+
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
 
     w = make_workload(args.workload, args.n)
     theta = w.theta if args.theta is None else args.theta

@@ -140,8 +140,8 @@ int tc_direct(tc_ctx *ctx, const int32_t *targets, int nt, double G, double eps,
 /* ---- learned closure ---------------------------------------------------
  * An extension of the paper's monopole cells (§3.1): for a body x and an
  * accepted cell (centre of mass C, mass M, side s, traceless quadrupole Q)
- * a network predicts the normalised residual
- *     y = (a_exact - a_mono) |x - C|^2 / M      (G = 1)
+ * a network predicts the residual in units of the quadrupole scale
+ *     y = (a_exact - a_mono) |x - C|^4 / (M s^2)      (G = 1)
  * between the exact sum over the cell's bodies and its monopole, from the
  * features f = [(x - C)/s (3), Q/(M s^2) (6: xx yy zz xy xz yz),
  * ln(M / mbar) (1)], mbar = total mass / n.  The network is 10-64-64-3
@@ -198,7 +198,7 @@ int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, int64_t nrows, c
  * predicts, for each body of the walk group, the normalised residual yhat
  * (features as tc_residuals); if max |yhat| over the group exceeds tau the
  * cell falls back to the plain walk of its subtree at theta_p, otherwise it
- * is a monopole entry plus G M yhat / |x - C|^2 per body (no softening).
+ * is a monopole entry plus G M s^2 yhat / |x - C|^4 per body (no softening).
  * tau = 0 gives exactly the plain walk at theta_p; tau = +inf gives the
  * plain walk at theta_l plus every correction.  The potential keeps the
  * monopoles.  acc/pot as tc_forces (device, FP32, either may be NULL).

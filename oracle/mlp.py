@@ -123,15 +123,17 @@ def adam(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=1024, chunk=1 << 17):
+def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=1024, chunk=1 << 17,
+                        groups=None):
     """The learned walk with no fallback: for every walk group, the cells
     accepted at theta_l but opened at theta_p (the opening test of §3.1 on
     the group's box, FP64) are its learned cells; each of the group's bodies
-    gets the network's correction G M yhat / |x - C|^2 for each of them
+    gets the network's correction G M s^2 yhat / |x - C|^4 for each of them
     (bfloat16 operands as on the GPU).  Returns a dict: corr [n][3] in
     original order, per_group (learned cells per walk group), and per
     learned (group, cell) pair its group index and the largest |yhat| over
-    the group's bodies (the fallback test's statistic)."""
+    the group's bodies (the fallback test's statistic).  `groups` restricts
+    the work to those walk-group indices (the others get no corrections)."""
     n = tree.n
     c = tree.cells()
     _, size = tree.root()
@@ -142,7 +144,9 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
     gb, gc = tree.groups(gs, cluster)
     per_group = np.zeros(len(gb), np.int64)
     pairs = []                                        # (group, cell)
-    for g, (b, k) in enumerate(zip(gb, gc)):
+    todo = range(len(gb)) if groups is None else sorted(int(g) for g in groups)
+    for g in todo:
+        b, k = gb[g], gc[g]
         items = tree.walk_items_range(theta_l, b, b + k)
         acc_cells = items[items >= 0]
         if len(acc_cells) == 0:
@@ -181,7 +185,8 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
         rows.append(f.astype(np.float32))
         owners.append(perm[b:b + k])
         dd = x - c["com"][cl]
-        weights.append(M / ((dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]))
+        d2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+        weights.append(M * s * s / (d2 * d2))
         pidx.append(np.full(k, j))
         held += k
         if held >= chunk:

@@ -645,9 +645,11 @@ void orc_tree_forces_ranges(const orc_tree *t, double theta, double G, double ep
  * centre of mass C, mass M, side s, traceless quadrupole Q:
  *   features  (x - C)/s (3), Q/(M s^2) (6: xx yy zz xy xz yz), ln(M / mbar)
  *             with mbar = (total mass)/n,
- *   residual  y = (a_exact - a_mono) |x - C|^2 / M, where a_exact is the
- *             softened sum over the cell's bodies and a_mono = M (C - x) /
- *             (|C - x|^2 + eps^2)^{3/2} (G = 1).
+ *   residual  y = (a_exact - a_mono) |x - C|^4 / (M s^2), where a_exact is
+ *             the softened sum over the cell's bodies and a_mono = M (C - x) /
+ *             (|C - x|^2 + eps^2)^{3/2} (G = 1): the residual in units of the
+ *             quadrupole scale M s^2 / |x - C|^4, so targets are of order
+ *             |Q| / (M s^2) at every distance.
  * Pairs are in target order, then in walk order.  Writes at most cap pairs
  * (feat [cap][10] FP32, y [cap][3] FP64, target index and cell), count[t]
  * per target; returns the total number of pairs.  3D only. */
@@ -696,7 +698,7 @@ int64_t orc_residuals(const orc_tree *t, double theta, double eps, int64_t nt, c
                 for (int q = 0; q < 3; ++q) { dc[q] = C[q] - x[q]; d2 += dc[q] * dc[q]; }
                 const double inv = 1.0 / sqrt(d2 + e2);
                 const double w3 = M * inv * inv * inv;
-                for (int q = 0; q < 3; ++q) y[o * 3 + q] = (ex[q] - w3 * dc[q]) * d2 / M;
+                for (int q = 0; q < 3; ++q) y[o * 3 + q] = (ex[q] - w3 * dc[q]) * (d2 * d2) / (M * s * s);
                 for (int q = 0; q < 3; ++q) feat[o * 10 + q] = (float)((x[q] - C[q]) / s);
                 const double qs = M * s * s;
                 for (int q = 0; q < 6; ++q) feat[o * 10 + 3 + q] = (float)(t->Q[(int64_t)c * 6 + q] / qs);

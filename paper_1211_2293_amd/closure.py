@@ -24,7 +24,7 @@ def residual_pairs(tc, theta, eps, targets):
     return feat.clone(), y.clone()
 
 
-def train(tc, feat, y, *, epochs=20, batch=4096, lr=1e-3, lr_final=1e-4, seed=0, init_seed=0,
+def train(tc, feat, y, *, epochs=40, batch=4096, lr=3e-3, lr_final=3e-5, seed=0, init_seed=0,
           val=None, log=None):
     """Train from the seeded initial parameters: `epochs` passes over the
     pairs in seeded random minibatches of `batch`, Adam with the learning

@@ -151,11 +151,13 @@ __global__ void __launch_bounds__(256) k_residuals(const WalkCell* __restrict__ 
                 const double d2 = (dcx * dcx + dcy * dcy) + dcz * dcz;
                 const double inv = 1.0 / sqrt(d2 + eps2);
                 const double w3 = M * inv * inv * inv;
-                float* y = yout + k * 3;
-                y[0] = (float)((ex - w3 * dcx) * d2 / M);
-                y[1] = (float)((ey - w3 * dcy) * d2 / M);
-                y[2] = (float)((ez - w3 * dcz) * d2 / M);
                 const double s = ldexp(size, -c.level);
+                // residual in units of the quadrupole scale M s^2 / d^4
+                const double nrm = (d2 * d2) / (M * s * s);
+                float* y = yout + k * 3;
+                y[0] = (float)((ex - w3 * dcx) * nrm);
+                y[1] = (float)((ey - w3 * dcy) * nrm);
+                y[2] = (float)((ez - w3 * dcz) * nrm);
                 float* f = feat + k * 10;
                 f[0] = (float)((me.x - mo.com[0]) / s);
                 f[1] = (float)((me.y - mo.com[1]) / s);

@@ -11,7 +11,8 @@
 // of the group's bodies; if the largest |yhat| over the group exceeds tau
 // the cell falls back to the plain walk of its subtree at theta_P (its
 // children in mode P, or its bodies directly if it is a leaf), otherwise it
-// enters as a monopole entry plus, per body, G M / |x - C|^2 yhat.  With
+// enters as a monopole entry plus, per body, G M s^2 yhat / |x - C|^4 (the
+// network predicts the residual in units of the quadrupole scale).  With
 // tau = 0 every learned cell falls back and the walk is exactly the plain
 // walk at theta_P; with tau = inf it is the plain walk at theta_L plus the
 // corrections.  The potential keeps the monopoles.
@@ -350,7 +351,8 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                             L[len] = make_float4((float)(cx - rx), (float)(cy - ry), (float)(cz - rz), (float)M);
                         len += 1;
                         const double ex = me.x - cx, ey = me.y - cy, ez = me.z - cz;
-                        const float w = (float)(M / ((ex * ex + ey * ey) + ez * ez));
+                        const double dd = (ex * ex + ey * ey) + ez * ez;
+                        const float w = (float)(M * s * s / (dd * dd));   // quadrupole scale
                         comp_add(kx, ckx, w * yh[0]);
                         comp_add(ky, cky, w * yh[1]);
                         comp_add(kz, ckz, w * yh[2]);

@@ -99,29 +99,16 @@ def test_adam_step_matches_oracle(plummer):
 
 
 def test_training_on_residuals_lowers_the_loss():
+    from paper_1211_2293_amd import closure
     w = workloads.plummer_sphere(65536, seed=95)
     tc, keep = _ctx(w)
-    tr = to_dev(workloads.sample_indices(w.n, 512, seed=203).astype(np.int32))
-    va = to_dev(workloads.sample_indices(w.n, 128, seed=204).astype(np.int32))
-    f_tr, y_tr, _ = tc.residuals(0.9, 1e-2, tr)
-    f_tr, y_tr = f_tr.clone(), y_tr.clone()
-    f_va, y_va, _ = tc.residuals(0.9, 1e-2, va)
-    tc.mlp_load(to_dev(mlp.init_params(seed=8)))
-    base = float((y_va ** 2).mean())               # predicting zero
-    rng = np.random.default_rng(96)
-    steps = 2500
-    order = to_dev(np.concatenate([rng.permutation(len(f_tr)) for _ in range(steps * 4096 // len(f_tr) + 1)])
-                   .astype(np.int32))
-    losses = []
-    for step in range(steps):
-        idx = order[step * 4096:(step + 1) * 4096]
-        lr = 3e-3 if step < 2000 else 1e-3
-        losses.append(tc.mlp_step(f_tr, y_tr, idx, lr=lr, want_loss=(step % 500 == 0 or step == steps - 1)))
-    val = float(((tc.mlp_forward(f_va) - y_va) ** 2).mean())
-    print(f"pairs {len(f_tr)}; loss {losses[0]:.3e} -> {losses[-1]:.3e}; validation {val:.3e} vs zero "
-          f"predictor {base:.3e}", flush=True)
-    assert losses[-1] < 0.5 * losses[0]
-    assert val < 0.75 * base
+    f_tr, y_tr = closure.residual_pairs(tc, 0.9, 1e-2, workloads.sample_indices(w.n, 512, seed=203))
+    f_va, y_va = closure.residual_pairs(tc, 0.9, 1e-2, workloads.sample_indices(w.n, 128, seed=204))
+    st = closure.train(tc, f_tr, y_tr, epochs=40, val=(f_va, y_va))
+    print(f"pairs {st['pairs']}, {st['steps']} steps; loss {st['loss_first']:.3e} -> {st['loss_last']:.3e}; "
+          f"validation {st['val_mse']:.3e} vs zero predictor {st['val_mse_zero']:.3e}", flush=True)
+    assert st["loss_last"] < 0.5 * st["loss_first"]
+    assert st["val_mse"] < 0.5 * st["val_mse_zero"]
 
 
 @pytest.fixture(scope="module")

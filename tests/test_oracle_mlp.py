@@ -92,8 +92,11 @@ def test_two_body_cell_approaches_quadrupole(R):
     assert len(k) == 1
     y = r["y"][k[0]]
     # exact minus monopole along the axis: 6 G m a^2 / R^4 toward the pair,
-    # normalised by G M / R^2 with M = 2m: 3 a^2 / R^2, pointing to -x
-    ref = 3.0 * a * a / (R * R)
+    # in units of the quadrupole scale G M s^2 / R^4 with M = 2m: 3 a^2 / s^2,
+    # pointing to -x
+    lo, size = t.root()
+    s = size / 2.0 ** c["level"][r["cell"][k[0]]]
+    ref = 3.0 * a * a / (s * s)
     assert abs(-y[0] / ref - 1.0) < 1e-3 * (1 + (a / R) ** 2 * 1e3)
     assert abs(y[1]) < 1e-12 and abs(y[2]) < 1e-12
 
@@ -134,8 +137,8 @@ def test_pairs_are_the_per_body_walk():
 def test_learned_corrections_with_a_constant_network():
     """With W3 = 0 and b3 = (1, 0, 0) every prediction is (1, 0, 0); with
     theta_p = 0 every cell the theta_l walk accepts is learned, so the x
-    correction of a body is the sum of M / |x - C|^2 over the accepted cells
-    of its group's walk (brute force from the walk items)."""
+    correction of a body is the sum of M s^2 / |x - C|^4 over the accepted
+    cells of its group's walk (brute force from the walk items)."""
     from paper_1211_2293_amd import workloads
     w = workloads.plummer_sphere(1500, seed=85)
     t = oracle.Tree(w.pos, w.mass, 8)
@@ -146,6 +149,7 @@ def test_learned_corrections_with_a_constant_network():
     c = t.cells()
     perm = t.bodies()["perm"]
     gb, gc = t.groups(64, 1024)
+    _, size = t.root()
     ref = np.zeros(w.n)
     for g, (b, k) in enumerate(zip(gb, gc)):
         items = t.walk_items_range(0.7, b, b + k)
@@ -153,7 +157,8 @@ def test_learned_corrections_with_a_constant_network():
         assert r["per_group"][g] == len(acc_cells)
         for i in perm[b:b + k]:
             d = w.pos[i][None] - c["com"][acc_cells]
-            ref[i] = 2.0 * (c["M"][acc_cells] / (d * d).sum(1)).sum()
+            s2 = (size / 2.0 ** c["level"][acc_cells]) ** 2
+            ref[i] = 2.0 * (c["M"][acc_cells] * s2 / (d * d).sum(1) ** 2).sum()
     np.testing.assert_allclose(r["corr"][:, 0], ref, rtol=1e-12)
     assert np.all(r["corr"][:, 1:] == 0.0)
     assert np.allclose(r["pair_gmax"], 1.0)
