@@ -108,8 +108,17 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
 /* One kick-drift-kick leapfrog step of size dt (finite) on pos and vel (in
  * place, dtype of tc_build, caller order): v += dt/2 a(x); x += dt v;
  * rebuild, moments, walk and forces at the new x with the last theta, G and
- * eps; v += dt/2 a(x').  Requires a previous tc_forces. */
+ * eps; v += dt/2 a(x').  Requires a previous tc_forces.
+ * By default everything before the force kernel (about 70 short kernels) is
+ * recorded once as a HIP graph and replayed on a stream private to the
+ * context, ordered after and before the context's stream by events; it is
+ * recorded again when pos, vel, the workspace, n, dt or theta change.
+ * Results are the same as without the graph. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
+
+/* Switch the graph replay of tc_leapfrog on (default) or off (every kernel
+ * launched on the context's stream).  Off also frees the recorded graph. */
+int tc_set_graph(tc_ctx *ctx, int on);
 
 /* FP64 diagnostics of the last forces, with deterministic reductions:
  * out[0] = 1/2 sum m v^2, out[1] = 1/2 sum m phi, out[2..4] = sum m v,

@@ -122,6 +122,22 @@ struct tc_ctx {
     hipError_t last_hip = hipSuccess;
     int mlp_step = 0;          // Adam steps since the last tc_mlp_load
     bool mlp_loaded = false;
+    // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
+    bool use_graph = true;
+    hipStream_t gstream = nullptr;
+    hipEvent_t g_in = nullptr, g_out = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    struct GraphKey {
+        const void *pos, *vel, *mass;
+        const uint8_t* ws;
+        int64_t n;
+        int dim, dtype, leaf_cap;
+        double dt, theta;
+        bool operator==(const GraphKey& o) const {
+            return pos == o.pos && vel == o.vel && mass == o.mass && ws == o.ws && n == o.n && dim == o.dim &&
+                   dtype == o.dtype && leaf_cap == o.leaf_cap && dt == o.dt && theta == o.theta;
+        }
+    } g_key{};
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -164,12 +180,11 @@ hipEvent_t pooled_event(tc_ctx* ctx) {
 }
 
 // Everything tc_build enqueues, after its checks.
-int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf_cap, int dtype) {
+int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf_cap, int dtype, hipStream_t s) {
     const int dim = ctx->dim;
     ctx->lay = make_layout(n, dim, leaf_cap);
     const Layout& l = ctx->lay;
     const int f64 = dtype == TC_F64;
-    hipStream_t s = ctx->stream;
     DevParams* prm = ctx->prm();
     TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part), prm, s));
     TC_HIP(ctx, launch_keys(pos, n, dim, f64, prm, ctx->at<uint64_t>(l.off_keys_a),
@@ -202,21 +217,21 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     return TC_OK;
 }
 
-int do_moments(tc_ctx* ctx) {
+int do_moments(tc_ctx* ctx, hipStream_t s) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
                                ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
                                ctx->at<uint32_t>(l.off_lvl_off), ctx->at<Moments>(l.off_mom),
-                               ctx->at<WalkCell>(l.off_walk), ctx->stream));
+                               ctx->at<WalkCell>(l.off_walk), s));
     ctx->state = kMoments;
     return TC_OK;
 }
 
-int do_walk(tc_ctx* ctx, double theta) {
+int do_walk(tc_ctx* ctx, double theta, hipStream_t s) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta, l.cmax,
                            ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), nullptr, ctx->prm(),
-                           ctx->stream));
+                           s));
     ctx->theta = theta;
     ctx->state = kWalked;
     return TC_OK;
@@ -250,6 +265,59 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
     return TC_OK;
 }
 
+// The part of a step before the force kernel (kick + drift, tree build,
+// moments, opening radii: about 70 short kernels) on stream s.
+int enqueue_pre_force(tc_ctx* ctx, double dt, void* pos, void* vel, hipStream_t s) {
+    const int f64 = ctx->dtype == TC_F64;
+    TC_HIP(ctx, launch_kick_drift(pos, vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, f64, dt, s));
+    int rc = do_build(ctx, pos, ctx->mass, ctx->n, ctx->leaf_cap, ctx->dtype, s);
+    if (rc == TC_OK) rc = do_moments(ctx, s);
+    if (rc == TC_OK) rc = do_walk(ctx, ctx->theta, s);
+    return rc;
+}
+
+void drop_graph(tc_ctx* ctx) {
+    if (ctx->g_exec) (void)hipGraphExecDestroy(ctx->g_exec);
+    ctx->g_exec = nullptr;
+}
+
+// Replays the pre-force part as one graph launch on a private stream,
+// ordered after and before the context's stream by events.  The graph is
+// (re)captured whenever anything it bakes in (buffers, sizes, dt, theta)
+// changes.  Returns TC_OK, or an error with nothing enqueued.
+int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
+    tc_ctx::GraphKey key{pos, vel, ctx->mass, ctx->ws, ctx->n, ctx->dim, ctx->dtype, ctx->leaf_cap, dt, ctx->theta};
+    if (!ctx->gstream) {
+        TC_HIP(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        TC_HIP(ctx, hipEventCreateWithFlags(&ctx->g_in, hipEventDisableTiming));
+        TC_HIP(ctx, hipEventCreateWithFlags(&ctx->g_out, hipEventDisableTiming));
+    }
+    if (!ctx->g_exec || !(key == ctx->g_key)) {
+        drop_graph(ctx);
+        TC_HIP(ctx, hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeRelaxed));
+        const int rc = enqueue_pre_force(ctx, dt, pos, vel, ctx->gstream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->gstream, &g);
+        if (rc != TC_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != TC_OK ? rc : hip_fail(ctx, e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&ctx->g_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            ctx->g_exec = nullptr;
+            return hip_fail(ctx, ei);
+        }
+        ctx->g_key = key;
+    }
+    TC_HIP(ctx, hipEventRecord(ctx->g_in, ctx->stream));
+    TC_HIP(ctx, hipStreamWaitEvent(ctx->gstream, ctx->g_in, 0));
+    TC_HIP(ctx, hipGraphLaunch(ctx->g_exec, ctx->gstream));
+    TC_HIP(ctx, hipEventRecord(ctx->g_out, ctx->gstream));
+    TC_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->g_out, 0));
+    return TC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,6 +336,10 @@ void tc_destroy(tc_ctx* ctx) {
     if (!ctx) return;
     for (hipEvent_t e : ctx->ev_pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(ctx);
+    if (ctx->g_in) (void)hipEventDestroy(ctx->g_in);
+    if (ctx->g_out) (void)hipEventDestroy(ctx->g_out);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
     delete ctx;
 }
 
@@ -292,20 +364,20 @@ int tc_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int dim,
     const size_t es = dtype == TC_F64 ? 8 : 4;
     if (!aligned(pos, es) || !aligned(mass, es)) return TC_EINVAL;
     if (!ctx->ws || ctx->ws_bytes < make_layout(n, dim, leaf_cap).total) return TC_EWORKSPACE;
-    return do_build(ctx, pos, mass, n, leaf_cap, dtype);
+    return do_build(ctx, pos, mass, n, leaf_cap, dtype, ctx->stream);
 }
 
 int tc_moments(tc_ctx* ctx) {
     if (!ctx) return TC_EINVAL;
     if (ctx->state < kBuilt) return TC_ESTATE;
-    return do_moments(ctx);
+    return do_moments(ctx, ctx->stream);
 }
 
 int tc_walk(tc_ctx* ctx, double theta) {
     if (!ctx) return TC_EINVAL;
     if (!(theta >= 0.0 && theta <= 1.0)) return TC_EINVAL;
     if (ctx->state < kMoments) return TC_ESTATE;
-    return do_walk(ctx, theta);
+    return do_walk(ctx, theta, ctx->stream);
 }
 
 int tc_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
@@ -330,15 +402,20 @@ int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
     const size_t es = ctx->dtype == TC_F64 ? 8 : 4;
     if (!aligned(pos, es) || !aligned(vel, es)) return TC_EINVAL;
     if (ctx->state < kForced) return TC_ESTATE;
-    const int f64 = ctx->dtype == TC_F64;
-    const float* acc = ctx->at<float>(ctx->lay.off_acc);
-    TC_HIP(ctx, launch_kick_drift(pos, vel, acc, ctx->n, ctx->dim, f64, dt, ctx->stream));
-    int rc = do_build(ctx, pos, ctx->mass, ctx->n, ctx->leaf_cap, ctx->dtype);
-    if (rc == TC_OK) rc = do_moments(ctx);
-    if (rc == TC_OK) rc = do_walk(ctx, ctx->theta);
-    if (rc == TC_OK) rc = do_forces(ctx, ctx->G, ctx->eps);
+    int rc = ctx->use_graph ? pre_force_graph(ctx, dt, pos, vel) : enqueue_pre_force(ctx, dt, pos, vel, ctx->stream);
     if (rc != TC_OK) return rc;
-    TC_HIP(ctx, launch_kick(vel, acc, ctx->n, ctx->dim, f64, dt, ctx->stream));
+    ctx->state = kWalked;
+    rc = do_forces(ctx, ctx->G, ctx->eps);
+    if (rc != TC_OK) return rc;
+    TC_HIP(ctx, launch_kick(vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, ctx->dtype == TC_F64, dt,
+                            ctx->stream));
+    return TC_OK;
+}
+
+int tc_set_graph(tc_ctx* ctx, int on) {
+    if (!ctx) return TC_EINVAL;
+    ctx->use_graph = on != 0;
+    if (!ctx->use_graph) drop_graph(ctx);
     return TC_OK;
 }
 
@@ -392,7 +469,7 @@ int tc_residuals(tc_ctx* ctx, double theta, double eps, const int32_t* targets, 
     if (!(theta > 0.0 && theta <= 1.0) || !(eps > 0.0) || !isfinite(eps)) return TC_EINVAL;
     if (ctx->dim != 3) return TC_EINVAL;
     if (ctx->state < kMoments) return TC_ESTATE;
-    int rc = do_walk(ctx, theta);
+    int rc = do_walk(ctx, theta, ctx->stream);
     if (rc != TC_OK) return rc;
     const Layout& l = ctx->lay;
     hipStream_t s = ctx->stream;
@@ -479,7 +556,7 @@ int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double 
     if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
     if (ctx->dim != 3) return TC_EINVAL;
     if (ctx->state < kMoments || !ctx->mlp_loaded) return TC_ESTATE;
-    int rc = do_walk(ctx, theta_l);
+    int rc = do_walk(ctx, theta_l, ctx->stream);
     if (rc != TC_OK) return rc;
     const Layout& l = ctx->lay;
     hipStream_t s = ctx->stream;

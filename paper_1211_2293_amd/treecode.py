@@ -72,6 +72,7 @@ def lib():
         "tc_mlp_forward": (i32, [P, P, i64, P, i64, P]),
         "tc_mlp_step": (i32, [P, P, P, i64, P, i64, dbl, C.POINTER(C.c_float), P]),
         "tc_direct": (i32, [P, P, i32, dbl, dbl, P, P]),
+        "tc_set_graph": (i32, [P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -368,6 +369,10 @@ class Treecode:
         pot = torch.empty(len(targets), dtype=torch.float64, device=dev)
         _check(lib().tc_direct(self._h, _ptr(targets), len(targets), float(G), float(eps), _ptr(acc), _ptr(pot)))
         return acc, pot
+
+    def set_graph(self, on: bool):
+        """Replay the pre-force part of leapfrog steps as a HIP graph (default on)."""
+        _check(lib().tc_set_graph(self._h, int(bool(on))))
 
     def set_timing(self, on: bool):
         _check(lib().tc_set_timing(self._h, int(bool(on))))
