@@ -282,10 +282,12 @@ def main():
     tc.forces(w.G, w.eps)
     torch.cuda.synchronize()
 
+    diags = []
+
     def step():
         tc.leapfrog(w.dt, pos, vel)
         if not args.no_diag:
-            tc.diag(vel)
+            diags.append(tc.diag(vel))
 
     for _ in range(args.warmup):
         step()
@@ -314,6 +316,14 @@ def main():
     log(f"{ms_per_step:.3f} ms/step, force kernel {kern_avg_ms:.3f} ms/launch ({launches} launches), "
         f"{inter / w.n:.0f} interactions/body, {achieved_tflops:.1f} TFLOP/s in the force kernel")
 
+    drift = None
+    if len(diags) >= 2:
+        d0, d1 = diags[0], diags[-1]
+        e0, e1 = d0[0] + d0[1], d1[0] + d1[1]
+        drift = {"steps": len(diags) - 1, "energy_rel": float((e1 - e0) / abs(e0)),
+                 "momentum": float(np.linalg.norm(d1[2:2 + w.dim] - d0[2:2 + w.dim])),
+                 "note": "FP64 diagnostics of the warm-up and timed steps: total energy E_kin + E_pot and "
+                         "momentum sum(m v), first to last step"}
     result = {
         "metric": METRIC,
         "value": evals_per_s,
@@ -337,6 +347,7 @@ def main():
         "interactions_per_s": inter / (ms_per_step * 1e-3),
         "interactions_per_eval": inter,
         "force_kernel_interactions_per_s": inter / (kern_avg_ms * 1e-3),
+        "diagnostics_drift": drift,
         "roofline": {
             "bound": "alu",
             "kernel": "k_walk_force",

@@ -116,6 +116,16 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * Results are the same as without the graph. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 
+/* Per-body accumulation in the force kernel of tc_forces and tc_leapfrog:
+ * TC_ACC_COMPENSATED (default) sums each chunk of 64 list entries in FP32
+ * and folds the chunk sums into Neumaier-compensated totals;
+ * TC_ACC_PLAIN keeps one running FP32 sum per component over the whole
+ * list (the uncompensated reference for precision studies).  The learned
+ * walk always compensates. */
+#define TC_ACC_COMPENSATED 0
+#define TC_ACC_PLAIN 1
+int tc_set_accumulation(tc_ctx *ctx, int mode);
+
 /* Switch the graph replay of tc_leapfrog on (default) or off (every kernel
  * launched on the context's stream).  Off also frees the recorded graph. */
 int tc_set_graph(tc_ctx *ctx, int on);

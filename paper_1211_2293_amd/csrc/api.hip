@@ -124,6 +124,7 @@ struct tc_ctx {
     bool mlp_loaded = false;
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = true;
+    bool plain_acc = false;    // uncompensated running sums (precision study)
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;
     hipGraphExec_t g_exec = nullptr;
@@ -253,7 +254,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
                                   ctx->n, ctx->dim, ctx->leaf_cap,
                                   (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
                                   ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
-                                  ctx->at<int64_t>(l.off_p2p), ctx->stream));
+                                  ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->stream));
     if (ctx->timing) {
         TC_HIP(ctx, hipEventRecord(e1, ctx->stream));
         ctx->ev_pending.push_back(e0);
@@ -409,6 +410,12 @@ int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
     if (rc != TC_OK) return rc;
     TC_HIP(ctx, launch_kick(vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, ctx->dtype == TC_F64, dt,
                             ctx->stream));
+    return TC_OK;
+}
+
+int tc_set_accumulation(tc_ctx* ctx, int mode) {
+    if (!ctx || (mode != TC_ACC_COMPENSATED && mode != TC_ACC_PLAIN)) return TC_EINVAL;
+    ctx->plain_acc = mode == TC_ACC_PLAIN;
     return TC_OK;
 }
 

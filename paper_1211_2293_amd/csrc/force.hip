@@ -32,7 +32,7 @@ namespace {
 using namespace walk;
 constexpr int kWavesPerBlock = 4;
 
-template <int D>
+template <int D, bool PLAIN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
                                                     const Body* __restrict__ bodies,
                                                     const float4* __restrict__ bodies32,
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 const int na = __popcll(A);
                 if (na) {
                     if (len + na > kListCap) {
-                        flush<D>(L, len, xi, yi, zi, eps2, a);
+                        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
                         len = 0;
                     }
                     if (accept)
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                             tot += cl;
                         }
                         if (len + tot > kListCap) {
-                            flush<D>(L, len, xi, yi, zi, eps2, a);
+                            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
                             len = 0;
                         }
                         if (jj < my_cnt)
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                         for (int o = 0; o < cl; o += kWave) {
                             const int m = min(kWave, cl - o);
                             if (len + m > kListCap) {
-                                flush<D>(L, len, xi, yi, zi, eps2, a);
+                                flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
                                 len = 0;
                             }
                             if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 wc = wcn;
                 vc = vcn;
             }
-            flush<D>(L, len, xi, yi, zi, eps2, a);
+            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
 
             if (valid) {
                 // the body met itself once as a direct entry: no force (zero
@@ -242,7 +242,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, hipStream_t s) {
+                             int64_t* p2p, bool plain, hipStream_t s) {
     (void)n;
     // as many blocks as can be resident at once (the waves are persistent)
     static int resident[2] = {0, 0};
@@ -252,8 +252,8 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3>, 256, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2>, 256, 0);
+            e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false>, 256, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2, false>, 256, 0);
         if (e != hipSuccess) return e;
         res = cus * (per_cu > 0 ? per_cu : 1);
     }
@@ -264,12 +264,17 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
     int lpl_log2 = 0;                                   // lanes per leaf: next power of two, <= 64
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
-    if (dim == 3)
-        hipLaunchKernelGGL(k_walk_force<3>, dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, queue,
-                           lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
-    else
-        hipLaunchKernelGGL(k_walk_force<2>, dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, queue,
-                           lpl_log2, G, eps2, prm, acc, pot, m2p, p2p);
+#define TC_LAUNCH_WF(DIM, PL)                                                                                      \
+    hipLaunchKernelGGL((k_walk_force<DIM, PL>), dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, \
+                       queue, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
+    if (dim == 3) {
+        if (plain) TC_LAUNCH_WF(3, true);
+        else TC_LAUNCH_WF(3, false);
+    } else {
+        if (plain) TC_LAUNCH_WF(2, true);
+        else TC_LAUNCH_WF(2, false);
+    }
+#undef TC_LAUNCH_WF
     return hipGetLastError();
 }
 

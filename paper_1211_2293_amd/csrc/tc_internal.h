@@ -133,7 +133,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, hipStream_t s);
+                             int64_t* p2p, bool plain, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
                            hipStream_t s);
 // closure.hip

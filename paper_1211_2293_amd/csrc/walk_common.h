@@ -52,8 +52,11 @@ struct Acc {
 };
 
 // Sum the first `cnt` list entries for this lane's body.  cnt is padded up
-// to a multiple of 8 with massless entries, which add exactly zero.
-template <int D>
+// to a multiple of 8 with massless entries, which add exactly zero.  By
+// default each chunk of 64 entries is summed plainly and folded into the
+// Neumaier-compensated totals; with PLAIN the whole list is one running
+// FP32 sum (the uncompensated reference of the precision study).
+template <int D, bool PLAIN = false>
 static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, float zi, float eps2, Acc& a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int padded = (cnt + 7) & ~7;
@@ -62,6 +65,12 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
     for (int e = 0; e < padded; e += kWave) {
         const int lim = min(kWave, padded - e);
         float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+        if (PLAIN) {
+            ax = a.sx;
+            ay = a.sy;
+            az = a.sz;
+            ap = a.sp;
+        }
         for (int k = 0; k < lim; k += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -84,10 +93,17 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
                 if (D == 3) az = fmaf(ms3, dz, az);
             }
         }
-        comp_add(a.sx, a.cx, ax);
-        comp_add(a.sy, a.cy, ay);
-        if (D == 3) comp_add(a.sz, a.cz, az);
-        comp_add(a.sp, a.cp, ap);
+        if (PLAIN) {
+            a.sx = ax;
+            a.sy = ay;
+            a.sz = az;
+            a.sp = ap;
+        } else {
+            comp_add(a.sx, a.cx, ax);
+            comp_add(a.sy, a.cy, ay);
+            if (D == 3) comp_add(a.sz, a.cz, az);
+            comp_add(a.sp, a.cp, ap);
+        }
     }
     wave_lds_sync();
 }

@@ -73,6 +73,7 @@ def lib():
         "tc_mlp_step": (i32, [P, P, P, i64, P, i64, dbl, C.POINTER(C.c_float), P]),
         "tc_direct": (i32, [P, P, i32, dbl, dbl, P, P]),
         "tc_set_graph": (i32, [P, i32]),
+        "tc_set_accumulation": (i32, [P, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -369,6 +370,10 @@ class Treecode:
         pot = torch.empty(len(targets), dtype=torch.float64, device=dev)
         _check(lib().tc_direct(self._h, _ptr(targets), len(targets), float(G), float(eps), _ptr(acc), _ptr(pot)))
         return acc, pot
+
+    def set_accumulation(self, compensated: bool):
+        """Compensated chunk sums (default) or one plain running FP32 sum."""
+        _check(lib().tc_set_accumulation(self._h, 0 if compensated else 1))
 
     def set_graph(self, on: bool):
         """Replay the pre-force part of leapfrog steps as a HIP graph (default on)."""
