@@ -239,7 +239,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--learned", type=lambda v: tuple(float(x) for x in v.split(",")), nargs="*",
-                    default=[(0.8, 0.5, float("inf")), (0.8, 0.5, 1e-3), (0.7, 0.5, float("inf"))],
+                    default=[(0.8, 0.5, float("inf")), (0.8, 0.5, 1e-3), (0.8, 0.5, 1e-2), (0.8, 0.5, 3e-2),
+                             (0.7, 0.5, float("inf")), (0.7, 0.5, 1e-2)],
                     help="theta_l,theta_p,tau triples")
     ap.add_argument("--no-diag", action="store_true", help="leave the diagnostics out of the step")
     ap.add_argument("--no-graph", action="store_true",

@@ -215,7 +215,8 @@ int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, int64_t nrows, c
  * monopole entry; a cell accepted at theta_l but opened at theta_p is a
  * learned cell.  For a learned cell the network loaded by tc_mlp_load
  * predicts, for each body of the walk group, the normalised residual yhat
- * (features as tc_residuals); if max |yhat| over the group exceeds tau the
+ * (features as tc_residuals); if the largest predicted residual relative to
+ * the monopole, |yhat| s^2 / |x - C|^2, over the group exceeds tau the
  * cell falls back to the plain walk of its subtree at theta_p, otherwise it
  * is a monopole entry plus G M s^2 yhat / |x - C|^4 per body (no softening).
  * tau = 0 gives exactly the plain walk at theta_p; tau = +inf gives the

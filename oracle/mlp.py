@@ -131,8 +131,9 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
     gets the network's correction G M s^2 yhat / |x - C|^4 for each of them
     (bfloat16 operands as on the GPU).  Returns a dict: corr [n][3] in
     original order, per_group (learned cells per walk group), and per
-    learned (group, cell) pair its group index and the largest |yhat| over
-    the group's bodies (the fallback test's statistic).  `groups` restricts
+    learned (group, cell) pair its group index and the largest predicted
+    residual relative to the monopole, |yhat| s^2 / |x - C|^2, over the
+    group's bodies (the fallback test's statistic).  `groups` restricts
     the work to those walk-group indices (the others get no corrections)."""
     n = tree.n
     c = tree.cells()
@@ -161,16 +162,16 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
     corr = np.zeros((n, 3))
     pair_group = np.array([p[0] for p in pairs], np.int64)
     pair_gmax = np.zeros(len(pairs))
-    rows, owners, weights, pidx = [], [], [], []
+    rows, owners, weights, pidx, ratios = [], [], [], [], []
 
     def run():
         F = np.concatenate(rows)
         y, _ = forward(params, F, bf16_ops=True)
         W = np.concatenate(weights)
         np.add.at(corr, np.concatenate(owners), G * W[:, None] * y)
-        nrm = np.sqrt((y * y).sum(1))
+        nrm = np.sqrt((y * y).sum(1)) * np.concatenate(ratios)
         np.maximum.at(pair_gmax, np.concatenate(pidx), nrm)
-        rows.clear(), owners.clear(), weights.clear(), pidx.clear()
+        rows.clear(), owners.clear(), weights.clear(), pidx.clear(), ratios.clear()
 
     held = 0
     for j, (g, cl) in enumerate(pairs):
@@ -187,6 +188,7 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
         dd = x - c["com"][cl]
         d2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
         weights.append(M * s * s / (d2 * d2))
+        ratios.append(s * s / d2)
         pidx.append(np.full(k, j))
         held += k
         if held >= chunk:

@@ -181,16 +181,12 @@ __global__ void k_inverse_perm(const uint32_t* __restrict__ perm, int64_t n, uin
 // --------------------------------------------------------------- network ----
 
 __device__ __forceinline__ uint16_t f2bf(float f) {        // round to nearest, ties to even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return gelu_f(z); }
 
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
-}
+__device__ __forceinline__ float gelu_grad(float z) { return gelu_grad_f(z); }
 
 // One 16x16 output tile of a product of BF16 matrices held in LDS:
 //   D(i, j) = sum_k A(i0 + i, k) B(k, j0 + j),  k < K (a multiple of 16),

@@ -8,8 +8,9 @@
 //           cell opened at theta_L is opened (children stay in mode L);
 //   mode P: the plain walk at theta_P (children stay in mode P).
 // For a learned cell the network predicts the normalised residual for each
-// of the group's bodies; if the largest |yhat| over the group exceeds tau
-// the cell falls back to the plain walk of its subtree at theta_P (its
+// of the group's bodies; if the largest predicted residual relative to the
+// monopole, |yhat| s^2 / |x - C|^2, over the group exceeds tau the cell falls
+// back to the plain walk of its subtree at theta_P (its
 // children in mode P, or its bodies directly if it is a leaf), otherwise it
 // enters as a monopole entry plus, per body, G M s^2 yhat / |x - C|^4 (the
 // network predicts the residual in units of the quadrupole scale).  With
@@ -45,12 +46,10 @@ struct NetT {                                         // transposed BF16 weights
 };
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest, ties to even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return gelu_f(z); }
 
 __device__ __forceinline__ short4_t pack_gelu(float4_t z, const float* b, int h0) {
     short4_t r;
@@ -300,16 +299,18 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                     const int64_t kc = bfs2pre[b];
                     const Moments& mo = mom[kc];
                     const double cx = mo.com[0], cy = mo.com[1], cz = mo.com[2], M = mo.M;
-                    const double s = ldexp(size, -cells[kc].level);
-                    const double qs = M * s * s;
+                    const int lev = cells[kc].level;
+                    const double s = ldexp(size, -lev);
+                    const double inv_s = ldexp(1.0 / size, lev);   // exact: size is a power of two
+                    const double iq = 1.0 / (M * s * s);
                     short4_t f4[4];
                     {
                         float f[16];
-                        f[0] = (float)((me.x - cx) / s);
-                        f[1] = (float)((me.y - cy) / s);
-                        f[2] = (float)((me.z - cz) / s);
+                        f[0] = (float)((me.x - cx) * inv_s);
+                        f[1] = (float)((me.y - cy) * inv_s);
+                        f[2] = (float)((me.z - cz) * inv_s);
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) f[3 + q] = (float)(mo.Q[q] / qs);
+                        for (int q = 0; q < 6; ++q) f[3 + q] = (float)(mo.Q[q] * iq);
                         f[9] = (float)log(M / mbar);
 #pragma unroll
                         for (int q = 10; q < 16; ++q) f[q] = 0.f;
@@ -323,8 +324,12 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                     wave_lds_sync();
                     float yh[3];
                     net_infer(N, xs, ys, yh);
-                    const float nrm = valid ? sqrtf(yh[0] * yh[0] + yh[1] * yh[1] + yh[2] * yh[2]) : 0.f;
-                    float gmax = nrm;
+                    // predicted residual relative to the monopole: |yhat| s^2 / |x - C|^2
+                    const double ex = me.x - cx, ey = me.y - cy, ez = me.z - cz;
+                    const double dd = (ex * ex + ey * ey) + ez * ez;
+                    const float ratio =
+                        valid ? sqrtf(yh[0] * yh[0] + yh[1] * yh[1] + yh[2] * yh[2]) * (float)(s * s / dd) : 0.f;
+                    float gmax = ratio;
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, kWave));
                     gmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(gmax)));
@@ -350,8 +355,6 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                         if (lane == 0)
                             L[len] = make_float4((float)(cx - rx), (float)(cy - ry), (float)(cz - rz), (float)M);
                         len += 1;
-                        const double ex = me.x - cx, ey = me.y - cy, ez = me.z - cz;
-                        const double dd = (ex * ex + ey * ey) + ez * ez;
                         const float w = (float)(M * s * s / (dd * dd));   // quadrupole scale
                         comp_add(kx, ckx, w * yh[0]);
                         comp_add(ky, cky, w * yh[1]);

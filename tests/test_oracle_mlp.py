@@ -151,17 +151,23 @@ def test_learned_corrections_with_a_constant_network():
     gb, gc = t.groups(64, 1024)
     _, size = t.root()
     ref = np.zeros(w.n)
+    gmax = []
     for g, (b, k) in enumerate(zip(gb, gc)):
         items = t.walk_items_range(0.7, b, b + k)
         acc_cells = items[items >= 0]
         assert r["per_group"][g] == len(acc_cells)
+        s2 = (size / 2.0 ** c["level"][acc_cells]) ** 2
+        ratio = np.zeros(len(acc_cells))
         for i in perm[b:b + k]:
             d = w.pos[i][None] - c["com"][acc_cells]
-            s2 = (size / 2.0 ** c["level"][acc_cells]) ** 2
-            ref[i] = 2.0 * (c["M"][acc_cells] * s2 / (d * d).sum(1) ** 2).sum()
+            d2 = (d * d).sum(1)
+            ref[i] = 2.0 * (c["M"][acc_cells] * s2 / d2 ** 2).sum()
+            ratio = np.maximum(ratio, s2 / d2)
+        gmax.append(ratio)
     np.testing.assert_allclose(r["corr"][:, 0], ref, rtol=1e-12)
     assert np.all(r["corr"][:, 1:] == 0.0)
-    assert np.allclose(r["pair_gmax"], 1.0)
+    # the fallback statistic: the largest |yhat| s^2 / d^2 over the group
+    np.testing.assert_allclose(r["pair_gmax"], np.concatenate(gmax), rtol=1e-12)
     # theta_p close to theta_l leaves few learned cells, never more
     r2 = mlp.learned_corrections(t, 0.7, 0.69, mlp.flatten(p))
     assert np.all(r2["per_group"] <= r["per_group"]) and r2["per_group"].sum() < r["per_group"].sum()
