@@ -243,8 +243,8 @@ def main():
                              (0.7, 0.5, float("inf")), (0.7, 0.5, 1e-2)],
                     help="theta_l,theta_p,tau triples")
     ap.add_argument("--no-diag", action="store_true", help="leave the diagnostics out of the step")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="launch every kernel of the step instead of replaying the pre-force graph")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the pre-force part of each step as a HIP graph")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -273,7 +273,7 @@ def main():
     vel = torch.from_numpy(w.vel).to(dev)
     mass = torch.from_numpy(w.mass).to(dev)
     tc = treecode.Treecode(w.dim, leaf_cap=w.leaf_cap)
-    tc.set_graph(not args.no_graph)
+    tc.set_graph(args.graph)
     log(f"workload {w.name}: n={w.n} dim={w.dim} theta={theta} eps={w.eps} leaf_cap={w.leaf_cap}")
 
     # initial force evaluation (part of set-up, not timed)

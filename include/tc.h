@@ -109,11 +109,11 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * place, dtype of tc_build, caller order): v += dt/2 a(x); x += dt v;
  * rebuild, moments, walk and forces at the new x with the last theta, G and
  * eps; v += dt/2 a(x').  Requires a previous tc_forces.
- * By default everything before the force kernel (about 70 short kernels) is
- * recorded once as a HIP graph and replayed on a stream private to the
- * context, ordered after and before the context's stream by events; it is
- * recorded again when pos, vel, the workspace, n, dt or theta change.
- * Results are the same as without the graph. */
+ * With tc_set_graph(ctx, 1) everything before the force kernel (about 70
+ * short kernels) is recorded once as a HIP graph and replayed on a stream
+ * private to the context, ordered after and before the context's stream by
+ * events; it is recorded again when pos, vel, the workspace, n, dt or theta
+ * change.  Results are the same as without the graph. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 
 /* Per-body accumulation in the force kernel of tc_forces and tc_leapfrog:
@@ -126,7 +126,7 @@ int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 #define TC_ACC_PLAIN 1
 int tc_set_accumulation(tc_ctx *ctx, int mode);
 
-/* Switch the graph replay of tc_leapfrog on (default) or off (every kernel
+/* Switch the graph replay of tc_leapfrog on or off (default: every kernel
  * launched on the context's stream).  Off also frees the recorded graph. */
 int tc_set_graph(tc_ctx *ctx, int on);
 

@@ -123,7 +123,7 @@ struct tc_ctx {
     int mlp_step = 0;          // Adam steps since the last tc_mlp_load
     bool mlp_loaded = false;
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
-    bool use_graph = true;
+    bool use_graph = false;
     bool plain_acc = false;    // uncompensated running sums (precision study)
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;

@@ -376,7 +376,7 @@ class Treecode:
         _check(lib().tc_set_accumulation(self._h, 0 if compensated else 1))
 
     def set_graph(self, on: bool):
-        """Replay the pre-force part of leapfrog steps as a HIP graph (default on)."""
+        """Replay the pre-force part of leapfrog steps as a HIP graph (default off)."""
         _check(lib().tc_set_graph(self._h, int(bool(on))))
 
     def set_timing(self, on: bool):
