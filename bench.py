@@ -12,6 +12,9 @@ After the timed steps (outside the timed region):
   * the relative force error E = sqrt(sum |a - a_ref|^2 / sum |a_ref|^2) of
     a fresh evaluation against the FP64 direct sum (computed on the GPU by
     tc_direct) on 8,192 seeded sample bodies;
+  * the same evaluations with per-body lists written to memory and summed
+    by a separate kernel (tc_lists_count / tc_lists_forces), over a theta
+    sweep;
   * for 3D workloads, the learned-vs-plain study on the initial positions:
     plain evaluations over a theta sweep (time per evaluation and E), the
     closure network trained on residuals generated at theta = 0.9 for 4,096
@@ -169,6 +172,39 @@ def learned_study(w, args):
                       "p99": e["p99"], "interactions_per_body": inter / w.n})
         log(f"  plain theta={th}: {ms:.3f} ms/eval, E={e['E']:.3e}, {inter / w.n:.0f} interactions/body")
     out = {"sample": f"{len(sample)} seeded bodies (seed 104), FP64 direct sum on the GPU", "plain": sweep}
+
+    # per-body lists written to HBM and summed (the treecode as the paper states it)
+    per_body = []
+    buf = None
+    for th in args.per_body_sweep:
+        tc.build(pos, mass)
+        tc.moments()
+        tc.walk(th)
+        total, _ = tc.lists_count()
+        if buf is None or buf.numel() < total:
+            buf = None
+            torch.cuda.empty_cache()
+            buf = torch.empty(int(total * 1.05) + 1, dtype=torch.int32, device=dev)
+
+        def run_pb():
+            tc.build(pos, mass)
+            tc.moments()
+            tc.walk(th)
+            tc.lists_count()
+            return tc.lists_forces(w.G, w.eps, lists=buf, want_pot=False)[0]
+
+        ms = time_evals(run_pb)
+        acc = run_pb().cpu().numpy()[sample]
+        e = rel_error(acc, ref)
+        per_body.append({"theta": th, "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "E": e["E"],
+                         "entries_per_body": total / w.n, "list_bytes": 4 * total,
+                         "grouped_evals_per_s_at_same_E": (None if interp_ms_at_error(sweep, e["E"]) is None
+                                                           else 1e3 / interp_ms_at_error(sweep, e["E"]))})
+        log(f"  per-body theta={th}: {ms:.3f} ms/eval, E={e['E']:.3e}, {total / w.n:.0f} entries/body, "
+            f"lists {4 * total / 1e9:.2f} GB")
+    del buf
+    torch.cuda.empty_cache()
+    out["per_body"] = per_body
     if w.dim != 3:
         return out
 
@@ -234,6 +270,7 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--sample", type=int, default=8192)
     ap.add_argument("--sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
+    ap.add_argument("--per-body-sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7])
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
     ap.add_argument("--epochs", type=int, default=40)

@@ -116,6 +116,28 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * change.  Results are the same as without the graph. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 
+/* ---- per-body lists (the treecode as §3.1 states it) ----------------------
+ * Every body walks the tree alone (its box is the point itself) at the
+ * opening radii of the last tc_walk, and its list of accepted cells and
+ * nearby bodies is written to memory before being summed.  The grouped walk
+ * of tc_forces is the fast path; this one measures what per-body lists cost
+ * and how accurate they are. */
+
+/* Count every body's list (one walk per body) and return the total number
+ * of entries in *total (host); counts (device u32 [n], bodies in key order,
+ * see tc_get_keys) may be NULL.  Synchronises.  Requires tc_walk. */
+int tc_lists_count(tc_ctx *ctx, int64_t *total, uint32_t *counts);
+
+/* Write the lists into `lists` (device u32, cap >= the total of the last
+ * tc_lists_count, else TC_EINVAL; body k's list follows body k-1's, bodies in
+ * key order; an entry is a cell's level-order index, or 0x80000000 | the
+ * key-order index of a body) and sum them: acc/pot as tc_forces (device,
+ * FP32, caller order, either may be NULL).  Entries are offsets from the body
+ * formed in FP64 and rounded to FP32; chunk sums are compensated and the
+ * wave's lanes reduced in FP64.  Requires tc_lists_count after the last
+ * tc_walk. */
+int tc_lists_forces(tc_ctx *ctx, double G, double eps, uint32_t *lists, int64_t cap, void *acc, void *pot);
+
 /* Per-body accumulation in the force kernel of tc_forces and tc_leapfrog:
  * TC_ACC_COMPENSATED (default) sums each chunk of 64 list entries in FP32
  * and folds the chunk sums into Neumaier-compensated totals;

@@ -96,6 +96,9 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_p2p = take(8 * (size_t)l.gmax);
     l.off_nlearn = take(8 * (size_t)l.gmax);
     l.off_nfall = take(8 * (size_t)l.gmax);
+    l.off_pb_cnt = take(4 * (size_t)n);
+    l.off_pb_off = take(8 * (size_t)(n + 1));
+    l.off_pb_part = take(8 * (size_t)((n + 4095) / 4096));
     l.total = off;
     return l;
 }
@@ -125,6 +128,8 @@ struct tc_ctx {
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = false;
     bool plain_acc = false;    // uncompensated running sums (precision study)
+    bool pb_counted = false;   // per-body list lengths of the current walk are known
+    int64_t pb_total = 0;
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;
     hipGraphExec_t g_exec = nullptr;
@@ -235,6 +240,7 @@ int do_walk(tc_ctx* ctx, double theta, hipStream_t s) {
                            s));
     ctx->theta = theta;
     ctx->state = kWalked;
+    ctx->pb_counted = false;
     return TC_OK;
 }
 
@@ -410,6 +416,50 @@ int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
     if (rc != TC_OK) return rc;
     TC_HIP(ctx, launch_kick(vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, ctx->dtype == TC_F64, dt,
                             ctx->stream));
+    return TC_OK;
+}
+
+int tc_lists_count(tc_ctx* ctx, int64_t* total, uint32_t* counts) {
+    if (!ctx || !total) return TC_EINVAL;
+    if (counts && !aligned(counts, 4)) return TC_EINVAL;
+    if (ctx->state < kWalked) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    uint64_t* offs = ctx->at<uint64_t>(l.off_pb_off);
+    TC_HIP(ctx, launch_pb_count(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies), ctx->n, ctx->dim,
+                                ctx->at<uint32_t>(l.off_pb_cnt), offs, ctx->at<uint64_t>(l.off_pb_part), s));
+    if (counts)
+        TC_HIP(ctx, hipMemcpyAsync(counts, ctx->at<uint32_t>(l.off_pb_cnt), 4 * (size_t)ctx->n,
+                                   hipMemcpyDeviceToDevice, s));
+    uint64_t tot = 0;
+    TC_HIP(ctx, hipMemcpyAsync(&tot, offs + ctx->n, sizeof(tot), hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    ctx->pb_total = (int64_t)tot;
+    ctx->pb_counted = true;
+    *total = (int64_t)tot;
+    return TC_OK;
+}
+
+int tc_lists_forces(tc_ctx* ctx, double G, double eps, uint32_t* lists, int64_t cap, void* acc, void* pot) {
+    if (!ctx || !lists || !aligned(lists, 4)) return TC_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
+    if (ctx->state < kWalked || !ctx->pb_counted) return TC_ESTATE;
+    if (cap < ctx->pb_total) return TC_EINVAL;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    TC_HIP(ctx, launch_pb_write_sum(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
+                                    ctx->at<uint32_t>(l.off_idx_a), ctx->n, ctx->dim, ctx->at<uint64_t>(l.off_pb_off),
+                                    lists, cap, l.cmax, (float)G, (float)(eps * eps), ctx->at<float>(l.off_acc),
+                                    ctx->at<float>(l.off_pot), s));
+    ctx->G = G;
+    ctx->eps = eps;
+    ctx->state = kForced;
+    if (acc)
+        TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * ctx->dim,
+                                   hipMemcpyDeviceToDevice, s));
+    if (pot)
+        TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n, hipMemcpyDeviceToDevice, s));
     return TC_OK;
 }
 

@@ -5,11 +5,12 @@
 // mass M, side s, traceless quadrupole Q), a correction predicted by a small
 // network from features of the pair:
 //   f = [(x - C)/s (3), Q/(M s^2) (6), ln(M/mbar) (1)],  mbar = total mass / n,
-//   yhat = MLP(f) (3),  a += G [ a_mono + (M/|x - C|^2) yhat ].
-// The training target is the normalised residual
-//   y = (a_exact - a_mono) |x - C|^2 / M   (G = 1),
+//   yhat = MLP(f) (3),  a += G [ a_mono + (M s^2/|x - C|^4) yhat ].
+// The training target is the residual in units of the quadrupole scale
+//   y = (a_exact - a_mono) |x - C|^4 / (M s^2)   (G = 1),
 // where a_exact sums the cell's bodies directly.  The network is
-// 10-64-64-3 with GELU (exact erf form); its products run on BF16
+// 10-64-64-3 with GELU (erf form, erf by Abramowitz and Stegun 7.1.26);
+// its products run on BF16
 // matrix-core instructions (16x16x16 tiles, FP32 accumulation) with FP32
 // master weights, trained by mean squared error and Adam.
 //

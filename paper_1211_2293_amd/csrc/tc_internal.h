@@ -87,7 +87,7 @@ struct Layout {
         off_walk, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
         off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
-        off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, total;
+        off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
     int64_t gmax;        // bound on walk groups
     int64_t cscan_tiles; // scan tiles over cmax cells
@@ -140,6 +140,12 @@ hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_
 struct MlpState;
 hipError_t launch_direct64(const Body* bodies, const uint32_t* inv_perm, int64_t n, const int32_t* targets, int nt,
                            double eps2, double G, DevParams* prm, double* acc, double* pot, hipStream_t s);
+// perbody.hip
+hipError_t launch_pb_count(const WalkCell* walk, const Body* bodies, int64_t n, int dim, uint32_t* counts,
+                           uint64_t* offs, uint64_t* part, hipStream_t s);
+hipError_t launch_pb_write_sum(const WalkCell* walk, const Body* bodies, const uint32_t* perm, int64_t n, int dim,
+                               const uint64_t* offs, uint32_t* lists, int64_t cap, int64_t cbound, float G,
+                               float eps2, float* acc, float* pot, hipStream_t s);
 hipError_t launch_inverse_perm(const uint32_t* perm, int64_t n, uint32_t* inv, hipStream_t s);
 hipError_t launch_residuals(bool write, const WalkCell* walk, const Body* bodies, const Cell* cells,
                             const Moments* mom, const uint32_t* bfs2pre, const uint32_t* inv_perm,

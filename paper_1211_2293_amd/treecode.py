@@ -74,6 +74,8 @@ def lib():
         "tc_direct": (i32, [P, P, i32, dbl, dbl, P, P]),
         "tc_set_graph": (i32, [P, i32]),
         "tc_set_accumulation": (i32, [P, i32]),
+        "tc_lists_count": (i32, [P, C.POINTER(C.c_int64), P]),
+        "tc_lists_forces": (i32, [P, dbl, dbl, P, i64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -370,6 +372,27 @@ class Treecode:
         pot = torch.empty(len(targets), dtype=torch.float64, device=dev)
         _check(lib().tc_direct(self._h, _ptr(targets), len(targets), float(G), float(eps), _ptr(acc), _ptr(pot)))
         return acc, pot
+
+    def lists_count(self, want_counts: bool = False):
+        """Per-body walks (count pass): total list entries and, optionally,
+        the per-body counts (u32 CUDA tensor, bodies in key order)."""
+        tot = C.c_int64()
+        cnt = torch.empty(self.n, dtype=torch.int32, device=self.stream.device) if want_counts else None
+        _check(lib().tc_lists_count(self._h, C.byref(tot), _ptr(cnt)))
+        return int(tot.value), cnt
+
+    def lists_forces(self, G: float = 1.0, eps: float = 1e-2, lists=None, want_pot=True):
+        """Per-body lists written to `lists` (u32/int32 CUDA tensor of at
+        least the counted total; allocated if None) and summed."""
+        dev = self.stream.device
+        if lists is None:
+            total, _ = self.lists_count()
+            lists = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        self._dev(lists, "lists")
+        acc = torch.empty((self.n, self.dim), dtype=torch.float32, device=dev)
+        pot = torch.empty(self.n, dtype=torch.float32, device=dev) if want_pot else None
+        _check(lib().tc_lists_forces(self._h, float(G), float(eps), _ptr(lists), lists.numel(), _ptr(acc), _ptr(pot)))
+        return acc, pot, lists
 
     def set_accumulation(self, compensated: bool):
         """Compensated chunk sums (default) or one plain running FP32 sum."""
