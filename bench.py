@@ -12,6 +12,8 @@ After the timed steps (outside the timed region):
   * the relative force error E = sqrt(sum |a - a_ref|^2 / sum |a_ref|^2) of
     a fresh evaluation against the FP64 direct sum (computed on the GPU by
     tc_direct) on 8,192 seeded sample bodies;
+  * the plain walk with every accepted cell's quadrupole term added, over a
+    theta sweep (the analytic control for the learned closure);
   * the same evaluations with per-body lists written to memory and summed
     by a separate kernel (tc_lists_count / tc_lists_forces), over a theta
     sweep;
@@ -173,6 +175,24 @@ def learned_study(w, args):
         log(f"  plain theta={th}: {ms:.3f} ms/eval, E={e['E']:.3e}, {inter / w.n:.0f} interactions/body")
     out = {"sample": f"{len(sample)} seeded bodies (seed 104), FP64 direct sum on the GPU", "plain": sweep}
 
+    # quadrupole terms on every accepted cell (the analytic control for the closure)
+    if w.dim == 3:
+        quad = []
+        tc.set_multipole(2)
+        for th in args.quad_sweep:
+            ms = time_evals(lambda: plain(th))
+            acc = plain(th).cpu().numpy()[sample]
+            e = rel_error(acc, ref)
+            pm = interp_ms_at_error(sweep, e["E"])
+            quad.append({"theta": th, "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "E": e["E"], "p99": e["p99"],
+                         "interactions_per_body": tc.interactions() / w.n,
+                         "plain_evals_per_s_at_same_E": None if pm is None else 1e3 / pm,
+                         "speedup_vs_plain_at_same_E": None if pm is None else pm / ms})
+            log(f"  quadrupole theta={th}: {ms:.3f} ms/eval, E={e['E']:.3e}, speedup at same E "
+                f"{quad[-1]['speedup_vs_plain_at_same_E']}")
+        tc.set_multipole(1)
+        out["quadrupole"] = quad
+
     # per-body lists written to HBM and summed (the treecode as the paper states it)
     per_body = []
     buf = None
@@ -271,6 +291,7 @@ def main():
     ap.add_argument("--sample", type=int, default=8192)
     ap.add_argument("--sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
     ap.add_argument("--per-body-sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7])
+    ap.add_argument("--quad-sweep", type=float, nargs="*", default=[0.5, 0.6, 0.7, 0.8, 0.9, 1.0])
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
     ap.add_argument("--epochs", type=int, default=40)

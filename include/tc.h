@@ -138,6 +138,14 @@ int tc_lists_count(tc_ctx *ctx, int64_t *total, uint32_t *counts);
  * tc_walk. */
 int tc_lists_forces(tc_ctx *ctx, double G, double eps, uint32_t *lists, int64_t cap, void *acc, void *pot);
 
+/* Expansion order of accepted cells in tc_forces and tc_leapfrog: 1 (the
+ * default) is the monopole of §3.1; 2 (3D only, else TC_EINVAL) adds each
+ * accepted cell's quadrupole term: with d the cell's centre of mass minus
+ * the body, s = (|d|^2 + eps^2)^{-1/2} and Q its traceless quadrupole
+ * (sum m (3 dd - |d|^2 I)), a += G [-Q d s^5 + (5/2) (d.Q d) d s^7] and
+ * phi -= (G/2) (d.Q d) s^5.  The walk and its counts are unchanged. */
+int tc_set_multipole(tc_ctx *ctx, int order);
+
 /* Per-body accumulation in the force kernel of tc_forces and tc_leapfrog:
  * TC_ACC_COMPENSATED (default) sums each chunk of 64 list entries in FP32
  * and folds the chunk sums into Neumaier-compensated totals;

@@ -62,7 +62,7 @@ def lib():
         L.orc_groups.restype = i64
         L.orc_walk_counts_ranges.argtypes = [P, dbl, i64, P, P, P, P]
         L.orc_walk_counts_ranges.restype = None
-        L.orc_tree_forces_ranges.argtypes = [P, dbl, dbl, dbl, i64, P, P, P, P]
+        L.orc_tree_forces_ranges.argtypes = [P, dbl, dbl, dbl, i64, P, P, i32, P, P]
         L.orc_tree_forces_ranges.restype = None
         L.orc_residuals.argtypes = [P, dbl, dbl, i64, P, i64, P, P, P, P, P]
         L.orc_residuals.restype = i64
@@ -215,26 +215,26 @@ class Tree:
                                      _p(m2p), _p(p2p))
         return m2p, p2p
 
-    def forces_groups(self, theta, gbeg, gcnt, G=1.0, eps=1e-3, acc=None, pot=None):
+    def forces_groups(self, theta, gbeg, gcnt, G=1.0, eps=1e-3, acc=None, pot=None, order=1):
         """Treecode forces of the bodies of the given groups, original
         order; bodies outside them keep the values in acc/pot (zeros by
-        default)."""
+        default).  order=2 adds every accepted cell's quadrupole term (3D)."""
         gbeg = np.ascontiguousarray(gbeg, np.int64)
         gcnt = np.ascontiguousarray(gcnt, np.int64)
         if acc is None:
             acc = np.zeros((self.n, self.dim))
         if pot is None:
             pot = np.zeros(self.n)
-        lib().orc_tree_forces_ranges(self._h, float(theta), G, eps, len(gbeg), _p(gbeg), _p(gcnt),
+        lib().orc_tree_forces_ranges(self._h, float(theta), G, eps, len(gbeg), _p(gbeg), _p(gcnt), int(order),
                                      _p(acc), _p(pot))
         return acc, pot
 
-    def walk_forces(self, theta, G=1.0, eps=1e-3, gs=64, cluster=1024):
+    def walk_forces(self, theta, G=1.0, eps=1e-3, gs=64, cluster=1024, order=1):
         """Treecode forces with the walk groups of the GPU path: runs of at
         most gs consecutive sorted bodies inside cluster cells of at most
         `cluster` bodies."""
         gb, gc = self.groups(gs, cluster)
-        return self.forces_groups(theta, gb, gc, G=G, eps=eps)
+        return self.forces_groups(theta, gb, gc, G=G, eps=eps, order=order)
 
     def walk_items_range(self, theta, b, e):
         cap = 1 << 16

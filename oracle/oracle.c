@@ -553,8 +553,15 @@ int64_t orc_walk_items(const orc_tree *t, double theta, int gs, int64_t g, int32
 /* Forces on the bodies of one group (sorted [b, e)): the sum over the
  * group's list of the softened point-mass interaction, cells as
  * pseudo-bodies of mass M at their centre of mass (§3.1). */
+/* Forces on the sorted bodies [b, e) from their group's walk.  With
+ * order 2 (3D) an accepted cell also contributes its quadrupole term: for
+ * d = C - x (cell centre of mass minus body), softened 1/r = s =
+ * (|d|^2 + eps^2)^{-1/2} and the traceless Q = sum m (3 dd - |d|^2 I),
+ *   a_Q = G [ -Q d s^5 + (5/2) (d.Q d) d s^7 ],  phi_Q = -(G/2) (d.Q d) s^5,
+ * the second term of the expansion of -G sum m / |x - x_j| about C with 1/r
+ * replaced by its softened value. */
 static void group_forces(const orc_tree *t, const double *rc, int64_t b, int64_t e, double G,
-                         double e2, double *acc, double *pot)
+                         double e2, int order, double *acc, double *pot)
 {
     const int D = t->dim;
     walk_out w = {0};
@@ -579,6 +586,16 @@ static void group_forces(const orc_tree *t, const double *rc, int64_t b, int64_t
                 p -= wv;
                 const double w3 = wv * inv * inv;
                 for (int q = 0; q < D; ++q) a[q] += w3 * d[q];
+                if (order == 2 && D == 3 && it >= 0) {
+                    const double *Q = t->Q + (int64_t)j * 6;     /* xx yy zz xy xz yz */
+                    const double qd[3] = {Q[0] * d[0] + Q[3] * d[1] + Q[4] * d[2],
+                                          Q[3] * d[0] + Q[1] * d[1] + Q[5] * d[2],
+                                          Q[4] * d[0] + Q[5] * d[1] + Q[2] * d[2]};
+                    const double dqd = d[0] * qd[0] + d[1] * qd[1] + d[2] * qd[2];
+                    const double s2 = inv * inv, s5 = s2 * s2 * inv, s7 = s5 * s2;
+                    for (int q = 0; q < 3; ++q) a[q] += -qd[q] * s5 + 2.5 * dqd * d[q] * s7;
+                    p -= 0.5 * dqd * s5;
+                }
             }
         }
         const int64_t o = t->perm[i];
@@ -619,20 +636,20 @@ void orc_tree_forces(const orc_tree *t, double theta, int gs, double G, double e
     for (int64_t s = 0; s < NG; ++s) {
         const int64_t g = groups ? groups[s] : s;
         const int64_t b = g * gs, e = (b + gs < t->n) ? b + gs : t->n;
-        group_forces(t, rc, b, e, G, eps * eps, acc, pot);
+        group_forces(t, rc, b, e, G, eps * eps, 1, acc, pot);
     }
     free(rc);
 }
 
 /* The same for explicit groups [gbeg[k], gbeg[k] + gcnt[k]), k < ng. */
 void orc_tree_forces_ranges(const orc_tree *t, double theta, double G, double eps, int64_t ng,
-                            const int64_t *gbeg, const int64_t *gcnt, double *acc, double *pot)
+                            const int64_t *gbeg, const int64_t *gcnt, int order, double *acc, double *pot)
 {
     double *rc = malloc(t->ncells * sizeof(double));
     orc_mac_radii(t, theta, rc);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < ng; ++k)
-        group_forces(t, rc, gbeg[k], gbeg[k] + gcnt[k], G, eps * eps, acc, pot);
+        group_forces(t, rc, gbeg[k], gbeg[k] + gcnt[k], G, eps * eps, order, acc, pot);
     free(rc);
 }
 

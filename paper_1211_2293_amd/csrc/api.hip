@@ -99,6 +99,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_pb_cnt = take(4 * (size_t)n);
     l.off_pb_off = take(8 * (size_t)(n + 1));
     l.off_pb_part = take(8 * (size_t)((n + 4095) / 4096));
+    l.off_walkq = take(32 * (size_t)l.cmax);
     l.total = off;
     return l;
 }
@@ -128,6 +129,7 @@ struct tc_ctx {
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = false;
     bool plain_acc = false;    // uncompensated running sums (precision study)
+    int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
     hipStream_t gstream = nullptr;
@@ -253,7 +255,13 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         if (!e0 || !e1) return hip_fail(ctx, hipErrorOutOfMemory);
         TC_HIP(ctx, hipEventRecord(e0, ctx->stream));
     }
-    TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), ctx->at<Body>(l.off_bodies),
+    float4* walkq = nullptr;
+    if (ctx->mp_order == 2 && ctx->dim == 3) {
+        walkq = ctx->at<float4>(l.off_walkq);
+        TC_HIP(ctx, launch_quad_pack(ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_pre2bfs), ctx->prm(), l.cmax,
+                                     walkq, ctx->stream));
+    }
+    TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
                                   ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                   ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
                                   ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
@@ -460,6 +468,12 @@ int tc_lists_forces(tc_ctx* ctx, double G, double eps, uint32_t* lists, int64_t 
                                    hipMemcpyDeviceToDevice, s));
     if (pot)
         TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n, hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+int tc_set_multipole(tc_ctx* ctx, int order) {
+    if (!ctx || (order != 1 && order != 2) || (order == 2 && ctx->dim != 3)) return TC_EINVAL;
+    ctx->mp_order = order;
     return TC_OK;
 }
 

@@ -32,8 +32,9 @@ namespace {
 using namespace walk;
 constexpr int kWavesPerBlock = 4;
 
-template <int D, bool PLAIN>
+template <int D, bool PLAIN, bool QUAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
+                                                    const float4* __restrict__ walkq,
                                                     const Body* __restrict__ bodies,
                                                     const float4* __restrict__ bodies32,
                                                     const uint32_t* __restrict__ perm,
@@ -49,12 +50,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
     static_assert(kStackCap >= kWave + kReserve + kWave, "stack too small for its bound");
 
+    static_assert(!QUAD || D == 3, "quadrupole terms are 3D");
     __shared__ float4 s_list[kWavesPerBlock][kListCap];
     __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
+    __shared__ float4 s_qlist[kWavesPerBlock][QUAD ? 3 * kQuadCap : 1];   // accepted cells with Q
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     const uint64_t lanes_below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     float4* L = s_list[wv];
     uint32_t* S = s_stack[wv];
+    float4* LQ = s_qlist[wv];
     const int lpl = 1 << lpl_log2;                       // lanes per leaf in a copy batch
     const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
 
@@ -92,7 +96,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
 
             Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            int len = 0;
+            int len = 0, qlen = 0;
             int64_t nm2p = 0, np2p = 0;
 
             // The root is the first batch.  Each round: opening tests, pushes,
@@ -102,6 +106,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             int top = 0;
             bool vc = lane == 0;
             WalkCell wc = load_cell(walk, 0u, vc);
+            float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;   // quadrupole of the tested cell
+            if (QUAD && vc) {
+                q0 = walkq[0];
+                q1 = walkq[1];
+            }
             bool more = true;
             while (more) {
                 // opening test: squared distance from the centre of mass to the box
@@ -128,6 +137,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 more = top > 0;
                 bool vcn = false;
                 WalkCell wcn;
+                float4 q0n = make_float4(0.f, 0.f, 0.f, 0.f), q1n = q0n;
                 if (more) {
                     const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
                     const int rr = lane / R, j = lane % R;
@@ -137,13 +147,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                     const int rlen = (int)(packed & 7u) + 1;
                     vcn = rr < nr && j < rlen;
                     wcn = load_cell(walk, (packed >> 3) + j, vcn);
+                    if (QUAD && vcn) {
+                        const uint32_t bq = (packed >> 3) + j;
+                        q0n = walkq[2 * (size_t)bq];
+                        q1n = walkq[2 * (size_t)bq + 1];
+                    }
                 }
                 wave_lds_sync();
 
                 // accepted cells: one entry each, at their centre of mass
                 const uint64_t A = __ballot(accept);
                 const int na = __popcll(A);
-                if (na) {
+                if (QUAD && na) {
+                    // with their quadrupole: 3 float4 per entry in the second list
+                    if (qlen + na > kQuadCap) {
+                        flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
+                        qlen = 0;
+                    }
+                    if (accept) {
+                        const int at = 3 * (qlen + __popcll(A & lanes_below));
+                        LQ[at] = make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
+                        LQ[at + 1] = q0;
+                        LQ[at + 2] = q1;
+                    }
+                    qlen += na;
+                    nm2p += na;
+                } else if (na) {
                     if (len + na > kListCap) {
                         flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
                         len = 0;
@@ -205,8 +234,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 wave_lds_sync();
                 wc = wcn;
                 vc = vcn;
+                if (QUAD) {
+                    q0 = q0n;
+                    q1 = q1n;
+                }
             }
             flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+            if (QUAD) flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
 
             if (valid) {
                 // the body met itself once as a direct entry: no force (zero
@@ -231,13 +265,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     }
 }
 
+// FP32 copy of each cell's traceless quadrupole in level order, two float4
+// per cell: (xx, yy, zz, xy), (xz, yz, 0, 0).
+__global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ mom,
+                                                   const uint32_t* __restrict__ pre2bfs,
+                                                   const DevParams* __restrict__ prm, int64_t cmax,
+                                                   float4* __restrict__ walkq) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C; k += (int64_t)gridDim.x * blockDim.x) {
+        const Moments& mo = mom[k];
+        const size_t b = 2 * (size_t)pre2bfs[k];
+        walkq[b] = make_float4((float)mo.Q[0], (float)mo.Q[1], (float)mo.Q[2], (float)mo.Q[3]);
+        walkq[b + 1] = make_float4((float)mo.Q[4], (float)mo.Q[5], 0.f, 0.f);
+    }
+}
+
 __global__ void k_reset_queue(uint32_t* queue) {
     if (threadIdx.x < kXcd) queue[threadIdx.x] = 0u;
 }
 
 }  // namespace
 
-hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const float4* bodies32,
+hipError_t launch_quad_pack(const Moments* mom, const uint32_t* pre2bfs, const DevParams* prm, int64_t cmax,
+                            float4* walkq, hipStream_t s) {
+    int64_t nb = (cmax + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_quad_pack, dim3((unsigned)nb), dim3(256), 0, s, mom, pre2bfs, prm, cmax, walkq);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Body* bodies, const float4* bodies32,
                              const uint32_t* perm,
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
@@ -245,15 +303,17 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
                              int64_t* p2p, bool plain, hipStream_t s) {
     (void)n;
     // as many blocks as can be resident at once (the waves are persistent)
-    static int resident[2] = {0, 0};
-    int& res = resident[dim == 3];
+    static int resident[3] = {0, 0, 0};                // 2D, 3D, 3D with quadrupoles
+    const int kind = dim == 3 ? (walkq ? 2 : 1) : 0;
+    int& res = resident[kind];
     if (res == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false>, 256, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2, false>, 256, 0);
+            e = kind == 2   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, true>, 256, 0)
+                : kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, false>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2, false, false>, 256, 0);
         if (e != hipSuccess) return e;
         res = cus * (per_cu > 0 ? per_cu : 1);
     }
@@ -264,15 +324,18 @@ hipError_t launch_walk_force(const WalkCell* walk, const Body* bodies, const flo
     int lpl_log2 = 0;                                   // lanes per leaf: next power of two, <= 64
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
-#define TC_LAUNCH_WF(DIM, PL)                                                                                      \
-    hipLaunchKernelGGL((k_walk_force<DIM, PL>), dim3(nb), dim3(256), 0, s, walk, bodies, bodies32, perm, gbeg, gcnt, \
-                       queue, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
-    if (dim == 3) {
-        if (plain) TC_LAUNCH_WF(3, true);
-        else TC_LAUNCH_WF(3, false);
+#define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
+    hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
+                       gbeg, gcnt, queue, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
+    if (dim == 3 && walkq) {
+        if (plain) TC_LAUNCH_WF(3, true, true);
+        else TC_LAUNCH_WF(3, false, true);
+    } else if (dim == 3) {
+        if (plain) TC_LAUNCH_WF(3, true, false);
+        else TC_LAUNCH_WF(3, false, false);
     } else {
-        if (plain) TC_LAUNCH_WF(2, true);
-        else TC_LAUNCH_WF(2, false);
+        if (plain) TC_LAUNCH_WF(2, true, false);
+        else TC_LAUNCH_WF(2, false, false);
     }
 #undef TC_LAUNCH_WF
     return hipGetLastError();

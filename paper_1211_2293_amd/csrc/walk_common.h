@@ -11,6 +11,7 @@ namespace walk {
 
 constexpr int kListCap = 256;     // LDS list entries per wave (16 B each)
 constexpr int kStackCap = 320;    // LDS range-stack entries per wave (4 B each)
+constexpr int kQuadCap = 64;      // LDS quadrupole-list entries per wave (48 B each)
 
 // Order LDS accesses of the lanes of one wave (a wave's LDS operations are
 // performed in program order; this keeps the compiler from reordering them).
@@ -102,6 +103,70 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
             comp_add(a.sx, a.cx, ax);
             comp_add(a.sy, a.cy, ay);
             if (D == 3) comp_add(a.sz, a.cz, az);
+            comp_add(a.sp, a.cp, ap);
+        }
+    }
+    wave_lds_sync();
+}
+
+// Sum the first `cnt` entries of a quadrupole list (3 float4 per entry:
+// offset and mass, (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0)) for this lane's
+// body: the monopole term plus, with d the entry's offset from the body and
+// s = (|d|^2 + eps^2)^{-1/2}, a += -Q d s^5 + (5/2) (d.Q d) d s^7 and
+// phi -= (1/2) (d.Q d) s^5.  Padded to a multiple of 8 with zero entries.
+template <bool PLAIN = false>
+static __device__ __forceinline__ void flush_quad(float4* LQ, int cnt, float xi, float yi, float zi, float eps2,
+                                                  Acc& a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int padded = (cnt + 7) & ~7;
+    for (int j = cnt + lane; j < padded; j += kWave) {
+        LQ[3 * j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        LQ[3 * j + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        LQ[3 * j + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_lds_sync();
+    for (int e = 0; e < padded; e += kWave) {
+        const int lim = min(kWave, padded - e);
+        float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+        if (PLAIN) {
+            ax = a.sx;
+            ay = a.sy;
+            az = a.sz;
+            ap = a.sp;
+        }
+        for (int k = 0; k < lim; k += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 p = LQ[3 * (e + k + u)];
+                const float4 qa = LQ[3 * (e + k + u) + 1];
+                const float4 qb = LQ[3 * (e + k + u) + 2];
+                const float dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                const float s = __builtin_amdgcn_rsqf(r2);
+                const float s2 = s * s;
+                const float ms = p.w * s;
+                const float ms3 = ms * s2;
+                const float qx = fmaf(qa.x, dx, fmaf(qa.w, dy, qb.x * dz));
+                const float qy = fmaf(qa.w, dx, fmaf(qa.y, dy, qb.y * dz));
+                const float qz = fmaf(qb.x, dx, fmaf(qb.y, dy, qa.z * dz));
+                const float dqd = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
+                const float s5 = (s2 * s2) * s;
+                const float c = fmaf(2.5f * dqd, s5 * s2, ms3);
+                ap -= fmaf(0.5f * dqd, s5, ms);
+                ax = fmaf(-qx, s5, fmaf(c, dx, ax));
+                ay = fmaf(-qy, s5, fmaf(c, dy, ay));
+                az = fmaf(-qz, s5, fmaf(c, dz, az));
+            }
+        }
+        if (PLAIN) {
+            a.sx = ax;
+            a.sy = ay;
+            a.sz = az;
+            a.sp = ap;
+        } else {
+            comp_add(a.sx, a.cx, ax);
+            comp_add(a.sy, a.cy, ay);
+            comp_add(a.sz, a.cz, az);
             comp_add(a.sp, a.cp, ap);
         }
     }

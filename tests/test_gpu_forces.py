@@ -112,3 +112,41 @@ def test_G_scales_linearly():
     g1 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2, G=1.0)
     g2 = gpu_tree(w.pos, w.mass, 16, theta=0.5, eps=1e-2, G=2.5)
     np.testing.assert_allclose(g2["acc"], 2.5 * g1["acc"], rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.8])
+def test_quadrupole_cells_match_oracle(theta):
+    """Accepted cells with their quadrupole term (tc_set_multipole(2)):
+    the same walk and counts, forces within 1e-5 of the oracle's second-order
+    expansion, and closer to the direct sum than the monopole walk."""
+    import torch
+    from paper_1211_2293_amd import treecode
+    from tests.gpu_util import to_dev
+    w = workloads.plummer_sphere(30000, seed=65)
+    tc = treecode.Treecode(3, leaf_cap=16)
+    keep = (to_dev(w.pos), to_dev(w.mass))
+    tc.build(*keep)
+    tc.moments()
+    tc.walk(theta)
+    a1, _ = tc.forces(1.0, 1e-2)
+    a1 = a1.cpu().numpy()
+    tc.set_multipole(2)
+    acc, pot = tc.forces(1.0, 1e-2)
+    m2p, p2p = (v.cpu().numpy() for v in tc.counts())
+    t = oracle.Tree(w.pos, w.mass, 16)
+    gb, gc = t.groups(64, 1024)
+    rm2p, rp2p = t.walk_counts_groups(theta, gb, gc)
+    np.testing.assert_array_equal(m2p, rm2p)
+    np.testing.assert_array_equal(p2p, rp2p)
+    a, p = t.forces_groups(theta, gb, gc, eps=1e-2, order=2)
+    ea, ep = oracle.rel_l2(acc.cpu().numpy(), a), oracle.rel_l2(pot.cpu().numpy(), p)
+    s = workloads.sample_indices(w.n, 2000, seed=66)
+    d, _ = oracle.direct(w.pos, w.mass, eps=1e-2, targets=s)
+    e1, e2 = oracle.rel_l2(a1[s], d), oracle.rel_l2(acc.cpu().numpy()[s], d)
+    print(f"theta={theta}: quadrupole vs oracle acc {ea:.2e} pot {ep:.2e}; E vs direct monopole {e1:.2e} "
+          f"quadrupole {e2:.2e}", flush=True)
+    assert ea < 1e-5 and ep < 1e-5
+    assert e2 < 0.5 * e1
+    tc.set_multipole(1)
+    b1, _ = tc.forces(1.0, 1e-2)
+    np.testing.assert_array_equal(b1.cpu().numpy(), a1)

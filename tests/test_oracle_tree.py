@@ -279,3 +279,73 @@ def test_selected_groups_match_full_forces():
     idx = oracle.group_bodies(t, sel)
     np.testing.assert_array_equal(a[idx], b[idx])
     np.testing.assert_array_equal(p[idx], q[idx])
+
+
+def _pair(R, a=1e-3):
+    # two equal bodies at C -+ a x (one tight leaf) and a light target at
+    # C + R x; light far bodies keep the tree non-trivial
+    C = np.array([0.3, 0.3, 0.3])
+    pos = np.array([C - [a, 0, 0], C + [a, 0, 0], C + [R, 0, 0],
+                    [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.0, 1.0, 0.0]])
+    mass = np.array([1.0, 1.0, 1e-12, 1e-12, 1e-12, 1e-12])
+    return pos, mass
+
+
+@pytest.mark.parametrize("R", [0.5, 0.6])
+def test_quadrupole_term_of_an_equal_pair(R):
+    """Seen along its axis from R, a pair of equal masses m at -+a pulls with
+    G m [1/(R-a)^2 + 1/(R+a)^2] = (2 G m / R^2)(1 + 3 a^2/R^2 + 5 a^4/R^4 + ...):
+    the monopole misses the 3 a^2/R^2 term, the quadrupole expansion of the
+    accepted cell recovers it up to O(a^4/R^4)."""
+    a = 1e-3
+    pos, mass = _pair(R, a)
+    t = oracle.Tree(pos, mass, leaf_cap=2)
+    p = t.sorted_positions(np.array([2]))
+    exact = 1.0 / (R - a) ** 2 + 1.0 / (R + a) ** 2
+    err = {}
+    for order in (1, 2):
+        acc, _ = t.forces_groups(0.9, p, np.array([1]), eps=1e-9, order=order)
+        m2p, _ = t.walk_counts_groups(0.9, p, np.array([1]))
+        assert m2p[0] >= 1                           # the pair's cell is accepted
+        err[order] = (-acc[2, 0] - exact) / exact
+    assert abs(err[1] / (-3 * a * a / R ** 2) - 1.0) < 1e-3
+    assert abs(err[2]) < 1e-9
+
+
+def test_quadrupole_force_is_minus_the_potential_gradient():
+    """a = -grad phi for the expansion with quadrupole terms (central
+    differences of the returned potential; the step is too small to change
+    any list)."""
+    rng = np.random.default_rng(122)
+    pos = rng.normal(size=(800, 3))
+    mass = rng.uniform(0.5, 1.5, 800)
+    t = oracle.Tree(pos, mass, 8)
+    k = 17
+    x = pos[k].copy()
+    h = 1e-6
+    a0, _ = t.forces_groups(0.8, t.sorted_positions(np.array([k])), np.array([1]), eps=1e-2, order=2)
+    grad = np.zeros(3)
+    for q in range(3):
+        ph = []
+        for sgn in (1, -1):
+            pp = pos.copy()
+            pp[k, q] = x[q] + sgn * h
+            tt = oracle.Tree(pp, mass, 8)
+            _, pot = tt.forces_groups(0.8, tt.sorted_positions(np.array([k])), np.array([1]), eps=1e-2, order=2)
+            ph.append(pot[k])
+        grad[q] = (ph[0] - ph[1]) / (2 * h)
+    np.testing.assert_allclose(a0[k], -grad, rtol=1e-6)
+
+
+def test_quadrupole_order_leaves_bodies_and_theta_zero_alone():
+    rng = np.random.default_rng(121)
+    pos = rng.normal(size=(1500, 3))
+    mass = rng.uniform(0.5, 1.5, 1500)
+    t = oracle.Tree(pos, mass, 8)
+    a0, p0 = t.walk_forces(0.0, eps=1e-2, order=2)
+    d, dp = oracle.direct(pos, mass, eps=1e-2)
+    assert oracle.rel_l2(a0, d) < 1e-12 and oracle.rel_l2(p0, dp) < 1e-12
+    # quadrupoles improve the treecode at a fixed opening angle
+    a1, _ = t.walk_forces(0.8, eps=1e-2)
+    a2, _ = t.walk_forces(0.8, eps=1e-2, order=2)
+    assert oracle.rel_l2(a2, d) < 0.5 * oracle.rel_l2(a1, d)
