@@ -94,14 +94,47 @@ def cpu_baseline(w, theta: float, min_seconds: float):
         if time.perf_counter() - t_start >= min_seconds or len(times) >= 50:
             break
     t_eval = float(np.median(times))
+    cores = oracle.num_threads()
+    # one core: the tree build plus a seeded sample of 1/32 of the walk groups,
+    # scaled to the whole evaluation
+    tree = oracle.Tree(w.pos, w.mass, w.leaf_cap)
+    gb, gc = tree.groups(64, 1024)
+    sel = np.sort(np.random.default_rng(1234).choice(len(gb), size=max(1, len(gb) // 32), replace=False))
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        t1_tree = oracle.Tree(w.pos, w.mass, w.leaf_cap)
+        t_b = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        t1_tree.forces_groups(theta, gb[sel], gc[sel], G=w.G, eps=w.eps)
+        t_f = (time.perf_counter() - t0) * len(gb) / len(sel)
+    finally:
+        oracle.set_num_threads(cores)
     return {
         "value": 1.0 / t_eval,
         "unit": "force-evals/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"FP64 oracle, {len(times)} whole force evaluation(s) of all {n} bodies (build + walk + "
                    f"forces, theta={theta}, OpenMP over walk groups), median {t_eval:.2f} s each"),
+        "single_core": {"value": 1.0 / (t_b + t_f), "unit": "force-evals/s", "cores": 1,
+                        "sample": f"build of all bodies ({t_b:.2f} s) + walk and forces of {len(sel)} of "
+                                  f"{len(gb)} seeded walk groups, scaled ({t_f:.2f} s)"},
     }
+
+
+def _clock_mhz():
+    """Peak shader clock reported by the HIP runtime (MHz), or None."""
+    try:
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        # hipDeviceAttributeClockRate: kHz
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0 and v.value > 0:
+            return v.value / 1000.0
+    except OSError:
+        pass
+    return None
 
 
 def rel_error(acc, ref):
@@ -301,6 +334,7 @@ def main():
                              (0.7, 0.5, float("inf")), (0.7, 0.5, 1e-2)],
                     help="theta_l,theta_p,tau triples")
     ap.add_argument("--no-diag", action="store_true", help="leave the diagnostics out of the step")
+    ap.add_argument("--no-split", action="store_true", help="one wave per walk group at every n")
     ap.add_argument("--graph", action="store_true",
                     help="replay the pre-force part of each step as a HIP graph")
     args = ap.parse_args()
@@ -332,6 +366,7 @@ def main():
     mass = torch.from_numpy(w.mass).to(dev)
     tc = treecode.Treecode(w.dim, leaf_cap=w.leaf_cap)
     tc.set_graph(args.graph)
+    tc.set_split(not args.no_split)
     log(f"workload {w.name}: n={w.n} dim={w.dim} theta={theta} eps={w.eps} leaf_cap={w.leaf_cap}")
 
     # initial force evaluation (part of set-up, not timed)
@@ -383,6 +418,10 @@ def main():
                  "momentum": float(np.linalg.norm(d1[2:2 + w.dim] - d0[2:2 + w.dim])),
                  "note": "FP64 diagnostics of the warm-up and timed steps: total energy E_kin + E_pot and "
                          "momentum sum(m v), first to last step"}
+    props = torch.cuda.get_device_properties(dev)
+    gpu = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+           "compute_units": props.multi_processor_count, "memory_gb": props.total_memory / 2 ** 30,
+           "hip": torch.version.hip, "clock_mhz": _clock_mhz()}
     result = {
         "metric": METRIC,
         "value": evals_per_s,
@@ -407,6 +446,7 @@ def main():
         "interactions_per_eval": inter,
         "force_kernel_interactions_per_s": inter / (kern_avg_ms * 1e-3),
         "diagnostics_drift": drift,
+        "gpu": gpu,
         "roofline": {
             "bound": "alu",
             "kernel": "k_walk_force",

@@ -138,6 +138,14 @@ int tc_lists_count(tc_ctx *ctx, int64_t *total, uint32_t *counts);
  * tc_walk. */
 int tc_lists_forces(tc_ctx *ctx, double G, double eps, uint32_t *lists, int64_t cap, void *acc, void *pot);
 
+/* Split walks (default on): for n <= 16384 the force evaluation of
+ * tc_forces and tc_leapfrog cuts each group's walk into one task per
+ * (level-1 cell, child) (64 in 3D, 16 in 2D) so that no single long walk
+ * bounds the time; the tasks' FP32 partial sums are added in FP64 in a
+ * fixed order.  The interactions and counts are those of the unsplit walk;
+ * only the summation order differs.  Off: one wave per group at any n. */
+int tc_set_split(tc_ctx *ctx, int on);
+
 /* Expansion order of accepted cells in tc_forces and tc_leapfrog: 1 (the
  * default) is the monopole of §3.1; 2 (3D only, else TC_EINVAL) adds each
  * accepted cell's quadrupole term: with d the cell's centre of mass minus

@@ -70,6 +70,8 @@ def lib():
         L.orc_sorted_positions.restype = None
         L.orc_walk_items_range.argtypes = [P, dbl, i64, i64, P, i64]
         L.orc_walk_items_range.restype = i64
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         _LIB = L
@@ -86,6 +88,10 @@ def _f64(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    lib().orc_set_num_threads(int(k))
 
 
 # --------------------------------------------------------------------------

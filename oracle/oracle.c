@@ -751,3 +751,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads used by later calls (benchmarking). */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}

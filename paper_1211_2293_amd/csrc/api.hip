@@ -100,6 +100,8 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_pb_off = take(8 * (size_t)(n + 1));
     l.off_pb_part = take(8 * (size_t)((n + 4095) / 4096));
     l.off_walkq = take(32 * (size_t)l.cmax);
+    // partial sums of the split walk (64 tasks per group in 3D, 16 in 2D)
+    l.off_split = n <= kSplitMaxN ? take(16 * (size_t)(dim == 3 ? 64 : 16) * (size_t)n) : 0;
     l.total = off;
     return l;
 }
@@ -130,6 +132,7 @@ struct tc_ctx {
     bool use_graph = false;
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
+    bool split = true;         // split walks when n <= kSplitMaxN
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
     hipStream_t gstream = nullptr;
@@ -261,14 +264,25 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, launch_quad_pack(ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_pre2bfs), ctx->prm(), l.cmax,
                                      walkq, ctx->stream));
     }
-    TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
-                                  ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
-                                  ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
-                                  ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
-                                  ctx->n, ctx->dim, ctx->leaf_cap,
-                                  (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
-                                  ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
-                                  ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->stream));
+    if (ctx->n <= kSplitMaxN && ctx->split) {
+        TC_HIP(ctx, launch_walk_force_split(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
+                                            ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
+                                            ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
+                                            ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->n, ctx->dim, ctx->leaf_cap,
+                                            (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float4>(l.off_split),
+                                            ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot),
+                                            ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p), ctx->plain_acc,
+                                            ctx->stream));
+    } else {
+        TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
+                                      ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
+                                      ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
+                                      ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
+                                      ctx->n, ctx->dim, ctx->leaf_cap,
+                                      (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
+                                      ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
+                                      ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->stream));
+    }
     if (ctx->timing) {
         TC_HIP(ctx, hipEventRecord(e1, ctx->stream));
         ctx->ev_pending.push_back(e0);
@@ -468,6 +482,12 @@ int tc_lists_forces(tc_ctx* ctx, double G, double eps, uint32_t* lists, int64_t 
                                    hipMemcpyDeviceToDevice, s));
     if (pot)
         TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n, hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+int tc_set_split(tc_ctx* ctx, int on) {
+    if (!ctx) return TC_EINVAL;
+    ctx->split = on != 0;
     return TC_OK;
 }
 

@@ -26,11 +26,178 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace tc {
 namespace {
 
 using namespace walk;
 constexpr int kWavesPerBlock = 4;
+
+// Walk for one group from the batch of cells [first, first + first_len) (the
+// root alone for a whole walk) and sum its list into a, counting the cell
+// entries in nm2p and the body entries in np2p.  The group's box is
+// [lo, hi], its FP32 origin (rx, ry, rz), this lane's body (xi, yi, zi).
+template <int D, bool PLAIN, bool QUAD>
+__device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, const float4* __restrict__ walkq,
+                                           const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
+                                           float4* L, uint32_t* S, float4* LQ, int lpl_log2, float eps2,
+                                           double lox, double hix, double loy, double hiy, double loz, double hiz,
+                                           double rx, double ry, double rz, float xi, float yi, float zi,
+                                           uint32_t first, int first_len, Acc& a, int64_t& nm2p, int64_t& np2p) {
+    constexpr int R = D == 3 ? 8 : 4;                    // lanes (cells) per popped range
+    constexpr int RP = kWave / R;                        // ranges per full round
+    constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
+    static_assert(kStackCap >= kWave + kReserve + kWave, "stack too small for its bound");
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lanes_below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    const int lpl = 1 << lpl_log2;                       // lanes per leaf in a copy batch
+    const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
+        int len = 0, qlen = 0;
+
+        // The first batch is the range [first, first + first_len).  Each round: opening tests, pushes,
+        // then the NEXT batch is popped and its cell loads issued before
+        // this round's entries and leaf bodies are staged, so the two
+        // memory round trips of a round overlap.
+        int top = 0;
+        bool vc = lane < first_len;
+        WalkCell wc = load_cell(walk, first + (uint32_t)lane, vc);
+        float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;   // quadrupole of the tested cell
+        if (QUAD && vc) {
+            q0 = walkq[2 * (size_t)(first + lane)];
+            q1 = walkq[2 * (size_t)(first + lane) + 1];
+        }
+        bool more = true;
+        while (more) {
+            // opening test: squared distance from the centre of mass to the box
+            const double dxm = fmax(fmax(lox - wc.cx, 0.0), wc.cx - hix);
+            const double dym = fmax(fmax(loy - wc.cy, 0.0), wc.cy - hiy);
+            double d2 = dxm * dxm + dym * dym;
+            if (D == 3) {
+                const double dzm = fmax(fmax(loz - wc.cz, 0.0), wc.cz - hiz);
+                d2 = d2 + dzm * dzm;
+            }
+            const bool leaf = vc && wc.b < 0;
+            const bool accept = vc && d2 > wc.rcrit2;
+            const bool opened = vc && !accept && !leaf;
+            const bool direct = leaf && !accept;
+
+            // push the children ranges of opened cells
+            const uint64_t O = __ballot(opened);
+            if (opened) S[top + __popcll(O & lanes_below)] = ((uint32_t)wc.a << 3) | (uint32_t)(wc.b - 1);
+            top += __popcll(O);
+            wave_lds_sync();
+
+            // pop the next batch (full batches only while the depth-first
+            // reserve is free) and start loading its cells
+            more = top > 0;
+            bool vcn = false;
+            WalkCell wcn;
+            float4 q0n = make_float4(0.f, 0.f, 0.f, 0.f), q1n = q0n;
+            if (more) {
+                const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
+                const int rr = lane / R, j = lane % R;
+                uint32_t packed = 0;
+                if (rr < nr) packed = S[top - 1 - rr];
+                top -= nr;
+                const int rlen = (int)(packed & 7u) + 1;
+                vcn = rr < nr && j < rlen;
+                wcn = load_cell(walk, (packed >> 3) + j, vcn);
+                if (QUAD && vcn) {
+                    const uint32_t bq = (packed >> 3) + j;
+                    q0n = walkq[2 * (size_t)bq];
+                    q1n = walkq[2 * (size_t)bq + 1];
+                }
+            }
+            wave_lds_sync();
+
+            // accepted cells: one entry each, at their centre of mass
+            const uint64_t A = __ballot(accept);
+            const int na = __popcll(A);
+            if (QUAD && na) {
+                // with their quadrupole: 3 float4 per entry in the second list
+                if (qlen + na > kQuadCap) {
+                    flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
+                    qlen = 0;
+                }
+                if (accept) {
+                    const int at = 3 * (qlen + __popcll(A & lanes_below));
+                    LQ[at] = make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
+                    LQ[at + 1] = q0;
+                    LQ[at + 2] = q1;
+                }
+                qlen += na;
+                nm2p += na;
+            } else if (na) {
+                if (len + na > kListCap) {
+                    flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                    len = 0;
+                }
+                if (accept)
+                    L[len + __popcll(A & lanes_below)] =
+                        make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
+                len += na;
+                nm2p += na;
+            }
+
+            // leaves that are not accepted: their bodies, copied cooperatively
+            const int cnt = direct ? (wc.b & 0x7fffffff) : 0;
+            const uint64_t P = __ballot(direct);
+            if (P) {
+                const uint64_t big = __ballot(direct && cnt > lpl);
+                uint64_t small = P & ~big;
+                while (small) {
+                    int my_begin = 0, my_cnt = 0, my_off = 0, tot = 0;
+                    for (int s = 0; s < (kWave >> lpl_log2) && small; ++s) {
+                        const int l = __builtin_ctzll(small);
+                        small &= small - 1;
+                        const int cl = __builtin_amdgcn_readlane(cnt, l);
+                        const int bl = __builtin_amdgcn_readlane(wc.a, l);
+                        if (slot == s) {
+                            my_begin = bl;
+                            my_cnt = cl;
+                            my_off = tot;
+                        }
+                        tot += cl;
+                    }
+                    if (len + tot > kListCap) {
+                        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                        len = 0;
+                    }
+                    if (jj < my_cnt)
+                        L[len + my_off + jj] = body_entry(bodies, bodies32, my_begin + jj, rx, ry, rz);
+                    len += tot;
+                    np2p += tot;
+                }
+                uint64_t bg = big;
+                while (bg) {                                   // leaves larger than a batch slot
+                    const int l = __builtin_ctzll(bg);
+                    bg &= bg - 1;
+                    const int cl = __builtin_amdgcn_readlane(cnt, l);
+                    const int bl = __builtin_amdgcn_readlane(wc.a, l);
+                    for (int o = 0; o < cl; o += kWave) {
+                        const int m = min(kWave, cl - o);
+                        if (len + m > kListCap) {
+                            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                            len = 0;
+                        }
+                        if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
+                        len += m;
+                    }
+                    np2p += cl;
+                }
+            }
+            wave_lds_sync();
+            wc = wcn;
+            vc = vcn;
+            if (QUAD) {
+                q0 = q0n;
+                q1 = q1n;
+            }
+        }
+        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+        if (QUAD) flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
+}
 
 template <int D, bool PLAIN, bool QUAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
@@ -45,22 +212,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                                                     float* __restrict__ acc, float* __restrict__ pot,
                                                     int64_t* __restrict__ m2p_out,
                                                     int64_t* __restrict__ p2p_out) {
-    constexpr int R = D == 3 ? 8 : 4;                    // lanes (cells) per popped range
-    constexpr int RP = kWave / R;                        // ranges per full round
-    constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
-    static_assert(kStackCap >= kWave + kReserve + kWave, "stack too small for its bound");
-
     static_assert(!QUAD || D == 3, "quadrupole terms are 3D");
     __shared__ float4 s_list[kWavesPerBlock][kListCap];
     __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
     __shared__ float4 s_qlist[kWavesPerBlock][QUAD ? 3 * kQuadCap : 1];   // accepted cells with Q
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    const uint64_t lanes_below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     float4* L = s_list[wv];
     uint32_t* S = s_stack[wv];
     float4* LQ = s_qlist[wv];
-    const int lpl = 1 << lpl_log2;                       // lanes per leaf in a copy batch
-    const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
 
     // Persistent waves.  The groups are split into one contiguous share per
     // XCD (blocks are dealt round-robin over the 8 XCDs, so block b runs on
@@ -96,151 +255,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
 
             Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            int len = 0, qlen = 0;
             int64_t nm2p = 0, np2p = 0;
-
-            // The root is the first batch.  Each round: opening tests, pushes,
-            // then the NEXT batch is popped and its cell loads issued before
-            // this round's entries and leaf bodies are staged, so the two
-            // memory round trips of a round overlap.
-            int top = 0;
-            bool vc = lane == 0;
-            WalkCell wc = load_cell(walk, 0u, vc);
-            float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;   // quadrupole of the tested cell
-            if (QUAD && vc) {
-                q0 = walkq[0];
-                q1 = walkq[1];
-            }
-            bool more = true;
-            while (more) {
-                // opening test: squared distance from the centre of mass to the box
-                const double dxm = fmax(fmax(lox - wc.cx, 0.0), wc.cx - hix);
-                const double dym = fmax(fmax(loy - wc.cy, 0.0), wc.cy - hiy);
-                double d2 = dxm * dxm + dym * dym;
-                if (D == 3) {
-                    const double dzm = fmax(fmax(loz - wc.cz, 0.0), wc.cz - hiz);
-                    d2 = d2 + dzm * dzm;
-                }
-                const bool leaf = vc && wc.b < 0;
-                const bool accept = vc && d2 > wc.rcrit2;
-                const bool opened = vc && !accept && !leaf;
-                const bool direct = leaf && !accept;
-
-                // push the children ranges of opened cells
-                const uint64_t O = __ballot(opened);
-                if (opened) S[top + __popcll(O & lanes_below)] = ((uint32_t)wc.a << 3) | (uint32_t)(wc.b - 1);
-                top += __popcll(O);
-                wave_lds_sync();
-
-                // pop the next batch (full batches only while the depth-first
-                // reserve is free) and start loading its cells
-                more = top > 0;
-                bool vcn = false;
-                WalkCell wcn;
-                float4 q0n = make_float4(0.f, 0.f, 0.f, 0.f), q1n = q0n;
-                if (more) {
-                    const int nr = (top + kWave + kReserve <= kStackCap) ? min(top, RP) : 1;
-                    const int rr = lane / R, j = lane % R;
-                    uint32_t packed = 0;
-                    if (rr < nr) packed = S[top - 1 - rr];
-                    top -= nr;
-                    const int rlen = (int)(packed & 7u) + 1;
-                    vcn = rr < nr && j < rlen;
-                    wcn = load_cell(walk, (packed >> 3) + j, vcn);
-                    if (QUAD && vcn) {
-                        const uint32_t bq = (packed >> 3) + j;
-                        q0n = walkq[2 * (size_t)bq];
-                        q1n = walkq[2 * (size_t)bq + 1];
-                    }
-                }
-                wave_lds_sync();
-
-                // accepted cells: one entry each, at their centre of mass
-                const uint64_t A = __ballot(accept);
-                const int na = __popcll(A);
-                if (QUAD && na) {
-                    // with their quadrupole: 3 float4 per entry in the second list
-                    if (qlen + na > kQuadCap) {
-                        flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
-                        qlen = 0;
-                    }
-                    if (accept) {
-                        const int at = 3 * (qlen + __popcll(A & lanes_below));
-                        LQ[at] = make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
-                        LQ[at + 1] = q0;
-                        LQ[at + 2] = q1;
-                    }
-                    qlen += na;
-                    nm2p += na;
-                } else if (na) {
-                    if (len + na > kListCap) {
-                        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
-                        len = 0;
-                    }
-                    if (accept)
-                        L[len + __popcll(A & lanes_below)] =
-                            make_float4((float)(wc.cx - rx), (float)(wc.cy - ry), (float)(wc.cz - rz), wc.m);
-                    len += na;
-                    nm2p += na;
-                }
-
-                // leaves that are not accepted: their bodies, copied cooperatively
-                const int cnt = direct ? (wc.b & 0x7fffffff) : 0;
-                const uint64_t P = __ballot(direct);
-                if (P) {
-                    const uint64_t big = __ballot(direct && cnt > lpl);
-                    uint64_t small = P & ~big;
-                    while (small) {
-                        int my_begin = 0, my_cnt = 0, my_off = 0, tot = 0;
-                        for (int s = 0; s < (kWave >> lpl_log2) && small; ++s) {
-                            const int l = __builtin_ctzll(small);
-                            small &= small - 1;
-                            const int cl = __builtin_amdgcn_readlane(cnt, l);
-                            const int bl = __builtin_amdgcn_readlane(wc.a, l);
-                            if (slot == s) {
-                                my_begin = bl;
-                                my_cnt = cl;
-                                my_off = tot;
-                            }
-                            tot += cl;
-                        }
-                        if (len + tot > kListCap) {
-                            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
-                            len = 0;
-                        }
-                        if (jj < my_cnt)
-                            L[len + my_off + jj] = body_entry(bodies, bodies32, my_begin + jj, rx, ry, rz);
-                        len += tot;
-                        np2p += tot;
-                    }
-                    uint64_t bg = big;
-                    while (bg) {                                   // leaves larger than a batch slot
-                        const int l = __builtin_ctzll(bg);
-                        bg &= bg - 1;
-                        const int cl = __builtin_amdgcn_readlane(cnt, l);
-                        const int bl = __builtin_amdgcn_readlane(wc.a, l);
-                        for (int o = 0; o < cl; o += kWave) {
-                            const int m = min(kWave, cl - o);
-                            if (len + m > kListCap) {
-                                flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
-                                len = 0;
-                            }
-                            if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
-                            len += m;
-                        }
-                        np2p += cl;
-                    }
-                }
-                wave_lds_sync();
-                wc = wcn;
-                vc = vcn;
-                if (QUAD) {
-                    q0 = q0n;
-                    q1 = q1n;
-                }
-            }
-            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
-            if (QUAD) flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
+            walk_group<D, PLAIN, QUAD>(walk, walkq, bodies, bodies32, L, S, LQ, lpl_log2, eps2, lox, hix, loy, hiy,
+                                       loz, hiz, rx, ry, rz, xi, yi, zi, 0u, 1, a, nm2p, np2p);
 
             if (valid) {
                 // the body met itself once as a direct entry: no force (zero
@@ -262,6 +279,118 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
                            (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
         }
+    }
+}
+
+// Split walks for small N, where the longest single group otherwise bounds
+// the kernel: the walk of group g is cut into kSplitTasks<D> tasks, one per
+// (level-1 cell k, child slot j).  If cell k is accepted or is a leaf, task
+// (k, 0) walks it and the other slots of k do nothing; if k is opened, task
+// (k, j) walks its j-th child.  Together the tasks visit exactly the cells
+// and bodies of the unsplit walk (the root is never accepted for a group
+// inside it).  Each task writes its FP32 sums for the group's bodies to its
+// own slice of part; k_split_reduce adds the slices in FP64 in task order.
+template <int D>
+constexpr int kSplitTasks = D == 3 ? 64 : 16;
+
+template <int D, bool PLAIN, bool QUAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force_split(
+    const WalkCell* __restrict__ walk, const float4* __restrict__ walkq, const Body* __restrict__ bodies,
+    const float4* __restrict__ bodies32, const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
+    int lpl_log2, float eps2, const DevParams* __restrict__ prm, int64_t n, float4* __restrict__ part,
+    unsigned long long* __restrict__ m2p_out, unsigned long long* __restrict__ p2p_out) {
+    constexpr int R = D == 3 ? 8 : 4;
+    constexpr int T = kSplitTasks<D>;
+    __shared__ float4 s_list[kWavesPerBlock][kListCap];
+    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
+    __shared__ float4 s_qlist[kWavesPerBlock][QUAD ? 3 * kQuadCap : 1];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t g = task / T;
+    const int t = (int)(task % T);
+    if (g >= (int64_t)prm->ngroups) return;
+    const int64_t i0 = gbeg[g];
+    const int gn = gcnt[g];
+    const int64_t i = i0 + lane;
+    const bool valid = lane < gn;
+    const Body me = bodies[valid ? i : i0];
+    const double lox = uniform(wave_min(me.x)), hix = uniform(wave_max(me.x));
+    const double loy = uniform(wave_min(me.y)), hiy = uniform(wave_max(me.y));
+    const double loz = D == 3 ? uniform(wave_min(me.z)) : 0.0;
+    const double hiz = D == 3 ? uniform(wave_max(me.z)) : 0.0;
+    const double rx = (lox + hix) * 0.5, ry = (loy + hiy) * 0.5, rz = (loz + hiz) * 0.5;
+    const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
+
+    // this task's first batch: one cell or nothing
+    uint32_t first = 0;
+    int first_len = 0;
+    const WalkCell root = walk[0];
+    if (root.b < 0) {                                    // the root is a leaf
+        first_len = t == 0 ? 1 : 0;
+    } else {
+        const int k = t / R, j = t % R;
+        if (k < root.b) {
+            const uint32_t c1 = (uint32_t)root.a + (uint32_t)k;
+            const WalkCell w1 = walk[c1];
+            const double dxm = fmax(fmax(lox - w1.cx, 0.0), w1.cx - hix);
+            const double dym = fmax(fmax(loy - w1.cy, 0.0), w1.cy - hiy);
+            double d2 = dxm * dxm + dym * dym;
+            if (D == 3) {
+                const double dzm = fmax(fmax(loz - w1.cz, 0.0), w1.cz - hiz);
+                d2 = d2 + dzm * dzm;
+            }
+            if (d2 > w1.rcrit2 || w1.b < 0) {
+                first = c1;
+                first_len = j == 0 ? 1 : 0;
+            } else if (j < w1.b) {
+                first = (uint32_t)w1.a + (uint32_t)j;
+                first_len = 1;
+            }
+        }
+    }
+    Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int64_t nm2p = 0, np2p = 0;
+    walk_group<D, PLAIN, QUAD>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv], lpl_log2, eps2,
+                               lox, hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi, first, first_len, a, nm2p,
+                               np2p);
+    if (valid)
+        part[(int64_t)t * n + i] = make_float4(a.sx + a.cx, a.sy + a.cy, a.sz + a.cz, a.sp + a.cp);
+    if (lane == 0 && (nm2p | np2p)) {
+        atomicAdd(&m2p_out[g], (unsigned long long)nm2p);
+        atomicAdd(&p2p_out[g], (unsigned long long)np2p);
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_split_reduce(const float4* __restrict__ part, const Body* __restrict__ bodies,
+                                                      const uint32_t* __restrict__ perm, int64_t n, float G,
+                                                      float eps2, float* __restrict__ acc, float* __restrict__ pot) {
+    constexpr int T = kSplitTasks<D>;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
+        for (int t = 0; t < T; ++t) {
+            const float4 v = part[(int64_t)t * n + i];
+            ax += v.x;
+            ay += v.y;
+            az += v.z;
+            ap += v.w;
+        }
+        // the body met itself once as a direct entry: its -m/eps potential
+        // term is removed as in the unsplit kernel
+        const float mself = (float)bodies[i].m;
+        ap += (double)(mself * __builtin_amdgcn_rsqf(eps2));
+        const int64_t o = perm[i];
+        acc[o * D + 0] = (float)((double)G * ax);
+        acc[o * D + 1] = (float)((double)G * ay);
+        if (D == 3) acc[o * D + 2] = (float)((double)G * az);
+        pot[o] = (float)((double)G * ap);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ a, unsigned long long* __restrict__ b, int64_t k) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+        a[i] = 0ull;
+        b[i] = 0ull;
     }
 }
 
@@ -292,6 +421,40 @@ hipError_t launch_quad_pack(const Moments* mom, const uint32_t* pre2bfs, const D
     int64_t nb = (cmax + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_quad_pack, dim3((unsigned)nb), dim3(256), 0, s, mom, pre2bfs, prm, cmax, walkq);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, const Body* bodies,
+                                   const float4* bodies32, const uint32_t* perm, const int32_t* gbeg,
+                                   const int32_t* gcnt, int64_t gmax, int64_t n, int dim, int leaf_cap, float G,
+                                   float eps2, const DevParams* prm, float4* part, float* acc, float* pot,
+                                   int64_t* m2p, int64_t* p2p, bool plain, hipStream_t s) {
+    int lpl_log2 = 0;
+    while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
+    unsigned long long* c1 = reinterpret_cast<unsigned long long*>(m2p);
+    unsigned long long* c2 = reinterpret_cast<unsigned long long*>(p2p);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((gmax + 255) / 256)), dim3(256), 0, s, c1, c2, gmax);
+    const int T = dim == 3 ? kSplitTasks<3> : kSplitTasks<2>;
+    const unsigned nb = (unsigned)((gmax * T + kWavesPerBlock - 1) / kWavesPerBlock);
+#define TC_LAUNCH_SPLIT(DIM, PL, QU)                                                                               \
+    hipLaunchKernelGGL((k_walk_force_split<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, \
+                       gbeg, gcnt, lpl_log2, eps2, prm, n, part, c1, c2)
+    if (dim == 3 && walkq) {
+        if (plain) TC_LAUNCH_SPLIT(3, true, true);
+        else TC_LAUNCH_SPLIT(3, false, true);
+    } else if (dim == 3) {
+        if (plain) TC_LAUNCH_SPLIT(3, true, false);
+        else TC_LAUNCH_SPLIT(3, false, false);
+    } else {
+        if (plain) TC_LAUNCH_SPLIT(2, true, false);
+        else TC_LAUNCH_SPLIT(2, false, false);
+    }
+#undef TC_LAUNCH_SPLIT
+    const unsigned rb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (dim == 3)
+        hipLaunchKernelGGL(k_split_reduce<3>, dim3(rb), dim3(256), 0, s, part, bodies, perm, n, G, eps2, acc, pot);
+    else
+        hipLaunchKernelGGL(k_split_reduce<2>, dim3(rb), dim3(256), 0, s, part, bodies, perm, n, G, eps2, acc, pot);
     return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ def lib():
         "tc_set_graph": (i32, [P, i32]),
         "tc_set_accumulation": (i32, [P, i32]),
         "tc_set_multipole": (i32, [P, i32]),
+        "tc_set_split": (i32, [P, i32]),
         "tc_lists_count": (i32, [P, C.POINTER(C.c_int64), P]),
         "tc_lists_forces": (i32, [P, dbl, dbl, P, i64, P, P]),
     }
@@ -394,6 +395,10 @@ class Treecode:
         pot = torch.empty(self.n, dtype=torch.float32, device=dev) if want_pot else None
         _check(lib().tc_lists_forces(self._h, float(G), float(eps), _ptr(lists), lists.numel(), _ptr(acc), _ptr(pot)))
         return acc, pot, lists
+
+    def set_split(self, on: bool):
+        """Split walks for n <= 16384 (default on)."""
+        _check(lib().tc_set_split(self._h, int(bool(on))))
 
     def set_multipole(self, order: int):
         """1: monopole cells (default); 2: add quadrupole terms (3D)."""
