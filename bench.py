@@ -361,6 +361,13 @@ def main():
     theta = w.theta if args.theta is None else args.theta
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # a created stream (default priority): graph replay can record on it
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        return run(args, w, theta, dev, treecode, workloads, torch)
+
+
+def run(args, w, theta, dev, treecode, workloads, torch):
     pos = torch.from_numpy(w.pos).to(dev)
     vel = torch.from_numpy(w.vel).to(dev)
     mass = torch.from_numpy(w.mass).to(dev)

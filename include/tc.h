@@ -110,10 +110,11 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * rebuild, moments, walk and forces at the new x with the last theta, G and
  * eps; v += dt/2 a(x').  Requires a previous tc_forces.
  * With tc_set_graph(ctx, 1) everything before the force kernel (about 70
- * short kernels) is recorded once as a HIP graph and replayed on a stream
- * private to the context, ordered after and before the context's stream by
- * events; it is recorded again when pos, vel, the workspace, n, dt or theta
- * change.  Results are the same as without the graph. */
+ * short kernels) is recorded once as a HIP graph and replayed: on the
+ * context's stream if it is a created stream, else (the null stream cannot
+ * be recorded) on a stream private to the context, ordered after and before
+ * the context's stream by events.  It is recorded again when pos, vel, the
+ * workspace, n, dt or theta change.  Results are the same as without it. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 
 /* ---- per-body lists (the treecode as §3.1 states it) ----------------------

@@ -310,23 +310,26 @@ void drop_graph(tc_ctx* ctx) {
     ctx->g_exec = nullptr;
 }
 
-// Replays the pre-force part as one graph launch on a private stream,
-// ordered after and before the context's stream by events.  The graph is
+// Replays the pre-force part as one graph launch: on the context's stream
+// when that is a created stream, else (the null stream cannot be captured)
+// on a private stream ordered after and before it by events.  The graph is
 // (re)captured whenever anything it bakes in (buffers, sizes, dt, theta)
 // changes.  Returns TC_OK, or an error with nothing enqueued.
 int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
     tc_ctx::GraphKey key{pos, vel, ctx->mass, ctx->ws, ctx->n, ctx->dim, ctx->dtype, ctx->leaf_cap, dt, ctx->theta};
-    if (!ctx->gstream) {
+    const bool own = ctx->stream != nullptr;
+    if (!own && !ctx->gstream) {
         TC_HIP(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
         TC_HIP(ctx, hipEventCreateWithFlags(&ctx->g_in, hipEventDisableTiming));
         TC_HIP(ctx, hipEventCreateWithFlags(&ctx->g_out, hipEventDisableTiming));
     }
+    hipStream_t cs = own ? ctx->stream : ctx->gstream;
     if (!ctx->g_exec || !(key == ctx->g_key)) {
         drop_graph(ctx);
-        TC_HIP(ctx, hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeRelaxed));
-        const int rc = enqueue_pre_force(ctx, dt, pos, vel, ctx->gstream);
+        TC_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        const int rc = enqueue_pre_force(ctx, dt, pos, vel, cs);
         hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(ctx->gstream, &g);
+        const hipError_t e = hipStreamEndCapture(cs, &g);
         if (rc != TC_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return rc != TC_OK ? rc : hip_fail(ctx, e);
@@ -338,6 +341,10 @@ int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
             return hip_fail(ctx, ei);
         }
         ctx->g_key = key;
+    }
+    if (own) {
+        TC_HIP(ctx, hipGraphLaunch(ctx->g_exec, ctx->stream));
+        return TC_OK;
     }
     TC_HIP(ctx, hipEventRecord(ctx->g_in, ctx->stream));
     TC_HIP(ctx, hipStreamWaitEvent(ctx->gstream, ctx->g_in, 0));

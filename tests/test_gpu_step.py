@@ -121,13 +121,21 @@ def test_call_order_on_device():
     assert tc.status() == 0
 
 
-def test_graph_replay_matches_eager_launches():
+@pytest.mark.parametrize("created_stream", [False, True])
+def test_graph_replay_matches_eager_launches(created_stream):
     """Leapfrog steps with the pre-force part replayed as a graph give the
     same bits as launching every kernel; the graph is recorded again when
-    the buffers or dt change, and eager work in between is ordered."""
+    the buffers or dt change, and eager work in between is ordered.  On the
+    null stream the graph runs on a private stream behind events, on a
+    created stream it is recorded and replayed on that stream."""
     w = workloads.plummer_sphere(30000, seed=71)
+    stream = torch.cuda.Stream() if created_stream else torch.cuda.current_stream()
 
     def run(graph):
+        with torch.cuda.stream(stream):
+            return _run(graph)
+
+    def _run(graph):
         pos_a, vel_a, mass = to_dev(w.pos), to_dev(w.vel), to_dev(w.mass)
         pos_b, vel_b = to_dev(w.pos), to_dev(w.vel)
         tc = treecode.Treecode(3, leaf_cap=16)
