@@ -340,8 +340,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build has no "
-              "multi-GPU path; the sharding design is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on a single GPU "
+              "and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -200,7 +200,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
 }
 
 template <int D, bool PLAIN, bool QUAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
                                                     const float4* __restrict__ walkq,
                                                     const Body* __restrict__ bodies,
                                                     const float4* __restrict__ bodies32,
@@ -294,7 +294,7 @@ template <int D>
 constexpr int kSplitTasks = D == 3 ? 64 : 16;
 
 template <int D, bool PLAIN, bool QUAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_walk_force_split(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force_split(
     const WalkCell* __restrict__ walk, const float4* __restrict__ walkq, const Body* __restrict__ bodies,
     const float4* __restrict__ bodies32, const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
     int lpl_log2, float eps2, const DevParams* __restrict__ prm, int64_t n, float4* __restrict__ part,

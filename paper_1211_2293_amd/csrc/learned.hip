@@ -125,12 +125,6 @@ __device__ void net_infer(const NetT& N, const short4_t* xs, float4_t* ys, float
     wave_lds_sync();
 }
 
-__device__ __forceinline__ double bcast(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
 __global__ void __launch_bounds__(256) k_walk_force_learned(
     const WalkCell* __restrict__ walk, const double* __restrict__ rcp2, const Body* __restrict__ bodies,
     const float4* __restrict__ bodies32, const Cell* __restrict__ cells, const Moments* __restrict__ mom,

@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) k_pb_tile_sum(const uint32_t* __restrict_
     }
     s[threadIdx.x] = v;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (unsigned o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) k_pb_part_scan(uint64_t* __restrict__ par
         const uint64_t v = t < tiles ? part[t] : 0;
         s[threadIdx.x] = v;
         __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {          // inclusive Hillis-Steele scan
+        for (unsigned o = 1; o < 256; o <<= 1) {     // inclusive Hillis-Steele scan
             const uint64_t y = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
             __syncthreads();
             s[threadIdx.x] += y;
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_pb_apply(const uint32_t* __restrict__ c
     }
     s[threadIdx.x] = mine;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
+    for (unsigned o = 1; o < 256; o <<= 1) {
         const uint64_t y = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
         __syncthreads();
         s[threadIdx.x] += y;
