@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tc.h")
 
 TC_OK, TC_EINVAL, TC_EWORKSPACE, TC_ESTATE, TC_EHIP, TC_ENONFINITE = 0, -1, -2, -3, -4, -5
+TC_ACC_COMPENSATED, TC_ACC_PLAIN = 0, 1
 TC_F32, TC_F64 = 0, 1
 GROUP = 64
 CLUSTER = 1024
@@ -406,7 +407,7 @@ class Treecode:
 
     def set_accumulation(self, compensated: bool):
         """Compensated chunk sums (default) or one plain running FP32 sum."""
-        _check(lib().tc_set_accumulation(self._h, 0 if compensated else 1))
+        _check(lib().tc_set_accumulation(self._h, TC_ACC_COMPENSATED if compensated else TC_ACC_PLAIN))
 
     def set_graph(self, on: bool):
         """Replay the pre-force part of leapfrog steps as a HIP graph (default off)."""

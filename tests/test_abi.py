@@ -83,3 +83,51 @@ def test_call_order_and_arguments(L):
 def test_strerror(L):
     for code in (T.TC_OK, T.TC_EINVAL, T.TC_EWORKSPACE, T.TC_ESTATE, T.TC_EHIP, T.TC_ENONFINITE, 99):
         assert isinstance(L.tc_strerror(code), bytes) and L.tc_strerror(code)
+
+
+def test_closure_direct_lists_and_modes_check_arguments_first(L):
+    """The entry points beyond the core path reject bad arguments and call
+    orders on the host, before touching a device."""
+    h = _ctx(L)
+    h2 = _ctx(L, dim=2)
+    fake = C.c_void_p(1 << 40)
+    tot = C.c_int64()
+    # modes
+    assert L.tc_set_multipole(h, 3) == T.TC_EINVAL
+    assert L.tc_set_multipole(h2, 2) == T.TC_EINVAL            # quadrupoles are 3D
+    assert L.tc_set_multipole(h, 2) == T.TC_OK
+    assert L.tc_set_multipole(h, 1) == T.TC_OK
+    assert L.tc_set_accumulation(h, 2) == T.TC_EINVAL
+    assert L.tc_set_accumulation(h, T.TC_ACC_PLAIN) == T.TC_OK
+    assert L.tc_set_split(None, 1) == T.TC_EINVAL
+    assert L.tc_set_graph(None, 1) == T.TC_EINVAL
+    # direct sum
+    assert L.tc_direct(h, fake, 0, 1.0, 1e-2, fake, fake) == T.TC_EINVAL
+    assert L.tc_direct(h, None, 10, 1.0, 1e-2, fake, fake) == T.TC_EINVAL
+    assert L.tc_direct(h, fake, 10, 1.0, -1.0, fake, fake) == T.TC_EINVAL
+    assert L.tc_direct(h, fake, 10, 1.0, 1e-2, fake, fake) == T.TC_ESTATE
+    # per-body lists
+    assert L.tc_lists_count(h, None, None) == T.TC_EINVAL
+    assert L.tc_lists_count(h, C.byref(tot), None) == T.TC_ESTATE
+    assert L.tc_lists_forces(h, 1.0, 1e-2, None, 10, None, None) == T.TC_EINVAL
+    assert L.tc_lists_forces(h, 1.0, 0.0, fake, 10, None, None) == T.TC_EINVAL
+    assert L.tc_lists_forces(h, 1.0, 1e-2, fake, 10, None, None) == T.TC_ESTATE
+    # learned closure
+    assert L.tc_forces_learned(h, 1.0, 1e-2, 0.8, 0.9, 1.0, None, None) == T.TC_EINVAL   # theta_p >= theta_l
+    assert L.tc_forces_learned(h, 1.0, 1e-2, 1.2, 0.5, 1.0, None, None) == T.TC_EINVAL
+    assert L.tc_forces_learned(h, 1.0, 1e-2, 0.8, 0.5, -1.0, None, None) == T.TC_EINVAL
+    assert L.tc_forces_learned(h2, 1.0, 1e-2, 0.8, 0.5, 1.0, None, None) == T.TC_EINVAL  # 3D only
+    assert L.tc_forces_learned(h, 1.0, 1e-2, 0.8, 0.5, 1.0, None, None) == T.TC_ESTATE
+    assert L.tc_residuals(h, 0.9, 1e-2, fake, 0, fake, fake, fake, 10, C.byref(tot)) == T.TC_EINVAL
+    assert L.tc_residuals(h, 0.9, 1e-2, fake, 10, None, fake, fake, 10, C.byref(tot)) == T.TC_EINVAL
+    assert L.tc_residuals(h, 0.9, 1e-2, fake, 10, fake, fake, fake, 10, C.byref(tot)) == T.TC_ESTATE
+    assert L.tc_mlp_load(h, fake) == T.TC_ESTATE
+    assert L.tc_mlp_get(h, fake) == T.TC_ESTATE
+    assert L.tc_mlp_forward(h, fake, 10, None, 11, fake) == T.TC_EINVAL                # nb > nrows
+    assert L.tc_mlp_forward(h, fake, 10, None, 5, fake) == T.TC_ESTATE
+    assert L.tc_mlp_step(h, fake, fake, 10, None, 5, -1.0, None, None) == T.TC_EINVAL
+    assert L.tc_mlp_step(h, fake, fake, 10, None, 70000, 1e-3, None, None) == T.TC_EINVAL  # batch cap
+    assert L.tc_mlp_step(h, fake, fake, 10, None, 5, 1e-3, None, None) == T.TC_ESTATE
+    assert L.tc_get_learned_counts(h, None, None) == T.TC_ESTATE
+    L.tc_destroy(h)
+    L.tc_destroy(h2)
