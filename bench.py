@@ -64,15 +64,18 @@ def force_kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(per_launch_interactions: int):
+def traffic_from_profile(w, theta: float):
     """HBM bytes per launch of the force kernel from the committed counter
-    summary, when it was taken on the current kernel source; else None."""
+    summary, when it was taken on the current kernel source and on this
+    workload; else None."""
     p = os.path.join(ROOT, "profiles", "walk_force_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         d = json.load(f)
     if d.get("source_hash") != force_kernel_source_hash():
+        return None
+    if d.get("workload") != f"{w.name} N={w.n} theta={theta} eps={w.eps} leaf_cap={w.leaf_cap}":
         return None
     return d.get("bytes_per_launch")
 
@@ -234,6 +237,10 @@ def learned_study(w, args):
         tc.moments()
         tc.walk(th)
         total, _ = tc.lists_count()
+        if 4 * total > args.list_gb_max * 1e9:
+            log(f"  per-body theta={th}: lists of {4 * total / 1e9:.1f} GB exceed --list-gb-max, skipped")
+            per_body.append({"theta": th, "skipped": f"lists of {4 * total / 1e9:.1f} GB"})
+            continue
         if buf is None or buf.numel() < total:
             buf = None
             torch.cuda.empty_cache()
@@ -324,6 +331,7 @@ def main():
     ap.add_argument("--sample", type=int, default=8192)
     ap.add_argument("--sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
     ap.add_argument("--per-body-sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7])
+    ap.add_argument("--list-gb-max", type=float, default=64.0, help="largest per-body list buffer to allocate")
     ap.add_argument("--quad-sweep", type=float, nargs="*", default=[0.5, 0.6, 0.7, 0.8, 0.9, 1.0])
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
@@ -461,7 +469,7 @@ def run(args, w, theta, dev, treecode, workloads, torch):
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_TFLOPS,
-            "traffic": traffic_from_profile(inter),
+            "traffic": traffic_from_profile(w, theta),
             "kernel_ms": kern_avg_ms,
             "flops_per_interaction": FLOPS_PER_INTERACTION[w.dim],
         },
