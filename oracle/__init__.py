@@ -74,6 +74,16 @@ def lib():
         L.orc_set_num_threads.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
+        L.orc_fmm_pairs.argtypes = [P, dbl, P, i64, P, i64, P, P]
+        L.orc_fmm_pairs.restype = i32
+        L.orc_fmm_forces.argtypes = [P, dbl, dbl, dbl, P, P]
+        L.orc_fmm_forces.restype = i32
+        L.orc_fmm_m2l.argtypes = [dbl, P, P, dbl, P]
+        L.orc_fmm_m2l.restype = None
+        L.orc_fmm_l2l.argtypes = [P, P, P]
+        L.orc_fmm_l2l.restype = None
+        L.orc_fmm_l2p.argtypes = [P, P, dbl, P, P]
+        L.orc_fmm_l2p.restype = None
         _LIB = L
     return _LIB
 
@@ -286,6 +296,56 @@ class Tree:
             lib().orc_tree_forces(self._h, float(theta), gs, G, eps, len(gsel), _p(gsel),
                                   _p(acc), _p(pot))
         return acc, pot
+
+
+# --------------------------------------------------------------------------
+# Fast multipole method (3D): the Cartesian expansions to order 3 and the
+# dual tree traversal described in oracle.c.
+# --------------------------------------------------------------------------
+def fmm_m2l(M, Q6, R, eps):
+    """Local expansion (40 full-tensor coefficients: Lam_0, Lam_1[3],
+    Lam_2[3][3], Lam_3[3][3][3]) of a source of mass M and traceless
+    quadrupole Q6 at offset R = centre - source."""
+    lam = np.zeros(40)
+    lib().orc_fmm_m2l(float(M), _p(_f64(Q6)), _p(_f64(R)), float(eps), _p(lam))
+    return lam
+
+
+def fmm_l2l(lam, t):
+    """The expansion lam moved to a centre t further on."""
+    out = np.zeros(40)
+    lib().orc_fmm_l2l(_p(_f64(lam)), _p(_f64(t)), _p(out))
+    return out
+
+
+def fmm_l2p(lam, dl, G=1.0):
+    """(acc[3], pot) of the expansion at offset dl from its centre."""
+    acc = np.zeros(3)
+    pot = np.zeros(1)
+    lib().orc_fmm_l2p(_p(_f64(lam)), _p(_f64(dl)), float(G), _p(acc), _p(pot))
+    return acc, float(pot[0])
+
+
+def fmm_pairs(tree: "Tree", theta):
+    """(m2l [k][2], p2p [k][2]) (target, source) pre-order cell ids of the
+    dual tree traversal, in traversal order."""
+    L = lib()
+    nm, npp = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    if L.orc_fmm_pairs(tree._h, float(theta), None, 0, None, 0, _p(nm), _p(npp)) != 0:
+        raise ValueError("the FMM is 3D only")
+    m2l = np.zeros((int(nm[0]), 2), np.int32)
+    p2p = np.zeros((int(npp[0]), 2), np.int32)
+    L.orc_fmm_pairs(tree._h, float(theta), _p(m2l), len(m2l), _p(p2p), len(p2p), _p(nm), _p(npp))
+    return m2l, p2p
+
+
+def fmm_forces(tree: "Tree", theta, G=1.0, eps=1e-3):
+    """FMM acceleration [n][3] and potential [n] of every body (original order)."""
+    acc = np.zeros((tree.n, 3))
+    pot = np.zeros(tree.n)
+    if lib().orc_fmm_forces(tree._h, float(theta), float(G), float(eps), _p(acc), _p(pot)) != 0:
+        raise ValueError("the FMM is 3D only")
+    return acc, pot
 
 
 def group_bodies(tree: Tree, groups, gs=64):

@@ -761,3 +761,325 @@ void orc_set_num_threads(int k)
     (void)k;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Fast multipole method (§5 names it as the way beyond the treecode's      */
+/* O(N log N)).  The paper gives no algorithm, so this is the textbook      */
+/* Cartesian form (Greengard & Rokhlin 1987; Dehnen 2002), 3D only:         */
+/*                                                                          */
+/*   - every cell carries its multipole about its centre of mass (M, Q: the */
+/*     dipole vanishes there; Q is the traceless quadrupole, whose trace    */
+/*     part would only act through the softening) and a local expansion     */
+/*     about its geometric centre z: the coefficients Lam_n (n = 0..3) of   */
+/*       phi(z + dl) = -G sum_n (1/n!) Lam_n[dl^n],                         */
+/*       a(z + dl)   =  G sum_{n>=1} (1/(n-1)!) Lam_n[dl^(n-1), .];         */
+/*   - g(R) = (|R|^2 + eps^2)^(-1/2) and D_n = its n-th derivative tensor;  */
+/*     a source cell B acting on a target cell A with R = z_A - com_B adds  */
+/*       Lam_n += M D_n(R) + (1/6) Q : D_(n+2)(R)   (the second term only   */
+/*     while n + 2 <= 3), the expansion truncated at total order 3 (M2L);   */
+/*   - a child's expansion receives its parent's, moved by t = z_c - z_p:   */
+/*       Lam'_n += sum_k (1/k!) Lam_(n+k)[t^k]  (L2L), top-down;            */
+/*   - the dual tree traversal from the pair (root, root): a cell with      */
+/*     itself splits into all pairs of its children (a leaf: direct sum);  */
+/*     a pair is accepted for M2L iff |z_A - com_B| > (rho_A + rho_B)/theta */
+/*     (strict), with rho_A = (sqrt 3 / 2) s_A bounding A's bodies about    */
+/*     z_A and rho_B = (sqrt 3 / 2) s_B + |com_B - z_B| bounding B's about  */
+/*     com_B; otherwise two leaves sum directly (P2P) and otherwise the     */
+/*     larger cell (smaller level; the target on a tie, or whichever is not */
+/*     a leaf) is split into its children.  theta = 0 accepts nothing, and  */
+/*     the result is the direct sum;                                        */
+/*   - a body's force is its leaf's expansion evaluated at the body (L2P)   */
+/*     plus the direct sums over its leaf's P2P partners, self excluded.    */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_HALF_SQRT3 0.8660254037844386
+
+/* Geometric centre of cell c's subspace. */
+static void cell_centre(const orc_tree *t, int64_t c, double *ctr)
+{
+    const int D = t->dim, l = t->level[c];
+    const double s = ldexp(t->size, -l);
+    uint64_t org[ORC_MAXD] = {0, 0, 0};
+    for (int j = 1; j <= l; ++j) {
+        const unsigned d = (unsigned)((t->prefix[c] >> (D * (l - j))) & ((1u << D) - 1u));
+        for (int k = 0; k < D; ++k) org[k] = (org[k] << 1) | ((d >> (D - 1 - k)) & 1u);
+    }
+    for (int k = 0; k < D; ++k) ctr[k] = t->lo[k] + ((double)org[k] + 0.5) * s;
+}
+
+typedef struct {
+    const orc_tree *t;
+    double theta;
+    double *ctr, *rhoA, *rhoB;    /* per cell */
+    int32_t *m2l, *p2p;           /* (target, source) pairs, pre-order ids */
+    int64_t nm2l, np2p, cap_m, cap_p;
+} fmm_ctx;
+
+static void fmm_push(int32_t *arr, int64_t *n, int64_t cap, int64_t a, int64_t b)
+{
+    if (*n < cap) {
+        arr[2 * *n] = (int32_t)a;
+        arr[2 * *n + 1] = (int32_t)b;
+    }
+    *n += 1;
+}
+
+static int fmm_accept(const fmm_ctx *f, int64_t A, int64_t B)
+{
+    if (f->theta == 0.0) return 0;
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = f->ctr[A * 3 + k] - f->t->com[B * 3 + k];
+    const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const double r = (f->rhoA[A] + f->rhoB[B]) / f->theta;
+    return d2 > r * r;
+}
+
+static void fmm_rec(fmm_ctx *f, int64_t A, int64_t B)
+{
+    const orc_tree *t = f->t;
+    if (A == B) {
+        if (t->leaf[A]) {
+            fmm_push(f->p2p, &f->np2p, f->cap_p, A, A);
+            return;
+        }
+        for (int64_t a = A + 1; a < t->skip[A]; a = t->skip[a])
+            for (int64_t b = A + 1; b < t->skip[A]; b = t->skip[b]) fmm_rec(f, a, b);
+        return;
+    }
+    if (fmm_accept(f, A, B)) {
+        fmm_push(f->m2l, &f->nm2l, f->cap_m, A, B);
+        return;
+    }
+    if (t->leaf[A] && t->leaf[B]) {
+        fmm_push(f->p2p, &f->np2p, f->cap_p, A, B);
+        return;
+    }
+    if (!t->leaf[A] && (t->leaf[B] || t->level[A] <= t->level[B])) {
+        for (int64_t a = A + 1; a < t->skip[A]; a = t->skip[a]) fmm_rec(f, a, B);
+    } else {
+        for (int64_t b = B + 1; b < t->skip[B]; b = t->skip[b]) fmm_rec(f, A, b);
+    }
+}
+
+static void fmm_setup(fmm_ctx *f, const orc_tree *t, double theta)
+{
+    memset(f, 0, sizeof(*f));
+    f->t = t;
+    f->theta = theta;
+    f->ctr = malloc(t->ncells * 3 * sizeof(double));
+    f->rhoA = malloc(t->ncells * sizeof(double));
+    f->rhoB = malloc(t->ncells * sizeof(double));
+    for (int64_t c = 0; c < t->ncells; ++c) {
+        cell_centre(t, c, f->ctr + c * 3);
+        const double s = ldexp(t->size, -t->level[c]);
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = t->com[c * 3 + k] - f->ctr[c * 3 + k];
+        f->rhoA[c] = ORC_HALF_SQRT3 * s;
+        f->rhoB[c] = ORC_HALF_SQRT3 * s + sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    }
+}
+
+static void fmm_teardown(fmm_ctx *f)
+{
+    free(f->ctr);
+    free(f->rhoA);
+    free(f->rhoB);
+}
+
+/* The interaction pairs of the dual tree traversal at theta, in traversal
+ * order: m2l[2k], m2l[2k+1] = (target, source) pre-order cell ids, at most
+ * cap_m pairs written (likewise p2p).  Returns 0 (counts in n_m2l, n_p2p),
+ * or -1 for a 2D tree. */
+int orc_fmm_pairs(const orc_tree *t, double theta, int32_t *m2l, int64_t cap_m, int32_t *p2p, int64_t cap_p,
+                  int64_t *n_m2l, int64_t *n_p2p)
+{
+    if (t->dim != 3) return -1;
+    fmm_ctx f;
+    fmm_setup(&f, t, theta);
+    f.m2l = m2l;
+    f.p2p = p2p;
+    f.cap_m = cap_m;
+    f.cap_p = cap_p;
+    fmm_rec(&f, 0, 0);
+    *n_m2l = f.nm2l;
+    *n_p2p = f.np2p;
+    fmm_teardown(&f);
+    return 0;
+}
+
+/* Local expansion coefficients, full tensors: lam[0] = Lam_0,
+ * lam[1 + a] = Lam_1, lam[4 + 3a + b] = Lam_2, lam[13 + 9a + 3b + c] = Lam_3. */
+#define FMM_NL 40
+#define L1(a) (1 + (a))
+#define L2(a, b) (4 + 3 * (a) + (b))
+#define L3(a, b, c) (13 + 9 * (a) + 3 * (b) + (c))
+
+/* M2L: add to lam the expansion about a point R away from a source of mass
+ * M and traceless quadrupole Q6 = (xx, yy, zz, xy, xz, yz) at its centre of
+ * mass (R = target centre - source centre of mass). */
+void orc_fmm_m2l(double M, const double *Q6, const double *R, double eps, double *lam)
+{
+    const double r2 = ((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]) + eps * eps;
+    const double s = 1.0 / sqrt(r2);
+    const double s3 = s * s * s, s5 = s3 * s * s, s7 = s5 * s * s;
+    double D1[3], D2[3][3], D3[3][3][3], Q[3][3];
+    Q[0][0] = Q6[0]; Q[1][1] = Q6[1]; Q[2][2] = Q6[2];
+    Q[0][1] = Q[1][0] = Q6[3];
+    Q[0][2] = Q[2][0] = Q6[4];
+    Q[1][2] = Q[2][1] = Q6[5];
+    for (int a = 0; a < 3; ++a) {
+        D1[a] = -R[a] * s3;
+        for (int b = 0; b < 3; ++b) {
+            D2[a][b] = 3.0 * R[a] * R[b] * s5 - (a == b ? s3 : 0.0);
+            for (int c = 0; c < 3; ++c)
+                D3[a][b][c] = -15.0 * R[a] * R[b] * R[c] * s7 +
+                              3.0 * ((a == b ? R[c] : 0.0) + (a == c ? R[b] : 0.0) + (b == c ? R[a] : 0.0)) * s5;
+        }
+    }
+    double q0 = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) q0 += Q[a][b] * D2[a][b];
+    lam[0] += M * s + q0 / 6.0;
+    for (int a = 0; a < 3; ++a) {
+        double q1 = 0.0;
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) q1 += Q[b][c] * D3[a][b][c];
+        lam[L1(a)] += M * D1[a] + q1 / 6.0;
+        for (int b = 0; b < 3; ++b) {
+            lam[L2(a, b)] += M * D2[a][b];
+            for (int c = 0; c < 3; ++c) lam[L3(a, b, c)] += M * D3[a][b][c];
+        }
+    }
+}
+
+/* L2L: add to out the expansion lam moved by t (new centre = old + t). */
+void orc_fmm_l2l(const double *lam, const double *t, double *out)
+{
+    double s0 = lam[0], s1[3], s2[3][3];
+    for (int a = 0; a < 3; ++a) {
+        s1[a] = lam[L1(a)];
+        for (int b = 0; b < 3; ++b) s2[a][b] = lam[L2(a, b)];
+    }
+    for (int a = 0; a < 3; ++a) {
+        s0 += lam[L1(a)] * t[a];
+        for (int b = 0; b < 3; ++b) {
+            s0 += 0.5 * lam[L2(a, b)] * t[a] * t[b];
+            s1[a] += lam[L2(a, b)] * t[b];
+            for (int c = 0; c < 3; ++c) {
+                s0 += lam[L3(a, b, c)] * t[a] * t[b] * t[c] / 6.0;
+                s1[a] += 0.5 * lam[L3(a, b, c)] * t[b] * t[c];
+                s2[a][b] += lam[L3(a, b, c)] * t[c];
+            }
+        }
+    }
+    out[0] += s0;
+    for (int a = 0; a < 3; ++a) {
+        out[L1(a)] += s1[a];
+        for (int b = 0; b < 3; ++b) {
+            out[L2(a, b)] += s2[a][b];
+            for (int c = 0; c < 3; ++c) out[L3(a, b, c)] += lam[L3(a, b, c)];
+        }
+    }
+}
+
+/* L2P: acceleration and potential at offset dl from the expansion centre. */
+void orc_fmm_l2p(const double *lam, const double *dl, double G, double *acc, double *pot)
+{
+    double phi = lam[0];
+    for (int a = 0; a < 3; ++a) {
+        double g = lam[L1(a)];
+        phi += lam[L1(a)] * dl[a];
+        for (int b = 0; b < 3; ++b) {
+            g += lam[L2(a, b)] * dl[b];
+            phi += 0.5 * lam[L2(a, b)] * dl[a] * dl[b];
+            for (int c = 0; c < 3; ++c) {
+                g += 0.5 * lam[L3(a, b, c)] * dl[b] * dl[c];
+                phi += lam[L3(a, b, c)] * dl[a] * dl[b] * dl[c] / 6.0;
+            }
+        }
+        acc[a] = G * g;
+    }
+    *pot = -G * phi;
+}
+
+/* The FMM force on every body (original order): acc [n][3], pot [n].
+ * Returns 0, or -1 for a 2D tree. */
+int orc_fmm_forces(const orc_tree *t, double theta, double G, double eps, double *acc, double *pot)
+{
+    if (t->dim != 3) return -1;
+    fmm_ctx f;
+    fmm_setup(&f, t, theta);
+    /* traversal: count, then record */
+    fmm_rec(&f, 0, 0);
+    f.cap_m = f.nm2l;
+    f.cap_p = f.np2p;
+    f.m2l = malloc((f.cap_m + 1) * 2 * sizeof(int32_t));
+    f.p2p = malloc((f.cap_p + 1) * 2 * sizeof(int32_t));
+    f.nm2l = f.np2p = 0;
+    fmm_rec(&f, 0, 0);
+
+    const int64_t C = t->ncells;
+    double *lam = calloc(C * FMM_NL, sizeof(double));
+    for (int64_t k = 0; k < f.nm2l; ++k) {
+        const int64_t A = f.m2l[2 * k], B = f.m2l[2 * k + 1];
+        double R[3];
+        for (int a = 0; a < 3; ++a) R[a] = f.ctr[A * 3 + a] - t->com[B * 3 + a];
+        orc_fmm_m2l(t->M[B], t->Q + B * 6, R, eps, lam + A * FMM_NL);
+    }
+    /* top-down: pre-order visits every parent before its children */
+    for (int64_t c = 0; c < C; ++c) {
+        if (t->leaf[c]) continue;
+        for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) {
+            double tt[3];
+            for (int a = 0; a < 3; ++a) tt[a] = f.ctr[ch * 3 + a] - f.ctr[c * 3 + a];
+            orc_fmm_l2l(lam + c * FMM_NL, tt, lam + ch * FMM_NL);
+        }
+    }
+    /* P2P partners of each target leaf */
+    int64_t *pcnt = calloc(C + 1, sizeof(int64_t));
+    for (int64_t k = 0; k < f.np2p; ++k) pcnt[f.p2p[2 * k] + 1] += 1;
+    for (int64_t c = 0; c < C; ++c) pcnt[c + 1] += pcnt[c];
+    int64_t *fill = malloc(C * sizeof(int64_t));
+    memcpy(fill, pcnt, C * sizeof(int64_t));
+    int32_t *src = malloc((f.np2p + 1) * sizeof(int32_t));
+    for (int64_t k = 0; k < f.np2p; ++k) src[fill[f.p2p[2 * k]]++] = f.p2p[2 * k + 1];
+    const double e2 = eps * eps;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t c = 0; c < C; ++c) {
+        if (!t->leaf[c]) continue;
+        for (int64_t i = t->begin[c]; i < t->begin[c] + t->count[c]; ++i) {
+            double dl[3], a[3], p;
+            for (int k = 0; k < 3; ++k) dl[k] = t->x[i * 3 + k] - f.ctr[c * 3 + k];
+            orc_fmm_l2p(lam + c * FMM_NL, dl, G, a, &p);
+            double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+            for (int64_t q = pcnt[c]; q < pcnt[c + 1]; ++q) {
+                const int64_t B = src[q];
+                for (int64_t j = t->begin[B]; j < t->begin[B] + t->count[B]; ++j) {
+                    if (j == i) continue;
+                    const double dx = t->x[j * 3] - t->x[i * 3], dy = t->x[j * 3 + 1] - t->x[i * 3 + 1],
+                                 dz = t->x[j * 3 + 2] - t->x[i * 3 + 2];
+                    const double r2 = dx * dx + dy * dy + dz * dz + e2;
+                    const double s = 1.0 / sqrt(r2);
+                    const double ms = t->m[j] * s, ms3 = ms * s * s;
+                    ax += ms3 * dx;
+                    ay += ms3 * dy;
+                    az += ms3 * dz;
+                    ph -= ms;
+                }
+            }
+            const int64_t o = t->perm[i];
+            acc[o * 3] = a[0] + G * ax;
+            acc[o * 3 + 1] = a[1] + G * ay;
+            acc[o * 3 + 2] = a[2] + G * az;
+            pot[o] = p + G * ph;
+        }
+    }
+    free(pcnt);
+    free(fill);
+    free(src);
+    free(lam);
+    free(f.m2l);
+    free(f.p2p);
+    fmm_teardown(&f);
+    return 0;
+}
