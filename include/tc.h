@@ -139,6 +139,47 @@ int tc_lists_count(tc_ctx *ctx, int64_t *total, uint32_t *counts);
  * tc_walk. */
 int tc_lists_forces(tc_ctx *ctx, double G, double eps, uint32_t *lists, int64_t cap, void *acc, void *pot);
 
+/* ---- Fast multipole method (3D) ------------------------------------------
+ * The method §5 of the paper names as the way past the treecode's cost:
+ * cells act on cells through Cartesian expansions.  Each cell's multipole is
+ * its mass and traceless quadrupole about its centre of mass (the dipole
+ * vanishes there); its local expansion about its geometric centre z has 20
+ * FP64 coefficients, phi(z + d) = -G sum_{n<=3} (1/n!) Lam_n[d^n].  A dual tree
+ * traversal from (root, root) sorts cell pairs: a cell with itself becomes
+ * all pairs of its children (a leaf sums directly); target A and source B
+ * interact through an expansion (M2L, at total order 3, with the softened
+ * kernel (r^2 + eps^2)^(-1/2)) when |z_A - com_B| > (rho_A + rho_B) / theta,
+ * rho_A = (sqrt 3/2) s_A and rho_B = (sqrt 3/2) s_B + |com_B - z_B| bounding
+ * their bodies; two leaves that are not sum directly (P2P, FP32 with
+ * compensated chunks); otherwise the larger cell (smaller level, A on a tie,
+ * never a leaf) is split.  Parents pass their expansions down (L2L); each
+ * body gets its leaf's expansion (L2P) plus its leaf's direct sums.
+ * theta = 0 makes every pair direct: the result is the direct sum. */
+
+/* Bytes of the caller's FMM buffer for ncells cells (tc_num_cells) and the
+ * capacities of the traversal's widest level of pairs and of its M2L and
+ * P2P pair lists (each 1 <= cap < 2^32).  0 for invalid sizes. */
+size_t tc_fmm_buffer_bytes(int64_t ncells, int64_t frontier_cap, int64_t m2l_cap, int64_t p2p_cap);
+
+/* Traverse at theta >= 0 (after tc_moments; 3D contexts only) into the
+ * device buffer buf (256-byte aligned, bytes >= tc_fmm_buffer_bytes of the
+ * same capacities; owned by the caller, kept until the next tc_build or
+ * plan).  Synchronises the stream.  sizes[0..2] receive the widest level,
+ * the M2L pair count and the P2P pair count; if any exceeds its capacity
+ * the call returns TC_EWORKSPACE (sizes then hold lower bounds: retry with
+ * larger capacities).  Pairs are kept sorted by (target, source). */
+int tc_fmm_plan(tc_ctx *ctx, double theta, void *buf, size_t bytes, int64_t frontier_cap, int64_t m2l_cap,
+                int64_t p2p_cap, int64_t sizes[3]);
+
+/* Forces of the current plan: acc [n][3] and pot [n] (FP32, device, caller
+ * order; either may be NULL).  eps > 0.  TC_ESTATE without a plan. */
+int tc_fmm_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
+
+/* The plan's pairs as (target, source) pre-order cell indices, sorted:
+ * m2l [sizes[1]][2] and p2p [sizes[2]][2] int32 device arrays (either may be
+ * NULL).  For tests. */
+int tc_fmm_get_pairs(tc_ctx *ctx, int32_t *m2l, int32_t *p2p);
+
 /* Split walks (default on): for n <= 16384 the force evaluation of
  * tc_forces and tc_leapfrog cuts each group's walk into one task per
  * (level-1 cell, child) (64 in 3D, 16 in 2D) so that no single long walk

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["api.hip", "build.hip", "force.hip", "step.hip", "closure.hip", "learned.hip", "direct.hip", "perbody.hip"]
+SOURCES = ["api.hip", "build.hip", "force.hip", "step.hip", "closure.hip", "learned.hip", "direct.hip", "perbody.hip", "fmm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

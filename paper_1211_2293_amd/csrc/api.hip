@@ -135,6 +135,12 @@ struct tc_ctx {
     bool split = true;         // split walks when n <= kSplitMaxN
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
+    // the fast multipole plan (tc_fmm_plan) in the caller's buffer
+    bool fmm_planned = false;
+    uint8_t* fmm_buf = nullptr;
+    int fmm_bits = 1;
+    int64_t fmm_ncells = 0, fmm_m2l = 0, fmm_p2p = 0, fmm_capf = 0, fmm_capm = 0, fmm_capp = 0;
+    uint32_t fmm_lvl_off[64] = {};
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;
     hipGraphExec_t g_exec = nullptr;
@@ -225,6 +231,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     ctx->leaf_cap = leaf_cap;
     ctx->dtype = dtype;
     ctx->state = kBuilt;
+    ctx->fmm_planned = false;
     return TC_OK;
 }
 
@@ -354,9 +361,210 @@ int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
     return TC_OK;
 }
 
+// Carve-up of the caller's FMM buffer for C cells and the pair capacities.
+struct FmmLayout {
+    int64_t C, capf, capm, capp, capk, tiles, ctiles;
+    size_t off_geo, off_lam, off_mper, off_moff, off_pper, off_poff, off_part, off_ctr, off_fa, off_fb, off_m2l,
+        off_p2p, off_keys_b, off_idx_a, off_idx_b, off_hist, off_digit, total;
+};
+
+bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* f) {
+    if (C < 1 || capf < 1 || capm < 1 || capp < 1) return false;
+    const int64_t lim = (int64_t)1 << 32;   // offsets are 32-bit
+    if (capf >= lim || capm >= lim || capp >= lim) return false;
+    memset(f, 0, sizeof(*f));
+    f->C = C;
+    f->capf = capf;
+    f->capm = capm;
+    f->capp = capp;
+    f->capk = capm > capp ? capm : capp;
+    f->tiles = (f->capk + kSortTile - 1) / kSortTile;
+    f->ctiles = (C + kScanTile - 1) / kScanTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    f->off_geo = take(sizeof(FmmGeo) * (size_t)C);
+    f->off_lam = take(8 * 20 * (size_t)C);
+    f->off_mper = take(4 * (size_t)C);
+    f->off_moff = take(4 * (size_t)(C + 1));
+    f->off_pper = take(4 * (size_t)C);
+    f->off_poff = take(4 * (size_t)(C + 1));
+    f->off_part = take(4 * (size_t)f->ctiles);
+    f->off_ctr = take(8 * 4);
+    f->off_fa = take(8 * (size_t)capf);
+    f->off_fb = take(8 * (size_t)capf);
+    f->off_m2l = take(8 * (size_t)capm);
+    f->off_p2p = take(8 * (size_t)capp);
+    f->off_keys_b = take(8 * (size_t)f->capk);
+    f->off_idx_a = take(4 * (size_t)f->capk);
+    f->off_idx_b = take(4 * (size_t)f->capk);
+    f->off_hist = take(4 * 256 * (size_t)f->tiles);
+    f->off_digit = take(4 * 256);
+    f->total = off;
+    return true;
+}
+
+// Sort n packed (target, source) keys in place (2 * bits bits; an even
+// number of 8-bit passes leaves them in keys).
+hipError_t fmm_sort(uint64_t* keys, int64_t n, int bits, uint8_t* buf, const FmmLayout& f, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fmm_pack(keys, reinterpret_cast<uint32_t*>(buf + f.off_idx_a), n, bits, s);
+    if (e != hipSuccess) return e;
+    int passes = (2 * bits + 7) / 8;
+    passes += passes & 1;
+    return launch_sort(keys, reinterpret_cast<uint32_t*>(buf + f.off_idx_a),
+                       reinterpret_cast<uint64_t*>(buf + f.off_keys_b), reinterpret_cast<uint32_t*>(buf + f.off_idx_b),
+                       n, 8 * passes, reinterpret_cast<uint32_t*>(buf + f.off_hist),
+                       reinterpret_cast<uint32_t*>(buf + f.off_digit), (n + kSortTile - 1) / kSortTile, s);
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t tc_fmm_buffer_bytes(int64_t ncells, int64_t frontier_cap, int64_t m2l_cap, int64_t p2p_cap) {
+    FmmLayout f;
+    if (!fmm_layout(ncells, frontier_cap, m2l_cap, p2p_cap, &f)) return 0;
+    return f.total;
+}
+
+int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t frontier_cap, int64_t m2l_cap,
+                int64_t p2p_cap, int64_t sizes[3]) {
+    if (!ctx || !buf || !sizes || !aligned(buf, 256)) return TC_EINVAL;
+    if (!(theta >= 0.0) || !isfinite(theta)) return TC_EINVAL;
+    if (ctx->dim != 3) return TC_EINVAL;
+    if (ctx->state < kMoments) return TC_ESTATE;
+    ctx->fmm_planned = false;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    DevParams p;
+    TC_HIP(ctx, hipMemcpyAsync(&p, ctx->prm(), sizeof(p), hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    const int64_t C = (int64_t)p.ncells < l.cmax ? (int64_t)p.ncells : l.cmax;
+    FmmLayout f;
+    if (!fmm_layout(C, frontier_cap, m2l_cap, p2p_cap, &f)) return TC_EINVAL;
+    if (bytes < f.total) return TC_EWORKSPACE;
+    uint8_t* B = (uint8_t*)buf;
+    int bits = 1;
+    while (((int64_t)1 << bits) < C) ++bits;
+    const Cell* cells = ctx->at<Cell>(l.off_cells);
+    const Moments* mom = ctx->at<Moments>(l.off_mom);
+    FmmGeo* geo = reinterpret_cast<FmmGeo*>(B + f.off_geo);
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(B + f.off_ctr);
+    uint32_t* mper = reinterpret_cast<uint32_t*>(B + f.off_mper);
+    uint32_t* pper = reinterpret_cast<uint32_t*>(B + f.off_pper);
+    uint64_t* fa = reinterpret_cast<uint64_t*>(B + f.off_fa);
+    uint64_t* fb = reinterpret_cast<uint64_t*>(B + f.off_fb);
+    uint64_t* m2l = reinterpret_cast<uint64_t*>(B + f.off_m2l);
+    uint64_t* p2p = reinterpret_cast<uint64_t*>(B + f.off_p2p);
+    TC_HIP(ctx, launch_fmm_geo(cells, mom, ctx->prm(), C, geo, s));
+    TC_HIP(ctx, launch_fill_u32(mper, C, s));
+    TC_HIP(ctx, launch_fill_u32(pper, C, s));
+    TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 8, s));
+    TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(fa), 2, s));   // the pair (root, root)
+    // one launch per level of pairs; the traversal is at most twice the
+    // tree's depth plus one levels deep
+    int64_t nin = 1, fmax = 1;
+    unsigned long long hc[3] = {0, 0, 0};
+    bool overflow = false;
+    for (int it = 0; nin > 0; ++it) {
+        if (it > 2 * (levels_for(3) + 1) + 1) return TC_EHIP;   // cannot happen for a valid tree
+        TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 2, s));
+        TC_HIP(ctx, launch_fmm_dtt(cells, mom, geo, theta, fa, nin, fb, f.capf, m2l, f.capm, p2p, f.capp, ctr, mper,
+                                   pper, s));
+        TC_HIP(ctx, hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        TC_HIP(ctx, hipStreamSynchronize(s));
+        nin = (int64_t)hc[0];
+        if (nin > fmax) fmax = nin;
+        if (nin > f.capf) {
+            overflow = true;
+            break;
+        }
+        uint64_t* t = fa;
+        fa = fb;
+        fb = t;
+    }
+    sizes[0] = fmax;
+    sizes[1] = (int64_t)hc[1];
+    sizes[2] = (int64_t)hc[2];
+    if (overflow || sizes[1] > f.capm || sizes[2] > f.capp) return TC_EWORKSPACE;
+    uint32_t* moff = reinterpret_cast<uint32_t*>(B + f.off_moff);
+    uint32_t* poff = reinterpret_cast<uint32_t*>(B + f.off_poff);
+    uint32_t* part = reinterpret_cast<uint32_t*>(B + f.off_part);
+    TC_HIP(ctx, launch_scan_u32(mper, C, moff, part, f.ctiles, s));
+    TC_HIP(ctx, launch_scan_u32(pper, C, poff, part, f.ctiles, s));
+    TC_HIP(ctx, fmm_sort(m2l, sizes[1], bits, B, f, s));
+    TC_HIP(ctx, fmm_sort(p2p, sizes[2], bits, B, f, s));
+    TC_HIP(ctx, hipMemcpyAsync(ctx->fmm_lvl_off, ctx->at<uint32_t>(l.off_lvl_off), sizeof(ctx->fmm_lvl_off),
+                               hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    ctx->fmm_buf = B;
+    ctx->fmm_bits = bits;
+    ctx->fmm_ncells = C;
+    ctx->fmm_m2l = sizes[1];
+    ctx->fmm_p2p = sizes[2];
+    ctx->fmm_capf = f.capf;
+    ctx->fmm_capm = f.capm;
+    ctx->fmm_capp = f.capp;
+    ctx->theta = theta;
+    ctx->fmm_planned = true;
+    return TC_OK;
+}
+
+int tc_fmm_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
+    if (!ctx) return TC_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
+    if (!ctx->fmm_planned) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    FmmLayout f;
+    if (!fmm_layout(ctx->fmm_ncells, ctx->fmm_capf, ctx->fmm_capm, ctx->fmm_capp, &f)) return TC_EINVAL;
+    uint8_t* B = ctx->fmm_buf;
+    const FmmGeo* geo = reinterpret_cast<const FmmGeo*>(B + f.off_geo);
+    double* lam = reinterpret_cast<double*>(B + f.off_lam);
+    const Cell* cells = ctx->at<Cell>(l.off_cells);
+    TC_HIP(ctx, launch_fmm_m2l(ctx->at<Moments>(l.off_mom), geo, ctx->prm(), f.C,
+                               reinterpret_cast<const uint64_t*>(B + f.off_m2l),
+                               reinterpret_cast<const uint32_t*>(B + f.off_moff), ctx->fmm_bits, eps * eps, lam, s));
+    for (int lv = 1; lv <= levels_for(3); ++lv) {   // level offsets cover levels 0..L and the end
+        const int64_t cnt = (int64_t)ctx->fmm_lvl_off[lv + 1] - (int64_t)ctx->fmm_lvl_off[lv];
+        TC_HIP(ctx, launch_fmm_l2l(cells, geo, ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_off),
+                                   lv, cnt, lam, s));
+    }
+    TC_HIP(ctx, launch_fmm_leaf(cells, ctx->at<Body>(l.off_bodies),
+                                ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
+                                ctx->at<uint32_t>(l.off_idx_a), geo, lam,
+                                reinterpret_cast<const uint64_t*>(B + f.off_p2p),
+                                reinterpret_cast<const uint32_t*>(B + f.off_poff), ctx->fmm_bits, ctx->prm(), f.C,
+                                (float)G, (float)(eps * eps), ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), s));
+    ctx->G = G;
+    ctx->eps = eps;
+    ctx->state = kForced;
+    if (acc)
+        TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * 3, hipMemcpyDeviceToDevice, s));
+    if (pot)
+        TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n, hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+int tc_fmm_get_pairs(tc_ctx* ctx, int32_t* m2l, int32_t* p2p) {
+    if (!ctx) return TC_EINVAL;
+    if ((m2l && !aligned(m2l, 4)) || (p2p && !aligned(p2p, 4))) return TC_EINVAL;
+    if (!ctx->fmm_planned) return TC_ESTATE;
+    FmmLayout f;
+    if (!fmm_layout(ctx->fmm_ncells, ctx->fmm_capf, ctx->fmm_capm, ctx->fmm_capp, &f)) return TC_EINVAL;
+    if (m2l)
+        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_m2l), ctx->fmm_m2l,
+                                      ctx->fmm_bits, m2l, ctx->stream));
+    if (p2p)
+        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_p2p), ctx->fmm_p2p,
+                                      ctx->fmm_bits, p2p, ctx->stream));
+    return TC_OK;
+}
 
 int tc_create(tc_ctx** out, int dim, void* hip_stream) {
     if (!out || (dim != 2 && dim != 3)) return TC_EINVAL;

@@ -177,6 +177,33 @@ hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, c
                                      int leaf_cap, float G, float eps2, float tau, int64_t n,
                                      const DevParams* prm, float* acc, float* pot, int64_t* m2p, int64_t* p2p,
                                      int64_t* learned, int64_t* fallback, hipStream_t s);
+// fmm.hip
+// Geometry of a cell for the fast multipole method: its geometric centre
+// (the local expansion's centre) and the radii bounding its bodies about
+// that centre (rhoA) and about its centre of mass (rhoB).
+struct __align__(16) FmmGeo {
+    double z[3];
+    double rhoA, rhoB;
+    double pad[3];
+};
+hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const DevParams* prm, int64_t cmax, FmmGeo* geo,
+                          hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_fmm_dtt(const Cell* cells, const Moments* mom, const FmmGeo* geo, double theta,
+                          const uint64_t* fin, int64_t nin, uint64_t* fout, int64_t capf, uint64_t* m2l, int64_t capm,
+                          uint64_t* p2p, int64_t capp, unsigned long long* ctr, uint32_t* m2l_per, uint32_t* p2p_per,
+                          hipStream_t s);
+hipError_t launch_fmm_pack(uint64_t* keys, uint32_t* idx, int64_t n, int bits, hipStream_t s);
+hipError_t launch_fmm_m2l(const Moments* mom, const FmmGeo* geo, const DevParams* prm, int64_t cmax,
+                          const uint64_t* keys, const uint32_t* off, int bits, double eps2, double* lam,
+                          hipStream_t s);
+hipError_t launch_fmm_l2l(const Cell* cells, const FmmGeo* geo, const uint32_t* bfs2pre, const uint32_t* lvl_off,
+                          int level, int64_t count, double* lam, hipStream_t s);
+hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* bodies32, const uint32_t* perm,
+                           const FmmGeo* geo, const double* lam, const uint64_t* pkeys, const uint32_t* poff,
+                           int bits, const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
+                           hipStream_t s);
+hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int bits, int32_t* out, hipStream_t s);
 // step.hip
 hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,
                              double dt, hipStream_t s);

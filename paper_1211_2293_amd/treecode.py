@@ -79,6 +79,10 @@ def lib():
         "tc_set_split": (i32, [P, i32]),
         "tc_lists_count": (i32, [P, C.POINTER(C.c_int64), P]),
         "tc_lists_forces": (i32, [P, dbl, dbl, P, i64, P, P]),
+        "tc_fmm_buffer_bytes": (C.c_size_t, [i64, i64, i64, i64]),
+        "tc_fmm_plan": (i32, [P, dbl, P, C.c_size_t, i64, i64, i64, P]),
+        "tc_fmm_forces": (i32, [P, dbl, dbl, P, P]),
+        "tc_fmm_get_pairs": (i32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -396,6 +400,50 @@ class Treecode:
         pot = torch.empty(self.n, dtype=torch.float32, device=dev) if want_pot else None
         _check(lib().tc_lists_forces(self._h, float(G), float(eps), _ptr(lists), lists.numel(), _ptr(acc), _ptr(pot)))
         return acc, pot, lists
+
+    def fmm_plan(self, theta: float):
+        """Dual tree traversal of the fast multipole method at theta into a
+        device buffer this object owns (grown, and the plan retried, while a
+        capacity is short).  Returns (widest level, M2L pairs, P2P pairs)."""
+        ncells = self.num_cells()
+        caps = list(getattr(self, "_fmm_caps", None) or (max(64, 8 * ncells), max(64, 64 * ncells),
+                                                        max(64, 16 * ncells)))
+        sizes = np.zeros(3, dtype=np.int64)
+        while True:
+            need = int(lib().tc_fmm_buffer_bytes(ncells, *caps))
+            if need == 0:
+                raise TcError(TC_EINVAL, f"FMM capacities {caps} out of range")
+            buf = getattr(self, "_fmm_buf", None)
+            if buf is None or buf.numel() < need:
+                self._fmm_buf = None
+                buf = self._fmm_buf = torch.empty(need, dtype=torch.uint8, device=self.stream.device)
+            rc = lib().tc_fmm_plan(self._h, float(theta), _ptr(buf), buf.numel(), *caps,
+                                   sizes.ctypes.data_as(C.c_void_p))
+            if rc != TC_EWORKSPACE:
+                _check(rc)
+                break
+            grown = [max(c, int(1.25 * z) + 64) if z > c else c for c, z in zip(caps, sizes)]
+            caps = grown if grown != caps else [2 * c for c in caps]
+        self._fmm_caps = tuple(caps)
+        return tuple(int(x) for x in sizes)
+
+    def fmm_forces(self, G: float = 1.0, eps: float = 1e-2, want_pot: bool = True):
+        """(acc [n][3], pot [n] or None) of the current FMM plan."""
+        dev = self.stream.device
+        acc = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        pot = torch.empty(self.n, dtype=torch.float32, device=dev) if want_pot else None
+        _check(lib().tc_fmm_forces(self._h, float(G), float(eps), _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def fmm_pairs(self, sizes):
+        """The current plan's (m2l [k][2], p2p [k][2]) int32 pairs of
+        (target, source) pre-order cell indices, sorted; sizes as returned by
+        fmm_plan."""
+        dev = self.stream.device
+        m2l = torch.empty((max(sizes[1], 1), 2), dtype=torch.int32, device=dev)
+        p2p = torch.empty((max(sizes[2], 1), 2), dtype=torch.int32, device=dev)
+        _check(lib().tc_fmm_get_pairs(self._h, _ptr(m2l), _ptr(p2p)))
+        return m2l[:sizes[1]], p2p[:sizes[2]]
 
     def set_split(self, on: bool):
         """Split walks for n <= 16384 (default on)."""
