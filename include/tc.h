@@ -167,7 +167,8 @@ size_t tc_fmm_buffer_bytes(int64_t ncells, int64_t frontier_cap, int64_t m2l_cap
  * plan).  Synchronises the stream.  sizes[0..2] receive the widest level,
  * the M2L pair count and the P2P pair count; if any exceeds its capacity
  * the call returns TC_EWORKSPACE (sizes then hold lower bounds: retry with
- * larger capacities).  Pairs are kept sorted by (target, source). */
+ * larger capacities).  Pairs are kept grouped by target, in a fixed order
+ * within each target, so results are reproducible bit for bit. */
 int tc_fmm_plan(tc_ctx *ctx, double theta, void *buf, size_t bytes, int64_t frontier_cap, int64_t m2l_cap,
                 int64_t p2p_cap, int64_t sizes[3]);
 
@@ -175,7 +176,8 @@ int tc_fmm_plan(tc_ctx *ctx, double theta, void *buf, size_t bytes, int64_t fron
  * order; either may be NULL).  eps > 0.  TC_ESTATE without a plan. */
 int tc_fmm_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
 
-/* The plan's pairs as (target, source) pre-order cell indices, sorted:
+/* The plan's pairs as (target, source) pre-order cell indices, grouped by
+ * target:
  * m2l [sizes[1]][2] and p2p [sizes[2]][2] int32 device arrays (either may be
  * NULL).  For tests. */
 int tc_fmm_get_pairs(tc_ctx *ctx, int32_t *m2l, int32_t *p2p);

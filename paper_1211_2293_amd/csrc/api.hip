@@ -138,7 +138,6 @@ struct tc_ctx {
     // the fast multipole plan (tc_fmm_plan) in the caller's buffer
     bool fmm_planned = false;
     uint8_t* fmm_buf = nullptr;
-    int fmm_bits = 1;
     int64_t fmm_ncells = 0, fmm_m2l = 0, fmm_p2p = 0, fmm_capf = 0, fmm_capm = 0, fmm_capp = 0;
     uint32_t fmm_lvl_off[64] = {};
     hipStream_t gstream = nullptr;
@@ -363,9 +362,9 @@ int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
 
 // Carve-up of the caller's FMM buffer for C cells and the pair capacities.
 struct FmmLayout {
-    int64_t C, capf, capm, capp, capk, tiles, ctiles;
-    size_t off_geo, off_lam, off_mper, off_moff, off_pper, off_poff, off_part, off_ctr, off_fa, off_fb, off_m2l,
-        off_p2p, off_keys_b, off_idx_a, off_idx_b, off_hist, off_digit, total;
+    int64_t C, capf, capm, capp, capk, tiles;
+    size_t off_geo, off_dc, off_lam, off_moff, off_poff, off_ctr, off_fa, off_fb, off_m2l,
+        off_p2p, off_keys_b, off_bt, off_base, off_hist, off_digit, total;
 };
 
 bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* f) {
@@ -379,7 +378,6 @@ bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* 
     f->capp = capp;
     f->capk = capm > capp ? capm : capp;
     f->tiles = (f->capk + kSortTile - 1) / kSortTile;
-    f->ctiles = (C + kScanTile - 1) / kScanTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -387,37 +385,31 @@ bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* 
         return o;
     };
     f->off_geo = take(sizeof(FmmGeo) * (size_t)C);
+    f->off_dc = take(sizeof(DttCell) * (size_t)C);
     f->off_lam = take(8 * 20 * (size_t)C);
-    f->off_mper = take(4 * (size_t)C);
     f->off_moff = take(4 * (size_t)(C + 1));
-    f->off_pper = take(4 * (size_t)C);
     f->off_poff = take(4 * (size_t)(C + 1));
-    f->off_part = take(4 * (size_t)f->ctiles);
     f->off_ctr = take(8 * 4);
     f->off_fa = take(8 * (size_t)capf);
     f->off_fb = take(8 * (size_t)capf);
     f->off_m2l = take(8 * (size_t)capm);
     f->off_p2p = take(8 * (size_t)capp);
     f->off_keys_b = take(8 * (size_t)f->capk);
-    f->off_idx_a = take(4 * (size_t)f->capk);
-    f->off_idx_b = take(4 * (size_t)f->capk);
+    f->off_bt = take(4 * 3 * (size_t)kFmmMaxBlocks);
+    f->off_base = take(8 * 3 * (size_t)kFmmMaxBlocks);
     f->off_hist = take(4 * 256 * (size_t)f->tiles);
     f->off_digit = take(4 * 256);
     f->total = off;
     return true;
 }
 
-// Sort n packed (target, source) keys in place (2 * bits bits; an even
-// number of 8-bit passes leaves them in keys).
+// Sort n pair keys ((source << 32) | target) in place by target, stably:
+// the low 16 * ceil(bits / 16) bits, an even number of 8-bit passes, so the
+// result lands back in keys.
 hipError_t fmm_sort(uint64_t* keys, int64_t n, int bits, uint8_t* buf, const FmmLayout& f, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipError_t e = launch_fmm_pack(keys, reinterpret_cast<uint32_t*>(buf + f.off_idx_a), n, bits, s);
-    if (e != hipSuccess) return e;
-    int passes = (2 * bits + 7) / 8;
-    passes += passes & 1;
-    return launch_sort(keys, reinterpret_cast<uint32_t*>(buf + f.off_idx_a),
-                       reinterpret_cast<uint64_t*>(buf + f.off_keys_b), reinterpret_cast<uint32_t*>(buf + f.off_idx_b),
-                       n, 8 * passes, reinterpret_cast<uint32_t*>(buf + f.off_hist),
+    return launch_sort(keys, nullptr, reinterpret_cast<uint64_t*>(buf + f.off_keys_b), nullptr, n,
+                       16 * ((bits + 15) / 16), reinterpret_cast<uint32_t*>(buf + f.off_hist),
                        reinterpret_cast<uint32_t*>(buf + f.off_digit), (n + kSortTile - 1) / kSortTile, s);
 }
 
@@ -454,15 +446,13 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     const Moments* mom = ctx->at<Moments>(l.off_mom);
     FmmGeo* geo = reinterpret_cast<FmmGeo*>(B + f.off_geo);
     unsigned long long* ctr = reinterpret_cast<unsigned long long*>(B + f.off_ctr);
-    uint32_t* mper = reinterpret_cast<uint32_t*>(B + f.off_mper);
-    uint32_t* pper = reinterpret_cast<uint32_t*>(B + f.off_pper);
     uint64_t* fa = reinterpret_cast<uint64_t*>(B + f.off_fa);
     uint64_t* fb = reinterpret_cast<uint64_t*>(B + f.off_fb);
     uint64_t* m2l = reinterpret_cast<uint64_t*>(B + f.off_m2l);
     uint64_t* p2p = reinterpret_cast<uint64_t*>(B + f.off_p2p);
-    TC_HIP(ctx, launch_fmm_geo(cells, mom, ctx->prm(), C, geo, s));
-    TC_HIP(ctx, launch_fill_u32(mper, C, s));
-    TC_HIP(ctx, launch_fill_u32(pper, C, s));
+    DttCell* dc = reinterpret_cast<DttCell*>(B + f.off_dc);
+    TC_HIP(ctx, launch_fmm_geo(cells, mom, ctx->at<WalkCell>(l.off_walk), ctx->at<uint32_t>(l.off_pre2bfs),
+                               ctx->prm(), C, geo, dc, s));
     TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 8, s));
     TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(fa), 2, s));   // the pair (root, root)
     // one launch per level of pairs; the traversal is at most twice the
@@ -473,8 +463,9 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     for (int it = 0; nin > 0; ++it) {
         if (it > 2 * (levels_for(3) + 1) + 1) return TC_EHIP;   // cannot happen for a valid tree
         TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 2, s));
-        TC_HIP(ctx, launch_fmm_dtt(cells, mom, geo, theta, fa, nin, fb, f.capf, m2l, f.capm, p2p, f.capp, ctr, mper,
-                                   pper, s));
+        TC_HIP(ctx, launch_fmm_dtt(dc, theta, fa, nin, fb, f.capf, m2l, f.capm, p2p, f.capp, ctr,
+                                   reinterpret_cast<uint32_t*>(B + f.off_bt),
+                                   reinterpret_cast<unsigned long long*>(B + f.off_base), s));
         TC_HIP(ctx, hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
         TC_HIP(ctx, hipStreamSynchronize(s));
         nin = (int64_t)hc[0];
@@ -491,18 +482,14 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     sizes[1] = (int64_t)hc[1];
     sizes[2] = (int64_t)hc[2];
     if (overflow || sizes[1] > f.capm || sizes[2] > f.capp) return TC_EWORKSPACE;
-    uint32_t* moff = reinterpret_cast<uint32_t*>(B + f.off_moff);
-    uint32_t* poff = reinterpret_cast<uint32_t*>(B + f.off_poff);
-    uint32_t* part = reinterpret_cast<uint32_t*>(B + f.off_part);
-    TC_HIP(ctx, launch_scan_u32(mper, C, moff, part, f.ctiles, s));
-    TC_HIP(ctx, launch_scan_u32(pper, C, poff, part, f.ctiles, s));
     TC_HIP(ctx, fmm_sort(m2l, sizes[1], bits, B, f, s));
     TC_HIP(ctx, fmm_sort(p2p, sizes[2], bits, B, f, s));
+    TC_HIP(ctx, launch_fmm_offsets(m2l, sizes[1], C, reinterpret_cast<uint32_t*>(B + f.off_moff), s));
+    TC_HIP(ctx, launch_fmm_offsets(p2p, sizes[2], C, reinterpret_cast<uint32_t*>(B + f.off_poff), s));
     TC_HIP(ctx, hipMemcpyAsync(ctx->fmm_lvl_off, ctx->at<uint32_t>(l.off_lvl_off), sizeof(ctx->fmm_lvl_off),
                                hipMemcpyDeviceToHost, s));
     TC_HIP(ctx, hipStreamSynchronize(s));
     ctx->fmm_buf = B;
-    ctx->fmm_bits = bits;
     ctx->fmm_ncells = C;
     ctx->fmm_m2l = sizes[1];
     ctx->fmm_p2p = sizes[2];
@@ -529,7 +516,7 @@ int tc_fmm_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
     const Cell* cells = ctx->at<Cell>(l.off_cells);
     TC_HIP(ctx, launch_fmm_m2l(ctx->at<Moments>(l.off_mom), geo, ctx->prm(), f.C,
                                reinterpret_cast<const uint64_t*>(B + f.off_m2l),
-                               reinterpret_cast<const uint32_t*>(B + f.off_moff), ctx->fmm_bits, eps * eps, lam, s));
+                               reinterpret_cast<const uint32_t*>(B + f.off_moff), eps * eps, lam, s));
     for (int lv = 1; lv <= levels_for(3); ++lv) {   // level offsets cover levels 0..L and the end
         const int64_t cnt = (int64_t)ctx->fmm_lvl_off[lv + 1] - (int64_t)ctx->fmm_lvl_off[lv];
         TC_HIP(ctx, launch_fmm_l2l(cells, geo, ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_off),
@@ -539,7 +526,7 @@ int tc_fmm_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
                                 ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                 ctx->at<uint32_t>(l.off_idx_a), geo, lam,
                                 reinterpret_cast<const uint64_t*>(B + f.off_p2p),
-                                reinterpret_cast<const uint32_t*>(B + f.off_poff), ctx->fmm_bits, ctx->prm(), f.C,
+                                reinterpret_cast<const uint32_t*>(B + f.off_poff), ctx->prm(), f.C,
                                 (float)G, (float)(eps * eps), ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), s));
     ctx->G = G;
     ctx->eps = eps;
@@ -558,11 +545,11 @@ int tc_fmm_get_pairs(tc_ctx* ctx, int32_t* m2l, int32_t* p2p) {
     FmmLayout f;
     if (!fmm_layout(ctx->fmm_ncells, ctx->fmm_capf, ctx->fmm_capm, ctx->fmm_capp, &f)) return TC_EINVAL;
     if (m2l)
-        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_m2l), ctx->fmm_m2l,
-                                      ctx->fmm_bits, m2l, ctx->stream));
+        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_m2l), ctx->fmm_m2l, m2l,
+                                      ctx->stream));
     if (p2p)
-        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_p2p), ctx->fmm_p2p,
-                                      ctx->fmm_bits, p2p, ctx->stream));
+        TC_HIP(ctx, launch_fmm_unpack(reinterpret_cast<const uint64_t*>(ctx->fmm_buf + f.off_p2p), ctx->fmm_p2p, p2p,
+                                      ctx->stream));
     return TC_OK;
 }
 

@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
         const int64_t i = tile * kSortTile + r * 256 + t;
         const bool valid = i < n;
         const uint64_t k = valid ? kin[i] : 0ull;
-        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t v = (valid && vin) ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
             uint32_t p = s_base[d] + (uint32_t)__popcll(before);
             for (int a = 0; a < w; ++a) p += s_wcnt[a][d];
             kout[p] = k;
-            vout[p] = v;
+            if (vout) vout[p] = v;
         }
         __syncthreads();
         s_base[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];

@@ -21,9 +21,9 @@
 //     its partner leaves in FP32 (P2P), coordinates relative to the leaf
 //     centre, compensated as in the treecode force loop.
 //
-// The pairs are sorted by (target, source) cell index before use, so every
-// sum runs in a fixed order and the results do not depend on the order the
-// traversal found the pairs in.
+// The traversal writes its pairs in a fixed order and a stable sort groups
+// them by target, so every sum runs in a fixed order and results are
+// reproducible bit for bit.
 #include "tc_internal.h"
 #include "walk_common.h"
 
@@ -45,8 +45,10 @@ __device__ __forceinline__ bool is_leaf(const Cell& c) { return c.leaf_nch < 0; 
 __device__ __forceinline__ int nchildren(const Cell& c) { return c.leaf_nch & 0x7fffffff; }
 
 __global__ void __launch_bounds__(256) k_fmm_geo(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
+                                                 const WalkCell* __restrict__ walk,
+                                                 const uint32_t* __restrict__ pre2bfs,
                                                  const DevParams* __restrict__ prm, int64_t cmax,
-                                                 FmmGeo* __restrict__ geo) {
+                                                 FmmGeo* __restrict__ geo, DttCell* __restrict__ dc) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
     const double size = prm->size;
@@ -71,125 +73,260 @@ __global__ void __launch_bounds__(256) k_fmm_geo(const Cell* __restrict__ cells,
         g.rhoB = kHalfSqrt3 * s + sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
         g.pad[0] = g.pad[1] = g.pad[2] = 0.0;
         geo[k] = g;
-    }
-}
-
-// Reserve n slots of a counter for this lane, one atomic per wave.  Every
-// lane of the wave must call it (n = 0 for lanes with nothing to write).
-__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* ctr, uint32_t n) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint32_t x = n;
+        const uint32_t kb = pre2bfs[k];
+        DttCell t;
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
+        for (int a = 0; a < 3; ++a) {
+            t.z[a] = g.z[a];
+            t.com[a] = mom[k].com[a];
+        }
+        t.rhoA = g.rhoA;
+        t.rhoB = g.rhoB;
+        t.child = is_leaf(c) ? -1 : walk[kb].a;
+        t.nch_leaf = c.leaf_nch;
+        t.level = l;
+        t.pre = (int32_t)k;
+        dc[kb] = t;
     }
-    const uint32_t total = __shfl(x, kWave - 1, kWave);
-    unsigned long long base = 0;
-    if (lane == kWave - 1 && total) base = atomicAdd(ctr, (unsigned long long)total);
-    base = __shfl(base, kWave - 1, kWave);
-    return base + x - n;
 }
 
 __device__ __forceinline__ uint64_t pair_key(uint32_t a, uint32_t b) { return ((uint64_t)a << 32) | b; }
 
-// One level of the traversal: every input pair becomes an M2L pair, a P2P
-// pair, or pairs of the next level.  Counters: [0] next level, [1] M2L,
-// [2] P2P; a slot at or beyond a capacity is counted but not written.
-__global__ void __launch_bounds__(256) k_fmm_dtt(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
-                                                 const FmmGeo* __restrict__ geo, double theta,
-                                                 const uint64_t* __restrict__ fin, int64_t nin,
-                                                 uint64_t* __restrict__ fout, int64_t capf,
-                                                 uint64_t* __restrict__ m2l, int64_t capm,
-                                                 uint64_t* __restrict__ p2p, int64_t capp,
-                                                 unsigned long long* __restrict__ ctr,
-                                                 uint32_t* __restrict__ m2l_per, uint32_t* __restrict__ p2p_per) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t iters = (nin + stride - 1) / stride;   // the same for every lane
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t i = it * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-        const bool valid = i < nin;
-        uint32_t A = 0, B = 0;
-        if (valid) {
-            const uint64_t pr = fin[i];
-            A = (uint32_t)(pr >> 32);
-            B = (uint32_t)pr;
-        }
-        // 0: nothing, 1: M2L, 2: P2P, 3: children of A x children of A,
-        // 4: children of A x B, 5: A x children of B
-        int kind = 0;
-        Cell ca, cb;
-        if (valid) {
-            ca = cells[A];
-            if (A == B) {
-                kind = is_leaf(ca) ? 2 : 3;
-            } else {
-                bool acc = false;
-                if (theta != 0.0) {
-                    const FmmGeo ga = geo[A], gb = geo[B];
-                    double d[3];
+// One level of the traversal, on level-order cell indices: every input
+// pair becomes an M2L pair, a P2P pair, or pairs of the next level.  Three
+// launches per level keep the output order fixed: each block counts the
+// outputs of its contiguous chunk of the input, one block turns the counts
+// into every block's first slots (and advances the running totals), and
+// each block writes its outputs in thread order.  A slot at or beyond a
+// capacity is counted but not written.  M2L and P2P pairs are stored as
+// (source << 32) | target with pre-order indices, ready for the sort by
+// target; pairs of the next level as (A << 32) | B in level order.
+struct DttOut {
+    int kind;          // 0: nothing, 1: M2L, 2: P2P, 3: children x children, 4: children x B, 5: A x children
+    uint32_t A, B;
+    int32_t child, nch;
+};
+
+__device__ __forceinline__ DttOut dtt_classify(const DttCell* __restrict__ dc, double theta, uint64_t pr) {
+    DttOut o;
+    o.A = (uint32_t)(pr >> 32);
+    o.B = (uint32_t)pr;
+    o.child = 0;
+    o.nch = 0;
+    const DttCell ca = dc[o.A];
+    const bool la = ca.nch_leaf < 0;
+    if (o.A == o.B) {
+        o.kind = la ? 2 : 3;
+        o.child = ca.child;
+        o.nch = ca.nch_leaf & 0x7fffffff;
+        return o;
+    }
+    const DttCell cb = dc[o.B];
+    bool acc = false;
+    if (theta != 0.0) {
+        double d[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) d[a] = ga.z[a] - mom[B].com[a];
-                    const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                    const double r = (ga.rhoA + gb.rhoB) / theta;
-                    acc = d2 > r * r;
-                }
-                if (acc) {
-                    kind = 1;
-                } else {
-                    cb = cells[B];
-                    if (is_leaf(ca) && is_leaf(cb)) kind = 2;
-                    else if (!is_leaf(ca) && (is_leaf(cb) || ca.level <= cb.level)) kind = 4;
-                    else kind = 5;
-                }
-            }
+        for (int a = 0; a < 3; ++a) d[a] = ca.z[a] - cb.com[a];
+        const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        const double r = (ca.rhoA + cb.rhoB) / theta;
+        acc = d2 > r * r;
+    }
+    const bool lb = cb.nch_leaf < 0;
+    if (acc) {
+        o.kind = 1;
+    } else if (la && lb) {
+        o.kind = 2;
+    } else if (!la && (lb || ca.level <= cb.level)) {
+        o.kind = 4;
+        o.child = ca.child;
+        o.nch = ca.nch_leaf & 0x7fffffff;
+    } else {
+        o.kind = 5;
+        o.child = cb.child;
+        o.nch = cb.nch_leaf & 0x7fffffff;
+    }
+    return o;
+}
+
+__device__ __forceinline__ uint32_t dtt_next(const DttOut& o) {
+    return o.kind == 3 ? (uint32_t)(o.nch * o.nch) : (o.kind >= 4 ? (uint32_t)o.nch : 0u);
+}
+
+constexpr int kDttBlock = 256;
+constexpr int kDttWaves = kDttBlock / kWave;
+
+// The same contiguous chunk of the input for a block in both sweeps.
+__device__ __forceinline__ void dtt_chunk(int64_t nin, int64_t& begin, int64_t& end) {
+    const int64_t chunk = ((nin + gridDim.x - 1) / gridDim.x + kDttBlock - 1) / kDttBlock * kDttBlock;
+    begin = (int64_t)blockIdx.x * chunk;
+    end = min(nin, begin + chunk);
+    if (end < begin) end = begin;
+}
+
+// Exclusive prefix of (a, b, c) over the block's threads in thread order;
+// returns the block totals in tot.  All threads must call it.
+__device__ __forceinline__ void block_scan3(uint32_t a, uint32_t b, uint32_t c, uint32_t* ex, uint32_t* tot,
+                                            uint32_t (*sw)[3]) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    uint32_t v[3] = {a, b, c};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(v[k], o, kWave);
+            if (lane >= o) v[k] += y;
         }
-        const int na = (kind >= 3 && kind <= 4) ? nchildren(ca) : 0;
-        const int nb = kind == 5 ? nchildren(cb) : 0;
-        const uint32_t nnext = kind == 3 ? (uint32_t)(na * na) : kind == 4 ? (uint32_t)na : (uint32_t)nb;
-        const uint64_t om = wave_reserve(&ctr[1], kind == 1 ? 1u : 0u);
-        const uint64_t op = wave_reserve(&ctr[2], kind == 2 ? 1u : 0u);
-        const uint64_t on = wave_reserve(&ctr[0], nnext);
-        if (kind == 1) {
-            if ((int64_t)om < capm) m2l[om] = pair_key(A, B);
-            atomicAdd(&m2l_per[A], 1u);
-        } else if (kind == 2) {
-            if ((int64_t)op < capp) p2p[op] = pair_key(A, B);
-            atomicAdd(&p2p_per[A], 1u);
-        } else if (kind == 3) {
-            uint32_t ch[8];
-            uint32_t c = A + 1;
-            for (int j = 0; j < na && j < 8; ++j) {
-                ch[j] = c;
-                c = (uint32_t)cells[c].skip;
-            }
-            uint64_t o = on;
-            for (int x = 0; x < na && x < 8; ++x)
-                for (int y = 0; y < na && y < 8; ++y, ++o)
-                    if ((int64_t)o < capf) fout[o] = pair_key(ch[x], ch[y]);
-        } else if (kind == 4) {
-            uint32_t c = A + 1;
-            for (int j = 0; j < na; ++j) {
-                if ((int64_t)(on + j) < capf) fout[on + j] = pair_key(c, B);
-                c = (uint32_t)cells[c].skip;
-            }
-        } else if (kind == 5) {
-            uint32_t c = B + 1;
-            for (int j = 0; j < nb; ++j) {
-                if ((int64_t)(on + j) < capf) fout[on + j] = pair_key(A, c);
-                c = (uint32_t)cells[c].skip;
-            }
+    }
+    if (lane == kWave - 1) {
+        sw[wv][0] = v[0];
+        sw[wv][1] = v[1];
+        sw[wv][2] = v[2];
+    }
+    __syncthreads();
+    uint32_t before[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        tot[k] = 0;
+        for (int w = 0; w < kDttWaves; ++w) {
+            if (w < wv) before[k] += sw[w][k];
+            tot[k] += sw[w][k];
         }
+    }
+    ex[0] = before[0] + v[0] - a;
+    ex[1] = before[1] + v[1] - b;
+    ex[2] = before[2] + v[2] - c;
+    __syncthreads();
+}
+
+// Sweep 1: bt[k * gridDim.x + block] = the block's M2L (k = 0), P2P (1)
+// and next-level (2) output counts.
+__global__ void __launch_bounds__(kDttBlock) k_fmm_dtt_count(const DttCell* __restrict__ dc, double theta,
+                                                             const uint64_t* __restrict__ fin, int64_t nin,
+                                                             uint32_t* __restrict__ bt) {
+    __shared__ uint32_t sw[kDttWaves][3];
+    int64_t begin, end;
+    dtt_chunk(nin, begin, end);
+    uint32_t cm = 0, cp = 0, cn = 0;
+    for (int64_t i = begin + threadIdx.x; i < end; i += kDttBlock) {
+        const DttOut o = dtt_classify(dc, theta, fin[i]);
+        cm += o.kind == 1;
+        cp += o.kind == 2;
+        cn += dtt_next(o);
+    }
+    uint32_t ex[3], tot[3];
+    block_scan3(cm, cp, cn, ex, tot, sw);
+    if (threadIdx.x == 0) {
+        bt[blockIdx.x] = tot[0];
+        bt[gridDim.x + blockIdx.x] = tot[1];
+        bt[2 * gridDim.x + blockIdx.x] = tot[2];
     }
 }
 
-// Pack (target, source) into a key of 2*bits bits for the radix sort.
-__global__ void __launch_bounds__(256) k_fmm_pack(uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, int64_t n,
-                                                  int bits) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = keys[i];
-        keys[i] = ((k >> 32) << bits) | (k & 0xffffffffull);
-        idx[i] = (uint32_t)i;
+// One block: every block's first output slots (M2L and P2P after the
+// running totals ctr[1], ctr[2]; the next level from 0), then ctr[0] =
+// next-level size and ctr[1], ctr[2] advanced.
+__global__ void __launch_bounds__(1024) k_fmm_dtt_scan(const uint32_t* __restrict__ bt, int nb,
+                                                       unsigned long long* __restrict__ ctr,
+                                                       unsigned long long* __restrict__ base) {
+    __shared__ unsigned long long s[1024];
+    const int t = threadIdx.x;
+    const int per = (nb + 1023) / 1024;    // at most kFmmMaxBlocks / 1024 blocks per thread
+    for (int k = 0; k < 3; ++k) {
+        unsigned long long mine = 0;
+        for (int j = 0; j < per; ++j) {
+            const int b = t * per + j;
+            if (b < nb) mine += bt[k * nb + b];
+        }
+        s[t] = mine;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {     // inclusive Hillis-Steele scan
+            const unsigned long long y = t >= o ? s[t - o] : 0ull;
+            __syncthreads();
+            s[t] += y;
+            __syncthreads();
+        }
+        const unsigned long long start = (k == 2 ? 0ull : ctr[k + 1]) + s[t] - mine;
+        unsigned long long run = start;
+        for (int j = 0; j < per; ++j) {
+            const int b = t * per + j;
+            if (b < nb) {
+                base[k * nb + b] = run;
+                run += bt[k * nb + b];
+            }
+        }
+        const unsigned long long total = s[1023];
+        __syncthreads();
+        if (t == 0) {
+            if (k == 2) ctr[0] = total;
+            else ctr[k + 1] += total;
+        }
+        __syncthreads();
+    }
+}
+
+// Sweep 2: the same classification, written in thread order from the
+// block's first slots.
+__global__ void __launch_bounds__(kDttBlock) k_fmm_dtt_write(const DttCell* __restrict__ dc, double theta,
+                                                             const uint64_t* __restrict__ fin, int64_t nin,
+                                                             const unsigned long long* __restrict__ base,
+                                                             uint64_t* __restrict__ fout, int64_t capf,
+                                                             uint64_t* __restrict__ m2l, int64_t capm,
+                                                             uint64_t* __restrict__ p2p, int64_t capp) {
+    __shared__ uint32_t sw[kDttWaves][3];
+    int64_t begin, end;
+    dtt_chunk(nin, begin, end);
+    const int64_t iters = (end - begin + kDttBlock - 1) / kDttBlock;
+    uint64_t om = base[blockIdx.x], op = base[gridDim.x + blockIdx.x], on = base[2 * gridDim.x + blockIdx.x];
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t i = begin + it * kDttBlock + threadIdx.x;
+        DttOut o;
+        o.kind = 0;
+        o.nch = 0;
+        if (i < end) o = dtt_classify(dc, theta, fin[i]);
+        uint32_t ex[3], tot[3];
+        block_scan3(o.kind == 1, o.kind == 2, dtt_next(o), ex, tot, sw);
+        if (o.kind == 1 || o.kind == 2) {
+            const uint64_t key = ((uint64_t)(uint32_t)dc[o.B].pre << 32) | (uint32_t)dc[o.A].pre;
+            if (o.kind == 1) {
+                const uint64_t s = om + ex[0];
+                if ((int64_t)s < capm) m2l[s] = key;
+            } else {
+                const uint64_t s = op + ex[1];
+                if ((int64_t)s < capp) p2p[s] = key;
+            }
+        } else if (o.kind == 3) {
+            uint64_t s = on + ex[2];
+            for (int x = 0; x < o.nch; ++x)
+                for (int y = 0; y < o.nch; ++y, ++s)
+                    if ((int64_t)s < capf) fout[s] = pair_key((uint32_t)(o.child + x), (uint32_t)(o.child + y));
+        } else if (o.kind == 4) {
+            const uint64_t s = on + ex[2];
+            for (int j = 0; j < o.nch; ++j)
+                if ((int64_t)(s + j) < capf) fout[s + j] = pair_key((uint32_t)(o.child + j), o.B);
+        } else if (o.kind == 5) {
+            const uint64_t s = on + ex[2];
+            for (int j = 0; j < o.nch; ++j)
+                if ((int64_t)(s + j) < capf) fout[s + j] = pair_key(o.A, (uint32_t)(o.child + j));
+        }
+        om += tot[0];
+        op += tot[1];
+        on += tot[2];
+    }
+}
+
+// Start of every target's run in the keys sorted by target (the low 32
+// bits): off[t] = the first key whose target is >= t, for t = 0..C
+// (off[C] = n).
+__global__ void __launch_bounds__(256) k_fmm_offsets(const uint64_t* __restrict__ keys, int64_t n, int64_t C,
+                                                     uint32_t* __restrict__ off) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t <= C; t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if ((int64_t)(uint32_t)keys[mid] < t) lo = mid + 1;
+            else hi = mid;
+        }
+        off[t] = (uint32_t)lo;
     }
 }
 
@@ -281,26 +418,41 @@ __device__ __forceinline__ void l2p(const double* lam, const double* dl, double*
     }
 }
 
-// M2L: one thread per target cell over its sorted sources; overwrites lam.
+// M2L: one wave per target cell; lane k takes the target's sorted sources
+// k, k + 64, ...; the lanes' sums are added by a fixed butterfly.
+// Overwrites lam.
 __global__ void __launch_bounds__(256) k_fmm_m2l(const Moments* __restrict__ mom, const FmmGeo* __restrict__ geo,
                                                  const DevParams* __restrict__ prm, int64_t cmax,
                                                  const uint64_t* __restrict__ keys, const uint32_t* __restrict__ off,
-                                                 int bits, double eps2, double* __restrict__ lam_out) {
+                                                 double eps2, double* __restrict__ lam_out) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
-    const uint64_t mask = ((uint64_t)1 << bits) - 1;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < C; t += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / kWave) + (threadIdx.x / kWave); t < C; t += nwaves) {
         double lam[kNL];
 #pragma unroll
         for (int k = 0; k < kNL; ++k) lam[k] = 0.0;
         const FmmGeo g = geo[t];
-        for (uint32_t q = off[t]; q < off[t + 1]; ++q) {
-            const uint32_t b = (uint32_t)(keys[q] & mask);
+        for (uint32_t q = off[t] + lane; q < off[t + 1]; q += kWave) {
+            const uint32_t b = (uint32_t)(keys[q] >> 32);
             const Moments& mb = mom[b];
             m2l_add(mb.M, mb.Q, g.z[0] - mb.com[0], g.z[1] - mb.com[1], g.z[2] - mb.com[2], eps2, lam);
         }
 #pragma unroll
-        for (int k = 0; k < kNL; ++k) lam_out[t * kNL + k] = lam[k];
+        for (int k = 0; k < kNL; ++k) {
+            double v = lam[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+            lam[k] = v;
+        }
+        if (lane < kNL) {
+            double v = lam[0];
+#pragma unroll
+            for (int k = 1; k < kNL; ++k)
+                if (lane == k) v = lam[k];
+            lam_out[t * kNL + lane] = v;
+        }
     }
 }
 
@@ -350,19 +502,25 @@ constexpr int kFmmWaves = 4;
 // L2P + P2P: one wave per target leaf.  Lanes are (target body, slice):
 // with nA target bodies, 64/P lanes per slice where P is the smallest power
 // of two >= nA (at most 64), and slice k sums list entries k, k + S, ...
-// (S slices); the slices' sums are added in FP64 in a fixed order.
+// (S slices); the slices' sums are added in FP64 in a fixed order.  The
+// partner leaves' bodies are gathered 64 at a time: 64 partner cells are
+// loaded together, their body counts scanned, and each lane finds its
+// body's partner by a binary search over the scan.
 __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
                                                   const float4* __restrict__ bodies32, const uint32_t* __restrict__ perm,
                                                   const FmmGeo* __restrict__ geo, const double* __restrict__ lam,
                                                   const uint64_t* __restrict__ pkeys, const uint32_t* __restrict__ poff,
-                                                  int bits, const DevParams* __restrict__ prm, int64_t cmax, float G,
+                                                  const DevParams* __restrict__ prm, int64_t cmax, float G,
                                                   float eps2, float* __restrict__ acc, float* __restrict__ pot) {
     __shared__ float4 s_list[kFmmWaves][kFmmList];
+    __shared__ uint32_t s_off[kFmmWaves][kWave];
+    __shared__ int32_t s_beg[kFmmWaves][kWave];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     float4* L = s_list[wv];
+    uint32_t* SO = s_off[wv];
+    int32_t* SB = s_beg[wv];
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
-    const uint64_t mask = ((uint64_t)1 << bits) - 1;
     const int64_t nwaves = (int64_t)gridDim.x * kFmmWaves;
     for (int64_t A = blockIdx.x * (int64_t)kFmmWaves + wv; A < C; A += nwaves) {
         const Cell ca = cells[A];
@@ -378,6 +536,14 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
             const bool tv = t < nA;
             const int64_t i = (int64_t)ca.begin + t0 + (tv ? t : 0);
             const Body me = bodies[i];
+            // the far field first: the leaf's expansion at the body
+            double g[3] = {0.0, 0.0, 0.0}, p = 0.0;
+            if (sl == 0 && tv) {
+                double lamA[kNL];
+                for (int k = 0; k < kNL; ++k) lamA[k] = lam[A * kNL + k];
+                const double dl[3] = {me.x - ga.z[0], me.y - ga.z[1], me.z - ga.z[2]};
+                l2p(lamA, dl, g, p);
+            }
             const float xi = (float)(me.x - ga.z[0]), yi = (float)(me.y - ga.z[1]), zi = (float)(me.z - ga.z[2]);
             float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
             int len = 0;
@@ -387,11 +553,11 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                     const int lim = min(cnt, e + kWave);
                     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
                     for (int k = e + sl; k < lim; k += S) {
-                        const float4 p = L[k];
-                        const float dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+                        const float4 q = L[k];
+                        const float dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
                         const float s = __builtin_amdgcn_rsqf(r2);
-                        const float ms = p.w * s;
+                        const float ms = q.w * s;
                         const float ms3 = ms * (s * s);
                         ap -= ms;
                         ax = fmaf(ms3, dx, ax);
@@ -405,16 +571,40 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                 }
                 wave_lds_sync();
             };
-            for (uint32_t q = q0; q < q1; ++q) {
-                const Cell cb = cells[(uint32_t)(pkeys[q] & mask)];
-                for (int o = 0; o < cb.count; o += kWave) {
-                    const int m = min(kWave, cb.count - o);
+            for (uint32_t qb = q0; qb < q1; qb += kWave) {
+                const int nq = (int)min((uint32_t)kWave, q1 - qb);
+                int32_t pb = 0;
+                uint32_t pc = 0;
+                if (lane < nq) {
+                    const Cell cb = cells[(uint32_t)(pkeys[qb + lane] >> 32)];
+                    pb = cb.begin;
+                    pc = (uint32_t)cb.count;
+                }
+                uint32_t incl = pc;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o, kWave);
+                    if (lane >= o) incl += y;
+                }
+                const uint32_t total = __shfl(incl, kWave - 1, kWave);
+                SO[lane] = incl - pc;              // first slot of partner `lane`
+                SB[lane] = pb;
+                wave_lds_sync();
+                for (uint32_t base = 0; base < total; base += kWave) {
+                    const int m = (int)min((uint32_t)kWave, total - base);
                     if (len + m > kFmmList) {
                         flush(len);
                         len = 0;
                     }
                     if (lane < m) {
-                        const int64_t j = (int64_t)cb.begin + o + lane;
+                        const uint32_t slot = base + lane;
+                        int lo = 0, hi = nq - 1;          // last partner whose first slot <= slot
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (SO[mid] <= slot) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const int64_t j = (int64_t)SB[lo] + (slot - SO[lo]);
                         float4 e;
                         if (bodies32) {
                             const float4 b = bodies32[j];
@@ -429,6 +619,7 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                     }
                     len += m;
                 }
+                wave_lds_sync();
             }
             flush(len);
             // slices' sums in FP64, in slice order
@@ -442,12 +633,6 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                 }
             }
             if (sl == 0 && tv) {
-                double lamA[kNL];
-#pragma unroll
-                for (int k = 0; k < kNL; ++k) lamA[k] = lam[A * kNL + k];
-                const double dl[3] = {me.x - ga.z[0], me.y - ga.z[1], me.z - ga.z[2]};
-                double g[3], p;
-                l2p(lamA, dl, g, p);
                 // the body met itself in its own leaf: no force, a -m/eps
                 // potential term removed as it was formed
                 const float mself = (float)me.m;
@@ -463,12 +648,11 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
 }
 
 // Pairs as (target, source) pre-order indices.
-__global__ void __launch_bounds__(256) k_fmm_unpack(const uint64_t* __restrict__ keys, int64_t n, int bits,
+__global__ void __launch_bounds__(256) k_fmm_unpack(const uint64_t* __restrict__ keys, int64_t n,
                                                     int32_t* __restrict__ out) {
-    const uint64_t mask = ((uint64_t)1 << bits) - 1;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        out[2 * i] = (int32_t)(keys[i] >> bits);
-        out[2 * i + 1] = (int32_t)(keys[i] & mask);
+        out[2 * i] = (int32_t)(uint32_t)keys[i];
+        out[2 * i + 1] = (int32_t)(keys[i] >> 32);
     }
 }
 
@@ -479,9 +663,10 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, int6
 
 }  // namespace
 
-hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const DevParams* prm, int64_t cmax, FmmGeo* geo,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_fmm_geo, dim3(grid_for(cmax)), dim3(256), 0, s, cells, mom, prm, cmax, geo);
+hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const WalkCell* walk, const uint32_t* pre2bfs,
+                          const DevParams* prm, int64_t cmax, FmmGeo* geo, DttCell* dc, hipStream_t s) {
+    hipLaunchKernelGGL(k_fmm_geo, dim3(grid_for(cmax)), dim3(256), 0, s, cells, mom, walk, pre2bfs, prm, cmax, geo,
+                       dc);
     return hipGetLastError();
 }
 
@@ -490,26 +675,29 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fmm_dtt(const Cell* cells, const Moments* mom, const FmmGeo* geo, double theta,
-                          const uint64_t* fin, int64_t nin, uint64_t* fout, int64_t capf, uint64_t* m2l, int64_t capm,
-                          uint64_t* p2p, int64_t capp, unsigned long long* ctr, uint32_t* m2l_per, uint32_t* p2p_per,
-                          hipStream_t s) {
+hipError_t launch_fmm_dtt(const DttCell* dc, double theta, const uint64_t* fin, int64_t nin, uint64_t* fout,
+                          int64_t capf, uint64_t* m2l, int64_t capm, uint64_t* p2p, int64_t capp,
+                          unsigned long long* ctr, uint32_t* bt, unsigned long long* base, hipStream_t s) {
     if (nin <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fmm_dtt, dim3(grid_for(nin, 8192)), dim3(256), 0, s, cells, mom, geo, theta, fin, nin, fout,
-                       capf, m2l, capm, p2p, capp, ctr, m2l_per, p2p_per);
+    const unsigned nb = grid_for(nin, kFmmMaxBlocks);
+    hipLaunchKernelGGL(k_fmm_dtt_count, dim3(nb), dim3(kDttBlock), 0, s, dc, theta, fin, nin, bt);
+    hipLaunchKernelGGL(k_fmm_dtt_scan, dim3(1), dim3(1024), 0, s, (const uint32_t*)bt, (int)nb, ctr, base);
+    hipLaunchKernelGGL(k_fmm_dtt_write, dim3(nb), dim3(kDttBlock), 0, s, dc, theta, fin, nin,
+                       (const unsigned long long*)base, fout, capf, m2l, capm, p2p, capp);
     return hipGetLastError();
 }
 
-hipError_t launch_fmm_pack(uint64_t* keys, uint32_t* idx, int64_t n, int bits, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fmm_pack, dim3(grid_for(n)), dim3(256), 0, s, keys, idx, n, bits);
+hipError_t launch_fmm_offsets(const uint64_t* keys, int64_t n, int64_t C, uint32_t* off, hipStream_t s) {
+    hipLaunchKernelGGL(k_fmm_offsets, dim3(grid_for(C + 1)), dim3(256), 0, s, keys, n, C, off);
     return hipGetLastError();
 }
 
 hipError_t launch_fmm_m2l(const Moments* mom, const FmmGeo* geo, const DevParams* prm, int64_t cmax,
-                          const uint64_t* keys, const uint32_t* off, int bits, double eps2, double* lam,
+                          const uint64_t* keys, const uint32_t* off, double eps2, double* lam,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_fmm_m2l, dim3(grid_for(cmax)), dim3(256), 0, s, mom, geo, prm, cmax, keys, off, bits, eps2,
+    int64_t blocks = (cmax + 3) / 4;   // one wave per cell
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fmm_m2l, dim3((unsigned)blocks), dim3(256), 0, s, mom, geo, prm, cmax, keys, off, eps2,
                        lam);
     return hipGetLastError();
 }
@@ -523,7 +711,7 @@ hipError_t launch_fmm_l2l(const Cell* cells, const FmmGeo* geo, const uint32_t* 
 
 hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* bodies32, const uint32_t* perm,
                            const FmmGeo* geo, const double* lam, const uint64_t* pkeys, const uint32_t* poff,
-                           int bits, const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
+                           const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
                            hipStream_t s) {
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -535,13 +723,13 @@ hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* 
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_fmm_leaf, dim3((unsigned)blocks), dim3(256), 0, s, cells, bodies, bodies32, perm, geo, lam,
-                       pkeys, poff, bits, prm, cmax, G, eps2, acc, pot);
+                       pkeys, poff, prm, cmax, G, eps2, acc, pot);
     return hipGetLastError();
 }
 
-hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int bits, int32_t* out, hipStream_t s) {
+hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int32_t* out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fmm_unpack, dim3(grid_for(n)), dim3(256), 0, s, keys, n, bits, out);
+    hipLaunchKernelGGL(k_fmm_unpack, dim3(grid_for(n)), dim3(256), 0, s, keys, n, out);
     return hipGetLastError();
 }
 

@@ -101,6 +101,8 @@ hipError_t launch_bbox(const void* pos, const void* mass, int64_t n, int dim, in
                        double* part, DevParams* prm, hipStream_t s);
 hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevParams* prm,
                        uint64_t* keys, uint32_t* idx, hipStream_t s);
+// LSD radix sort (stable) of the low key_bits bits; idx_a / idx_b may both be
+// null for keys without a payload.
 hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
                        int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
                        int64_t tiles, hipStream_t s);
@@ -186,24 +188,33 @@ struct __align__(16) FmmGeo {
     double rhoA, rhoB;
     double pad[3];
 };
-hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const DevParams* prm, int64_t cmax, FmmGeo* geo,
-                          hipStream_t s);
+// What the traversal reads of a cell, in level order: centre, centre of
+// mass, the two radii, its first child (level order; children are
+// contiguous there), child count with bit 31 set for a leaf, and level.
+constexpr int kFmmMaxBlocks = 4096;   // blocks per traversal launch
+struct __align__(16) DttCell {
+    double z[3];
+    double com[3];
+    double rhoA, rhoB;
+    int32_t child, nch_leaf, level, pre;   // pre: the cell's pre-order index
+};
+hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const WalkCell* walk, const uint32_t* pre2bfs,
+                          const DevParams* prm, int64_t cmax, FmmGeo* geo, DttCell* dc, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_fmm_dtt(const Cell* cells, const Moments* mom, const FmmGeo* geo, double theta,
-                          const uint64_t* fin, int64_t nin, uint64_t* fout, int64_t capf, uint64_t* m2l, int64_t capm,
-                          uint64_t* p2p, int64_t capp, unsigned long long* ctr, uint32_t* m2l_per, uint32_t* p2p_per,
-                          hipStream_t s);
-hipError_t launch_fmm_pack(uint64_t* keys, uint32_t* idx, int64_t n, int bits, hipStream_t s);
+hipError_t launch_fmm_dtt(const DttCell* dc, double theta, const uint64_t* fin, int64_t nin, uint64_t* fout,
+                          int64_t capf, uint64_t* m2l, int64_t capm, uint64_t* p2p, int64_t capp,
+                          unsigned long long* ctr, uint32_t* bt, unsigned long long* base, hipStream_t s);
+hipError_t launch_fmm_offsets(const uint64_t* keys, int64_t n, int64_t C, uint32_t* off, hipStream_t s);
 hipError_t launch_fmm_m2l(const Moments* mom, const FmmGeo* geo, const DevParams* prm, int64_t cmax,
-                          const uint64_t* keys, const uint32_t* off, int bits, double eps2, double* lam,
+                          const uint64_t* keys, const uint32_t* off, double eps2, double* lam,
                           hipStream_t s);
 hipError_t launch_fmm_l2l(const Cell* cells, const FmmGeo* geo, const uint32_t* bfs2pre, const uint32_t* lvl_off,
                           int level, int64_t count, double* lam, hipStream_t s);
 hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* bodies32, const uint32_t* perm,
                            const FmmGeo* geo, const double* lam, const uint64_t* pkeys, const uint32_t* poff,
-                           int bits, const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
+                           const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
                            hipStream_t s);
-hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int bits, int32_t* out, hipStream_t s);
+hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int32_t* out, hipStream_t s);
 // step.hip
 hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,
                              double dt, hipStream_t s);

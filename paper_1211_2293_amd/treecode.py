@@ -437,8 +437,8 @@ class Treecode:
 
     def fmm_pairs(self, sizes):
         """The current plan's (m2l [k][2], p2p [k][2]) int32 pairs of
-        (target, source) pre-order cell indices, sorted; sizes as returned by
-        fmm_plan."""
+        (target, source) pre-order cell indices, grouped by target; sizes as
+        returned by fmm_plan."""
         dev = self.stream.device
         m2l = torch.empty((max(sizes[1], 1), 2), dtype=torch.int32, device=dev)
         p2p = torch.empty((max(sizes[2], 1), 2), dtype=torch.int32, device=dev)
