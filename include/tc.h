@@ -149,8 +149,10 @@ int tc_lists_forces(tc_ctx *ctx, double G, double eps, uint32_t *lists, int64_t 
  * all pairs of its children (a leaf sums directly); target A and source B
  * interact through an expansion (M2L, at total order 3, with the softened
  * kernel (r^2 + eps^2)^(-1/2)) when |z_A - com_B| > (rho_A + rho_B) / theta,
- * rho_A = (sqrt 3/2) s_A and rho_B = (sqrt 3/2) s_B + |com_B - z_B| bounding
- * their bodies; two leaves that are not sum directly (P2P, FP32 with
+ * rho_A and rho_B bounding their bodies about z_A and com_B (a leaf: its
+ * farthest body; a cell: the largest centre distance plus radius over its
+ * children; capped by the geometric bounds (sqrt 3/2) s and (sqrt 3/2) s +
+ * |com - z|); two leaves that are not sum directly (P2P, FP32 with
  * compensated chunks); otherwise the larger cell (smaller level, A on a tie,
  * never a leaf) is split.  Parents pass their expansions down (L2L); each
  * body gets its leaf's expansion (L2P) plus its leaf's direct sums.

@@ -782,9 +782,13 @@ void orc_set_num_threads(int k)
 /*   - the dual tree traversal from the pair (root, root): a cell with      */
 /*     itself splits into all pairs of its children (a leaf: direct sum);  */
 /*     a pair is accepted for M2L iff |z_A - com_B| > (rho_A + rho_B)/theta */
-/*     (strict), with rho_A = (sqrt 3 / 2) s_A bounding A's bodies about    */
-/*     z_A and rho_B = (sqrt 3 / 2) s_B + |com_B - z_B| bounding B's about  */
-/*     com_B; otherwise two leaves sum directly (P2P) and otherwise the     */
+/*     (strict), with rho_A bounding A's bodies about z_A and rho_B bounding */
+/*     B's bodies about com_B: for a leaf the largest distance of one of    */
+/*     its bodies, for an internal cell the largest over its children of    */
+/*     (distance between the two centres + the child's radius), each        */
+/*     capped by the geometric bound ((sqrt 3 / 2) s about z, plus         */
+/*     |com - z| about com); otherwise two leaves sum directly (P2P) and    */
+/*     otherwise the                                                        */
 /*     larger cell (smaller level; the target on a tie, or whichever is not */
 /*     a leaf) is split into its children.  theta = 0 accepts nothing, and  */
 /*     the result is the direct sum;                                        */
@@ -861,6 +865,13 @@ static void fmm_rec(fmm_ctx *f, int64_t A, int64_t B)
     }
 }
 
+static double dist3(const double *a, const double *b)
+{
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = a[k] - b[k];
+    return sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+}
+
 static void fmm_setup(fmm_ctx *f, const orc_tree *t, double theta)
 {
     memset(f, 0, sizeof(*f));
@@ -869,13 +880,29 @@ static void fmm_setup(fmm_ctx *f, const orc_tree *t, double theta)
     f->ctr = malloc(t->ncells * 3 * sizeof(double));
     f->rhoA = malloc(t->ncells * sizeof(double));
     f->rhoB = malloc(t->ncells * sizeof(double));
-    for (int64_t c = 0; c < t->ncells; ++c) {
-        cell_centre(t, c, f->ctr + c * 3);
+    for (int64_t c = 0; c < t->ncells; ++c) cell_centre(t, c, f->ctr + c * 3);
+    /* children follow their parent in pre-order: go backwards */
+    for (int64_t c = t->ncells - 1; c >= 0; --c) {
+        const double *z = f->ctr + c * 3, *com = t->com + c * 3;
+        double ra = 0.0, rb = 0.0;
+        if (t->leaf[c]) {
+            for (int64_t j = t->begin[c]; j < t->begin[c] + t->count[c]; ++j) {
+                const double da = dist3(t->x + j * 3, z), db = dist3(t->x + j * 3, com);
+                if (da > ra) ra = da;
+                if (db > rb) rb = db;
+            }
+        } else {
+            for (int64_t ch = c + 1; ch < t->skip[c]; ch = t->skip[ch]) {
+                const double da = dist3(f->ctr + ch * 3, z) + f->rhoA[ch];
+                const double db = dist3(t->com + ch * 3, com) + f->rhoB[ch];
+                if (da > ra) ra = da;
+                if (db > rb) rb = db;
+            }
+        }
         const double s = ldexp(t->size, -t->level[c]);
-        double d[3];
-        for (int k = 0; k < 3; ++k) d[k] = t->com[c * 3 + k] - f->ctr[c * 3 + k];
-        f->rhoA[c] = ORC_HALF_SQRT3 * s;
-        f->rhoB[c] = ORC_HALF_SQRT3 * s + sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+        const double ga = ORC_HALF_SQRT3 * s, gb = ORC_HALF_SQRT3 * s + dist3(com, z);
+        f->rhoA[c] = ra < ga ? ra : ga;
+        f->rhoB[c] = rb < gb ? rb : gb;
     }
 }
 

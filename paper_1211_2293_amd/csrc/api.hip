@@ -453,6 +453,15 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     DttCell* dc = reinterpret_cast<DttCell*>(B + f.off_dc);
     TC_HIP(ctx, launch_fmm_geo(cells, mom, ctx->at<WalkCell>(l.off_walk), ctx->at<uint32_t>(l.off_pre2bfs),
                                ctx->prm(), C, geo, dc, s));
+    TC_HIP(ctx, hipMemcpyAsync(ctx->fmm_lvl_off, ctx->at<uint32_t>(l.off_lvl_off), sizeof(ctx->fmm_lvl_off),
+                               hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    for (int lv = levels_for(3); lv >= 0; --lv) {   // level offsets cover levels 0..L and the end
+        const int64_t cnt = (int64_t)ctx->fmm_lvl_off[lv + 1] - (int64_t)ctx->fmm_lvl_off[lv];
+        TC_HIP(ctx, launch_fmm_radii(cells, mom, ctx->at<Body>(l.off_bodies), ctx->at<WalkCell>(l.off_walk),
+                                     ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_off), lv, cnt,
+                                     geo, dc, s));
+    }
     TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 8, s));
     TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(fa), 2, s));   // the pair (root, root)
     // one launch per level of pairs; the traversal is at most twice the
@@ -486,8 +495,6 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     TC_HIP(ctx, fmm_sort(p2p, sizes[2], bits, B, f, s));
     TC_HIP(ctx, launch_fmm_offsets(m2l, sizes[1], C, reinterpret_cast<uint32_t*>(B + f.off_moff), s));
     TC_HIP(ctx, launch_fmm_offsets(p2p, sizes[2], C, reinterpret_cast<uint32_t*>(B + f.off_poff), s));
-    TC_HIP(ctx, hipMemcpyAsync(ctx->fmm_lvl_off, ctx->at<uint32_t>(l.off_lvl_off), sizeof(ctx->fmm_lvl_off),
-                               hipMemcpyDeviceToHost, s));
     TC_HIP(ctx, hipStreamSynchronize(s));
     ctx->fmm_buf = B;
     ctx->fmm_ncells = C;

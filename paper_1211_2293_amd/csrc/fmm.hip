@@ -9,8 +9,9 @@
 //     (target A, source B) pair reached from (root, root): a cell with
 //     itself becomes all pairs of its children (a leaf: a direct sum); A and
 //     B are far enough for an expansion when |z_A - com_B| > (rho_A + rho_B)
-//     / theta, with rho_A = (sqrt 3 / 2) s_A and rho_B = (sqrt 3 / 2) s_B +
-//     |com_B - z_B| bounding their bodies; two leaves that are not sum
+//     / theta, rho_A and rho_B bounding their bodies about z_A and com_B
+//     (from the bodies for a leaf, from the children for a cell, capped by
+//     the geometric bounds); two leaves that are not sum
 //     directly; otherwise the larger cell (smaller level, A on a tie, never
 //     a leaf) is split;
 //   * M2L: with g(R) = (|R|^2 + eps^2)^(-1/2), D_n its derivative tensors and
@@ -69,6 +70,7 @@ __global__ void __launch_bounds__(256) k_fmm_geo(const Cell* __restrict__ cells,
             g.z[a] = prm->lo[a] + ((double)org[a] + 0.5) * s;
             d[a] = mom[k].com[a] - g.z[a];
         }
+        // geometric bounds; k_fmm_radii tightens them from the bodies
         g.rhoA = kHalfSqrt3 * s;
         g.rhoB = kHalfSqrt3 * s + sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
         g.pad[0] = g.pad[1] = g.pad[2] = 0.0;
@@ -91,6 +93,53 @@ __global__ void __launch_bounds__(256) k_fmm_geo(const Cell* __restrict__ cells,
 }
 
 __device__ __forceinline__ uint64_t pair_key(uint32_t a, uint32_t b) { return ((uint64_t)a << 32) | b; }
+
+__device__ __forceinline__ double dist3(double ax, double ay, double az, double bx, double by, double bz) {
+    const double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+// The radii of the cells of one level (level-order range), deepest level
+// first: rho_A bounds the cell's bodies about its centre z, rho_B about its
+// centre of mass; for a leaf the largest distance of one of its bodies, for
+// an internal cell the largest (distance between the centres + the child's
+// radius) over its children; each capped by the geometric bound.
+__global__ void __launch_bounds__(256) k_fmm_radii(const Cell* __restrict__ cells, const Moments* __restrict__ mom,
+                                                   const Body* __restrict__ bodies, const WalkCell* __restrict__ walk,
+                                                   const uint32_t* __restrict__ bfs2pre,
+                                                   const uint32_t* __restrict__ lvl_off, int level,
+                                                   FmmGeo* __restrict__ geo, DttCell* __restrict__ dc) {
+    const int64_t lo = lvl_off[level], hi = lvl_off[level + 1];
+    for (int64_t k = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < hi;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = bfs2pre[k];
+        const Cell cc = cells[c];
+        FmmGeo g = geo[c];
+        const double cx = mom[c].com[0], cy = mom[c].com[1], cz = mom[c].com[2];
+        double ra = 0.0, rb = 0.0;
+        if (is_leaf(cc)) {
+            for (int64_t j = cc.begin; j < (int64_t)cc.begin + cc.count; ++j) {
+                const Body b = bodies[j];
+                ra = fmax(ra, dist3(b.x, b.y, b.z, g.z[0], g.z[1], g.z[2]));
+                rb = fmax(rb, dist3(b.x, b.y, b.z, cx, cy, cz));
+            }
+        } else {
+            const int32_t first = walk[k].a;
+            const int nch = nchildren(cc);
+            for (int i = 0; i < nch; ++i) {
+                const uint32_t ch = bfs2pre[first + i];
+                const FmmGeo gc = geo[ch];
+                ra = fmax(ra, dist3(gc.z[0], gc.z[1], gc.z[2], g.z[0], g.z[1], g.z[2]) + gc.rhoA);
+                rb = fmax(rb, dist3(mom[ch].com[0], mom[ch].com[1], mom[ch].com[2], cx, cy, cz) + gc.rhoB);
+            }
+        }
+        g.rhoA = fmin(ra, g.rhoA);
+        g.rhoB = fmin(rb, g.rhoB);
+        geo[c] = g;
+        dc[k].rhoA = g.rhoA;
+        dc[k].rhoB = g.rhoB;
+    }
+}
 
 // One level of the traversal, on level-order cell indices: every input
 // pair becomes an M2L pair, a P2P pair, or pairs of the next level.  Three
@@ -667,6 +716,15 @@ hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const WalkCell*
                           const DevParams* prm, int64_t cmax, FmmGeo* geo, DttCell* dc, hipStream_t s) {
     hipLaunchKernelGGL(k_fmm_geo, dim3(grid_for(cmax)), dim3(256), 0, s, cells, mom, walk, pre2bfs, prm, cmax, geo,
                        dc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmm_radii(const Cell* cells, const Moments* mom, const Body* bodies, const WalkCell* walk,
+                            const uint32_t* bfs2pre, const uint32_t* lvl_off, int level, int64_t count, FmmGeo* geo,
+                            DttCell* dc, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fmm_radii, dim3(grid_for(count)), dim3(256), 0, s, cells, mom, bodies, walk, bfs2pre, lvl_off,
+                       level, geo, dc);
     return hipGetLastError();
 }
 

