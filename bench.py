@@ -17,10 +17,10 @@ After the timed steps (outside the timed region):
   * the same evaluations with per-body lists written to memory and summed
     by a separate kernel (tc_lists_count / tc_lists_forces), over a theta
     sweep;
-  * for 3D workloads, the fast multipole method over a theta sweep (dual
-    tree traversal, M2L, L2L, L2P and direct sums; each timed evaluation
-    includes the tree build and the traversal), with the plain rate at the
-    same E;
+  * for 3D workloads, the fast multipole method over a theta sweep on a
+    tree of its own leaf size (64 by default; dual tree traversal, M2L, L2L,
+    L2P and direct sums; each timed evaluation includes the tree build and
+    the traversal), with the plain rate at the same E;
   * for 3D workloads, the learned-vs-plain study on the initial positions:
     plain evaluations over a theta sweep (time per evaluation and E), the
     closure network trained on residuals generated at theta = 0.9 for 4,096
@@ -272,34 +272,37 @@ def learned_study(w, args):
     if w.dim != 3:
         return out
 
-    # the fast multipole method (cell-cell expansions)
+    # the fast multipole method (cell-cell expansions), on a tree of its own
+    # leaf size
     fmm = []
+    tf = treecode.Treecode(w.dim, leaf_cap=args.fmm_leaf_cap) if args.fmm_sweep else None
     for th in args.fmm_sweep:
         def run_fmm():
-            tc.build(pos, mass)
-            tc.moments()
-            tc.fmm_plan(th)
-            return tc.fmm_forces(w.G, w.eps, want_pot=False)[0]
+            tf.build(pos, mass)
+            tf.moments()
+            tf.fmm_plan(th)
+            return tf.fmm_forces(w.G, w.eps, want_pot=False)[0]
 
         def run_plan():
-            tc.build(pos, mass)
-            tc.moments()
-            return tc.fmm_plan(th)
+            tf.build(pos, mass)
+            tf.moments()
+            return tf.fmm_plan(th)
 
         ms = time_evals(run_fmm)
         ms_plan = time_evals(run_plan)
         sizes = run_plan()
-        acc = tc.fmm_forces(w.G, w.eps, want_pot=False)[0].cpu().numpy()[sample]
+        acc = tf.fmm_forces(w.G, w.eps, want_pot=False)[0].cpu().numpy()[sample]
         e = rel_error(acc, ref)
         pm = interp_ms_at_error(sweep, e["E"])
-        fmm.append({"theta": th, "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "ms_build_and_traversal": ms_plan,
+        fmm.append({"theta": th, "leaf_cap": args.fmm_leaf_cap, "ms_per_eval": ms, "evals_per_s": 1e3 / ms,
+                    "ms_build_and_traversal": ms_plan,
                     "E": e["E"], "p99": e["p99"], "m2l_pairs": sizes[1], "p2p_leaf_pairs": sizes[2],
                     "plain_evals_per_s_at_same_E": None if pm is None else 1e3 / pm,
                     "speedup_vs_plain_at_same_E": None if pm is None else pm / ms})
         log(f"  fmm theta={th}: {ms:.3f} ms/eval ({ms_plan:.3f} build + traversal), E={e['E']:.3e}, "
             f"{sizes[1]} M2L / {sizes[2]} P2P pairs, speedup at same E {fmm[-1]['speedup_vs_plain_at_same_E']}")
     out["fmm"] = fmm
-    tc._fmm_buf = None
+    del tf
     torch.cuda.empty_cache()
 
     t0 = time.perf_counter()
@@ -367,7 +370,8 @@ def main():
     ap.add_argument("--per-body-sweep", type=float, nargs="*", default=[0.3, 0.4, 0.5, 0.6, 0.7])
     ap.add_argument("--list-gb-max", type=float, default=64.0, help="largest per-body list buffer to allocate")
     ap.add_argument("--quad-sweep", type=float, nargs="*", default=[0.5, 0.6, 0.7, 0.8, 0.9, 1.0])
-    ap.add_argument("--fmm-sweep", type=float, nargs="*", default=[0.5, 0.6, 0.7, 0.8, 0.9, 1.0])
+    ap.add_argument("--fmm-sweep", type=float, nargs="*", default=[0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
+    ap.add_argument("--fmm-leaf-cap", type=int, default=64, help="leaf size of the FMM's own tree")
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
     ap.add_argument("--epochs", type=int, default=40)

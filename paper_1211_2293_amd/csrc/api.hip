@@ -138,7 +138,7 @@ struct tc_ctx {
     // the fast multipole plan (tc_fmm_plan) in the caller's buffer
     bool fmm_planned = false;
     uint8_t* fmm_buf = nullptr;
-    int64_t fmm_ncells = 0, fmm_m2l = 0, fmm_p2p = 0, fmm_capf = 0, fmm_capm = 0, fmm_capp = 0;
+    int64_t fmm_ncells = 0, fmm_m2l = 0, fmm_p2p = 0, fmm_capf = 0, fmm_capm = 0, fmm_capp = 0, fmm_ntasks = 0;
     uint32_t fmm_lvl_off[64] = {};
     hipStream_t gstream = nullptr;
     hipEvent_t g_in = nullptr, g_out = nullptr;
@@ -364,7 +364,9 @@ int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
 struct FmmLayout {
     int64_t C, capf, capm, capp, capk, tiles;
     size_t off_geo, off_dc, off_lam, off_moff, off_poff, off_ctr, off_fa, off_fb, off_m2l,
-        off_p2p, off_keys_b, off_bt, off_base, off_hist, off_digit, total;
+        off_p2p, off_keys_b, off_bt, off_base, off_hist, off_digit, off_ntask, off_nslot, off_toff, off_soff, off_tpart,
+        total;
+    int64_t ctiles;
 };
 
 bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* f) {
@@ -399,6 +401,12 @@ bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* 
     f->off_base = take(8 * 3 * (size_t)kFmmMaxBlocks);
     f->off_hist = take(4 * 256 * (size_t)f->tiles);
     f->off_digit = take(4 * 256);
+    f->ctiles = (C + kScanTile - 1) / kScanTile;
+    f->off_ntask = take(4 * (size_t)C);
+    f->off_nslot = take(4 * (size_t)C);
+    f->off_toff = take(4 * (size_t)(C + 1));
+    f->off_soff = take(4 * (size_t)(C + 1));
+    f->off_tpart = take(4 * (size_t)f->ctiles);
     f->total = off;
     return true;
 }
@@ -495,6 +503,29 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     TC_HIP(ctx, fmm_sort(p2p, sizes[2], bits, B, f, s));
     TC_HIP(ctx, launch_fmm_offsets(m2l, sizes[1], C, reinterpret_cast<uint32_t*>(B + f.off_moff), s));
     TC_HIP(ctx, launch_fmm_offsets(p2p, sizes[2], C, reinterpret_cast<uint32_t*>(B + f.off_poff), s));
+    // the leaf kernel's tasks: long partner lists cut into chunks whose
+    // partial sums (4 doubles per body and chunk) use the frontier buffers
+    uint32_t* toff = reinterpret_cast<uint32_t*>(B + f.off_toff);
+    uint32_t* soff = reinterpret_cast<uint32_t*>(B + f.off_soff);
+    TC_HIP(ctx, launch_fmm_tasks(cells, reinterpret_cast<const uint32_t*>(B + f.off_poff), ctx->prm(), C,
+                                 reinterpret_cast<uint32_t*>(B + f.off_ntask),
+                                 reinterpret_cast<uint32_t*>(B + f.off_nslot), s));
+    TC_HIP(ctx, launch_scan_u32(reinterpret_cast<const uint32_t*>(B + f.off_ntask), C, toff,
+                                reinterpret_cast<uint32_t*>(B + f.off_tpart), f.ctiles, s));
+    TC_HIP(ctx, launch_scan_u32(reinterpret_cast<const uint32_t*>(B + f.off_nslot), C, soff,
+                                reinterpret_cast<uint32_t*>(B + f.off_tpart), f.ctiles, s));
+    uint32_t tot[2] = {0, 0};
+    TC_HIP(ctx, hipMemcpyAsync(&tot[0], toff + C, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipMemcpyAsync(&tot[1], soff + C, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(ctx, hipStreamSynchronize(s));
+    const int64_t part_slots = (int64_t)(f.off_fb + 8 * (size_t)f.capf - f.off_fa) / 32;
+    if ((int64_t)tot[1] > part_slots) {
+        sizes[0] = 2 * (int64_t)tot[1] + 1;          // frontier capacity that holds the partial sums
+        return TC_EWORKSPACE;
+    }
+    if ((int64_t)tot[0] > 2 * f.capk) return TC_EHIP;   // cannot happen: tasks <= leaves + P2P pairs
+    TC_HIP(ctx, launch_fmm_tasks_fill(toff, ctx->prm(), C, reinterpret_cast<uint32_t*>(B + f.off_keys_b), s));
+    ctx->fmm_ntasks = (int64_t)tot[0];
     TC_HIP(ctx, hipStreamSynchronize(s));
     ctx->fmm_buf = B;
     ctx->fmm_ncells = C;
@@ -533,7 +564,11 @@ int tc_fmm_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
                                 ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                 ctx->at<uint32_t>(l.off_idx_a), geo, lam,
                                 reinterpret_cast<const uint64_t*>(B + f.off_p2p),
-                                reinterpret_cast<const uint32_t*>(B + f.off_poff), ctx->prm(), f.C,
+                                reinterpret_cast<const uint32_t*>(B + f.off_poff),
+                                reinterpret_cast<const uint32_t*>(B + f.off_keys_b),
+                                reinterpret_cast<const uint32_t*>(B + f.off_toff),
+                                reinterpret_cast<const uint32_t*>(B + f.off_soff), ctx->fmm_ntasks,
+                                reinterpret_cast<double*>(B + f.off_fa), ctx->prm(), f.C,
                                 (float)G, (float)(eps * eps), ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), s));
     ctx->G = G;
     ctx->eps = eps;

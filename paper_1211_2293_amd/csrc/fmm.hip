@@ -548,7 +548,44 @@ __global__ void __launch_bounds__(256) k_fmm_l2l(const Cell* __restrict__ cells,
 constexpr int kFmmList = 256;
 constexpr int kFmmWaves = 4;
 
-// L2P + P2P: one wave per target leaf.  Lanes are (target body, slice):
+// A target leaf whose partner list is longer than kFmmChunk leaves is cut
+// into chunks of kFmmChunk partners, one task each, so that no single wave
+// carries a far-spread leaf's whole direct sum; the chunks' sums go to
+// partial slots and k_fmm_leaf_finish adds them in chunk order.
+constexpr uint32_t kFmmChunk = 256;
+
+// Tasks per cell (leaves: chunks of the partner list; other cells: none)
+// and partial slots (chunks x bodies, for leaves cut into several chunks).
+__global__ void __launch_bounds__(256) k_fmm_tasks_count(const Cell* __restrict__ cells,
+                                                         const uint32_t* __restrict__ poff,
+                                                         const DevParams* __restrict__ prm, int64_t cmax,
+                                                         uint32_t* __restrict__ ntask, uint32_t* __restrict__ nslot) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; A < C; A += (int64_t)gridDim.x * blockDim.x) {
+        const Cell ca = cells[A];
+        uint32_t nt = 0, ns = 0;
+        if (is_leaf(ca)) {
+            const uint32_t np = poff[A + 1] - poff[A];
+            nt = np > kFmmChunk ? (np + kFmmChunk - 1) / kFmmChunk : 1u;
+            ns = nt > 1 ? nt * (uint32_t)ca.count : 0u;
+        }
+        ntask[A] = nt;
+        nslot[A] = ns;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fmm_tasks_fill(const uint32_t* __restrict__ toff,
+                                                        const DevParams* __restrict__ prm, int64_t cmax,
+                                                        uint32_t* __restrict__ task) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; A < C; A += (int64_t)gridDim.x * blockDim.x)
+        for (uint32_t k = toff[A]; k < toff[A + 1]; ++k) task[k] = (uint32_t)A;
+}
+
+// L2P + P2P: one wave per task (a target leaf, or one chunk of a long
+// leaf's partner list).  Lanes are (target body, slice):
 // with nA target bodies, 64/P lanes per slice where P is the smallest power
 // of two >= nA (at most 64), and slice k sums list entries k, k + S, ...
 // (S slices); the slices' sums are added in FP64 in a fixed order.  The
@@ -559,8 +596,9 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                                                   const float4* __restrict__ bodies32, const uint32_t* __restrict__ perm,
                                                   const FmmGeo* __restrict__ geo, const double* __restrict__ lam,
                                                   const uint64_t* __restrict__ pkeys, const uint32_t* __restrict__ poff,
-                                                  const DevParams* __restrict__ prm, int64_t cmax, float G,
-                                                  float eps2, float* __restrict__ acc, float* __restrict__ pot) {
+                                                  const uint32_t* __restrict__ task, const uint32_t* __restrict__ toff,
+                                                  const uint32_t* __restrict__ soff, int64_t ntasks, double* __restrict__ part,
+                                                  float G, float eps2, float* __restrict__ acc, float* __restrict__ pot) {
     __shared__ float4 s_list[kFmmWaves][kFmmList];
     __shared__ uint32_t s_off[kFmmWaves][kWave];
     __shared__ int32_t s_beg[kFmmWaves][kWave];
@@ -568,14 +606,14 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
     float4* L = s_list[wv];
     uint32_t* SO = s_off[wv];
     int32_t* SB = s_beg[wv];
-    int64_t C = prm->ncells;
-    if (C > cmax) C = cmax;
     const int64_t nwaves = (int64_t)gridDim.x * kFmmWaves;
-    for (int64_t A = blockIdx.x * (int64_t)kFmmWaves + wv; A < C; A += nwaves) {
+    for (int64_t tk = blockIdx.x * (int64_t)kFmmWaves + wv; tk < ntasks; tk += nwaves) {
+        const uint32_t A = task[tk];
+        const uint32_t chunk = (uint32_t)tk - toff[A], nchunks = toff[A + 1] - toff[A];
         const Cell ca = cells[A];
-        if (!is_leaf(ca)) continue;
         const FmmGeo ga = geo[A];
-        const uint32_t q0 = poff[A], q1 = poff[A + 1];
+        const uint32_t q0 = poff[A] + chunk * kFmmChunk;
+        const uint32_t q1 = nchunks > 1 ? min(poff[A + 1], q0 + kFmmChunk) : poff[A + 1];
         for (int t0 = 0; t0 < ca.count; t0 += kWave) {
             const int nA = min(kWave, ca.count - t0);
             int P = 1;
@@ -585,9 +623,10 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
             const bool tv = t < nA;
             const int64_t i = (int64_t)ca.begin + t0 + (tv ? t : 0);
             const Body me = bodies[i];
-            // the far field first: the leaf's expansion at the body
+            // the far field first: the leaf's expansion at the body (a leaf
+            // cut into chunks gets it in k_fmm_leaf_finish)
             double g[3] = {0.0, 0.0, 0.0}, p = 0.0;
-            if (sl == 0 && tv) {
+            if (sl == 0 && tv && nchunks == 1) {
                 double lamA[kNL];
                 for (int k = 0; k < kNL; ++k) lamA[k] = lam[A * kNL + k];
                 const double dl[3] = {me.x - ga.z[0], me.y - ga.z[1], me.z - ga.z[2]};
@@ -681,7 +720,13 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                     if ((lane & o) == 0) v[k] += w;
                 }
             }
-            if (sl == 0 && tv) {
+            if (sl == 0 && tv && nchunks > 1) {
+                double* o = part + 4 * ((int64_t)soff[A] + (int64_t)chunk * ca.count + t0 + t);
+                o[0] = v[0];
+                o[1] = v[1];
+                o[2] = v[2];
+                o[3] = v[3];
+            } else if (sl == 0 && tv) {
                 // the body met itself in its own leaf: no force, a -m/eps
                 // potential term removed as it was formed
                 const float mself = (float)me.m;
@@ -692,6 +737,53 @@ __global__ void __launch_bounds__(256) k_fmm_leaf(const Cell* __restrict__ cells
                 acc[o * 3 + 2] = (float)((double)G * (g[2] + v[2]));
                 pot[o] = (float)((double)G * (-p + v[3] + self));
             }
+        }
+    }
+}
+
+// Bodies of the leaves cut into chunks: the chunks' sums in chunk order,
+// the leaf's expansion and the self term, as in k_fmm_leaf.  One wave per
+// cell, lanes over its bodies.
+__global__ void __launch_bounds__(256) k_fmm_leaf_finish(const Cell* __restrict__ cells, const Body* __restrict__ bodies,
+                                                         const uint32_t* __restrict__ perm,
+                                                         const FmmGeo* __restrict__ geo, const double* __restrict__ lam,
+                                                         const uint32_t* __restrict__ toff,
+                                                         const uint32_t* __restrict__ soff,
+                                                         const double* __restrict__ part,
+                                                         const DevParams* __restrict__ prm, int64_t cmax, float G,
+                                                         float eps2, float* __restrict__ acc, float* __restrict__ pot) {
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t A = blockIdx.x * (int64_t)(blockDim.x / kWave) + (threadIdx.x / kWave); A < C; A += nwaves) {
+        const uint32_t nchunks = toff[A + 1] - toff[A];
+        if (nchunks < 2) continue;
+        const Cell ca = cells[A];
+        const FmmGeo ga = geo[A];
+        for (int t = lane; t < ca.count; t += kWave) {
+            const int64_t i = (int64_t)ca.begin + t;
+            const Body me = bodies[i];
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (uint32_t j = 0; j < nchunks; ++j) {
+                const double* q = part + 4 * ((int64_t)soff[A] + (int64_t)j * ca.count + t);
+                v[0] += q[0];
+                v[1] += q[1];
+                v[2] += q[2];
+                v[3] += q[3];
+            }
+            double lamA[kNL];
+            for (int k = 0; k < kNL; ++k) lamA[k] = lam[A * kNL + k];
+            const double dl[3] = {me.x - ga.z[0], me.y - ga.z[1], me.z - ga.z[2]};
+            double g[3], p;
+            l2p(lamA, dl, g, p);
+            const float mself = (float)me.m;
+            const double self = (double)(mself * __builtin_amdgcn_rsqf(eps2));
+            const int64_t o = perm[i];
+            acc[o * 3 + 0] = (float)((double)G * (g[0] + v[0]));
+            acc[o * 3 + 1] = (float)((double)G * (g[1] + v[1]));
+            acc[o * 3 + 2] = (float)((double)G * (g[2] + v[2]));
+            pot[o] = (float)((double)G * (-p + v[3] + self));
         }
     }
 }
@@ -767,21 +859,39 @@ hipError_t launch_fmm_l2l(const Cell* cells, const FmmGeo* geo, const uint32_t* 
     return hipGetLastError();
 }
 
+hipError_t launch_fmm_tasks(const Cell* cells, const uint32_t* poff, const DevParams* prm, int64_t cmax,
+                            uint32_t* ntask, uint32_t* nslot, hipStream_t s) {
+    hipLaunchKernelGGL(k_fmm_tasks_count, dim3(grid_for(cmax)), dim3(256), 0, s, cells, poff, prm, cmax, ntask, nslot);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmm_tasks_fill(const uint32_t* toff, const DevParams* prm, int64_t cmax, uint32_t* task,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_fmm_tasks_fill, dim3(grid_for(cmax)), dim3(256), 0, s, toff, prm, cmax, task);
+    return hipGetLastError();
+}
+
 hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* bodies32, const uint32_t* perm,
                            const FmmGeo* geo, const double* lam, const uint64_t* pkeys, const uint32_t* poff,
-                           const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
-                           hipStream_t s) {
+                           const uint32_t* task, const uint32_t* toff, const uint32_t* soff, int64_t ntasks,
+                           double* part, const DevParams* prm, int64_t cmax, float G, float eps2, float* acc,
+                           float* pot, hipStream_t s) {
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    int64_t blocks = (cmax + kFmmWaves - 1) / kFmmWaves;
-    const int64_t cap = (int64_t)ncu * 16;
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_fmm_leaf, dim3((unsigned)blocks), dim3(256), 0, s, cells, bodies, bodies32, perm, geo, lam,
-                       pkeys, poff, prm, cmax, G, eps2, acc, pot);
+    if (ntasks > 0) {
+        int64_t blocks = (ntasks + kFmmWaves - 1) / kFmmWaves;
+        const int64_t cap = (int64_t)ncu * 16;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL(k_fmm_leaf, dim3((unsigned)blocks), dim3(256), 0, s, cells, bodies, bodies32, perm, geo,
+                           lam, pkeys, poff, task, toff, soff, ntasks, part, G, eps2, acc, pot);
+    }
+    int64_t fb = (cmax + 3) / 4;
+    if (fb > 65536) fb = 65536;
+    hipLaunchKernelGGL(k_fmm_leaf_finish, dim3((unsigned)fb), dim3(256), 0, s, cells, bodies, perm, geo, lam, toff,
+                       soff, (const double*)part, prm, cmax, G, eps2, acc, pot);
     return hipGetLastError();
 }
 

@@ -213,10 +213,15 @@ hipError_t launch_fmm_m2l(const Moments* mom, const FmmGeo* geo, const DevParams
                           hipStream_t s);
 hipError_t launch_fmm_l2l(const Cell* cells, const FmmGeo* geo, const uint32_t* bfs2pre, const uint32_t* lvl_off,
                           int level, int64_t count, double* lam, hipStream_t s);
+hipError_t launch_fmm_tasks(const Cell* cells, const uint32_t* poff, const DevParams* prm, int64_t cmax,
+                            uint32_t* ntask, uint32_t* nslot, hipStream_t s);
+hipError_t launch_fmm_tasks_fill(const uint32_t* toff, const DevParams* prm, int64_t cmax, uint32_t* task,
+                                 hipStream_t s);
 hipError_t launch_fmm_leaf(const Cell* cells, const Body* bodies, const float4* bodies32, const uint32_t* perm,
                            const FmmGeo* geo, const double* lam, const uint64_t* pkeys, const uint32_t* poff,
-                           const DevParams* prm, int64_t cmax, float G, float eps2, float* acc, float* pot,
-                           hipStream_t s);
+                           const uint32_t* task, const uint32_t* toff, const uint32_t* soff, int64_t ntasks,
+                           double* part, const DevParams* prm, int64_t cmax, float G, float eps2, float* acc,
+                           float* pot, hipStream_t s);
 hipError_t launch_fmm_unpack(const uint64_t* keys, int64_t n, int32_t* out, hipStream_t s);
 // step.hip
 hipError_t launch_kick_drift(void* pos, void* vel, const float* acc, int64_t n, int dim, int f64,

@@ -68,6 +68,19 @@ def test_clustered_pareto_masses():
     _check(w.pos, w.mass, 16, 0.6, 1e-3, G=2.0)
 
 
+def test_long_partner_lists_are_split():
+    # a dense clump and a few bodies spread around it: leaves with thousands
+    # of direct partners, whose sums are cut into chunks on the GPU
+    rng = np.random.default_rng(77)
+    w = workloads.plummer_sphere(20000, seed=77)
+    pos = np.concatenate([w.pos * 0.05, rng.uniform(0.5, 1.5, (6, 3))]).astype(np.float32)
+    mass = np.full(len(pos), 1.0 / len(pos), np.float32)
+    t = oracle.Tree(pos.astype(np.float64), mass.astype(np.float64), 16)
+    _, op = oracle.fmm_pairs(t, 0.3)
+    assert np.bincount(op[:, 0]).max() > 4 * 256      # several chunks for some leaves
+    _check(pos, mass, 16, 0.3, 1e-3)
+
+
 def test_theta_zero_is_the_direct_sum():
     w = workloads.plummer_sphere(5000, seed=72)
     _, sizes, acc, pot, m2l, _ = _gpu_fmm(w.pos, w.mass, 16, 0.0, 1e-2)
