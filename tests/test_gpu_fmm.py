@@ -154,3 +154,43 @@ def test_full_size_plummer_1m():
     ea, ep = oracle.rel_l2(acc, a), oracle.rel_l2(pot, p)
     print(f"  m2l {sizes[1]} p2p {sizes[2]}: acc {ea:.2e} pot {ep:.2e}", flush=True)
     assert ea < TOL and ep < TOL
+
+
+def test_plan_capacities_and_retry():
+    # through the C ABI: capacities of 1 are refused with lower bounds of
+    # what is needed; growing them to those bounds converges, and the plan
+    # then gives the binding's result bit for bit
+    import ctypes as C
+    w = workloads.plummer_sphere(20000, seed=78)
+    dev = torch.device("cuda:0")
+    tc = treecode.Treecode(3, leaf_cap=16)
+    tc.build(torch.from_numpy(w.pos).to(dev), torch.from_numpy(w.mass).to(dev))
+    tc.moments()
+    L = treecode.lib()
+    ncells = tc.num_cells()
+    caps = [1, 1, 1]
+    sizes = np.zeros(3, dtype=np.int64)
+    refusals = 0
+    while True:
+        need = int(L.tc_fmm_buffer_bytes(ncells, *caps))
+        assert need > 0
+        buf = torch.empty(need, dtype=torch.uint8, device=dev)
+        rc = L.tc_fmm_plan(tc._h, 0.6, C.c_void_p(buf.data_ptr()), need, *caps, sizes.ctypes.data_as(C.c_void_p))
+        if rc == treecode.TC_OK:
+            break
+        assert rc == treecode.TC_EWORKSPACE
+        refusals += 1
+        assert refusals < 20
+        grown = [max(c, int(z)) for c, z in zip(caps, sizes)]
+        assert grown != caps                      # every refusal names a larger need
+        caps = grown
+    assert refusals >= 1
+    acc = torch.empty((w.n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty(w.n, dtype=torch.float32, device=dev)
+    assert L.tc_fmm_forces(tc._h, 1.0, 1e-2, C.c_void_p(acc.data_ptr()), C.c_void_p(pot.data_ptr())) == 0
+    del buf
+    tc.fmm_plan(0.6)
+    a2, p2 = tc.fmm_forces(1.0, 1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(acc.cpu().numpy(), a2.cpu().numpy())
+    np.testing.assert_array_equal(pot.cpu().numpy(), p2.cpu().numpy())
