@@ -472,6 +472,7 @@ __global__ void __launch_bounds__(256) k_topo_link(Cell* __restrict__ cells,
 template <int D>
 __device__ void leaf_moments(const Cell& c, const Body* __restrict__ bodies, Moments& mo) {
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+#pragma unroll 4
     for (int32_t j = c.begin; j < c.begin + c.count; ++j) {
         const Body b = bodies[j];
         M = M + b.m;
@@ -484,6 +485,7 @@ __device__ void leaf_moments(const Cell& c, const Body* __restrict__ bodies, Mom
     mo.com[0] = S0 / M; mo.com[1] = S1 / M; mo.com[2] = D == 3 ? S2 / M : 0.0;
     double Q[6] = {0, 0, 0, 0, 0, 0};
     if (D == 3) {
+#pragma unroll 4
         for (int32_t j = c.begin; j < c.begin + c.count; ++j) {
             const Body b = bodies[j];
             const double d0 = b.x - mo.com[0], d1 = b.y - mo.com[1], d2 = b.z - mo.com[2];
@@ -500,11 +502,24 @@ __device__ void leaf_moments(const Cell& c, const Body* __restrict__ bodies, Mom
     mo.pad = 0.0;
 }
 
+// Children of cell p (pre-order) in digit order: contiguous in level order
+// from the level-order index of p + 1, its first child; their pre-order
+// indices are loaded together instead of following the skip chain.
 template <int D>
-__device__ void internal_moments(int64_t p, const Cell* __restrict__ cells, const Moments* mom, Moments& mo) {
-    const int64_t end = cells[p].skip;
+__device__ void internal_moments(int64_t p, const Cell* __restrict__ cells, const uint32_t* __restrict__ bfs2pre,
+                                 const uint32_t* __restrict__ pre2bfs, const Moments* mom, Moments& mo) {
+    const int nch = cells[p].leaf_nch & 0x7fffffff;
+    const uint32_t first = pre2bfs[p + 1];
+    uint32_t kids[1 << 3];
+#pragma unroll
+    for (int i = 0; i < (1 << D); ++i)
+        if (i < nch) kids[i] = bfs2pre[first + i];
+    // fixed trip counts (predicated) let all children's loads issue together
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
-    for (int64_t ch = p + 1; ch < end; ch = cells[ch].skip) {
+#pragma unroll
+    for (int i = 0; i < (1 << D); ++i) {
+        if (i >= nch) continue;
+        const int64_t ch = kids[i];
         M = M + mom[ch].M;
         S0 = S0 + mom[ch].S[0];
         S1 = S1 + mom[ch].S[1];
@@ -515,7 +530,10 @@ __device__ void internal_moments(int64_t p, const Cell* __restrict__ cells, cons
     mo.com[0] = S0 / M; mo.com[1] = S1 / M; mo.com[2] = D == 3 ? S2 / M : 0.0;
     double Q[6] = {0, 0, 0, 0, 0, 0};
     if (D == 3) {
-        for (int64_t ch = p + 1; ch < end; ch = cells[ch].skip) {
+#pragma unroll
+        for (int i = 0; i < (1 << D); ++i) {
+            if (i >= nch) continue;
+            const int64_t ch = kids[i];
             const double s0 = mom[ch].com[0] - mo.com[0];
             const double s1 = mom[ch].com[1] - mo.com[1];
             const double s2 = mom[ch].com[2] - mo.com[2];
@@ -570,7 +588,7 @@ __global__ void __launch_bounds__(256) k_moments_level(const Cell* __restrict__ 
         const Cell c = cells[k];
         Moments mo;
         if (c.leaf_nch < 0) leaf_moments<D>(c, bodies, mo);
-        else internal_moments<D>(k, cells, mom, mo);
+        else internal_moments<D>(k, cells, bfs2pre, pre2bfs, mom, mo);
         mom[k] = mo;
         store_walk(walk, pre2bfs, k, c, mo);
     }
