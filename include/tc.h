@@ -46,7 +46,8 @@ enum tc_status_code {
     TC_EINVAL = -1,      /* bad argument: n, dim, leaf_cap, theta, eps, dt, null/misaligned pointer */
     TC_EWORKSPACE = -2,  /* no workspace, or smaller than tc_workspace_bytes() */
     TC_ESTATE = -3,      /* call order violated (see each call) */
-    TC_EHIP = -4,        /* a HIP runtime call or launch failed (tc_strerror names it) */
+    TC_EHIP = -4,        /* a HIP runtime call or launch failed, or an internal check
+                            that is never expected to fail did (tc_strerror names it) */
     TC_ENONFINITE = -5   /* sticky: a position or mass was NaN/Inf, or a mass was <= 0 */
 };
 

@@ -168,6 +168,13 @@ int hip_fail(tc_ctx* ctx, hipError_t e) {
     return TC_EHIP;
 }
 
+// An internal invariant that failed (never expected): reported as TC_EHIP
+// with its description for tc_strerror.
+int internal_fail(const char* what) {
+    snprintf(g_errbuf, sizeof(g_errbuf), "internal error: %s", what);
+    return TC_EHIP;
+}
+
 #define TC_HIP(ctx, expr)                                  \
     do {                                                   \
         hipError_t e_ = (expr);                            \
@@ -478,7 +485,7 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
     unsigned long long hc[3] = {0, 0, 0};
     bool overflow = false;
     for (int it = 0; nin > 0; ++it) {
-        if (it > 2 * (levels_for(3) + 1) + 1) return TC_EHIP;   // cannot happen for a valid tree
+        if (it > 2 * (levels_for(3) + 1) + 1) return internal_fail("FMM traversal deeper than the tree allows");
         TC_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 2, s));
         TC_HIP(ctx, launch_fmm_dtt(dc, theta, fa, nin, fb, f.capf, m2l, f.capm, p2p, f.capp, ctr,
                                    reinterpret_cast<uint32_t*>(B + f.off_bt),
@@ -523,7 +530,8 @@ int tc_fmm_plan(tc_ctx* ctx, double theta, void* buf, size_t bytes, int64_t fron
         sizes[0] = 2 * (int64_t)tot[1] + 1;          // frontier capacity that holds the partial sums
         return TC_EWORKSPACE;
     }
-    if ((int64_t)tot[0] > 2 * f.capk) return TC_EHIP;   // cannot happen: tasks <= leaves + P2P pairs
+    if ((int64_t)tot[0] > 2 * f.capk)                      // tasks <= leaves + P2P pairs <= 2 capk
+        return internal_fail("FMM leaf tasks exceed their buffer");
     TC_HIP(ctx, launch_fmm_tasks_fill(toff, ctx->prm(), C, reinterpret_cast<uint32_t*>(B + f.off_keys_b), s));
     ctx->fmm_ntasks = (int64_t)tot[0];
     TC_HIP(ctx, hipStreamSynchronize(s));
