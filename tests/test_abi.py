@@ -131,3 +131,37 @@ def test_closure_direct_lists_and_modes_check_arguments_first(L):
     assert L.tc_get_learned_counts(h, None, None) == T.TC_ESTATE
     L.tc_destroy(h)
     L.tc_destroy(h2)
+
+
+def test_size_limits(L):
+    # level-order cell indices are packed into 28 bits: the cell bound of
+    # n bodies must stay below 2^28
+    assert L.tc_workspace_bytes(100_000_000, 3, 16) > 0
+    assert L.tc_workspace_bytes(130_000_000, 3, 16) == 0
+    assert L.tc_workspace_bytes(2_000_000_001, 3, 256) == 0      # beyond TC_MAX_N
+
+
+def test_fmm_checks_arguments_first(L):
+    h = _ctx(L)
+    h2 = _ctx(L, dim=2)
+    fake = C.c_void_p(1 << 40)
+    sizes = (C.c_int64 * 3)()
+    assert L.tc_fmm_buffer_bytes(0, 10, 10, 10) == 0
+    assert L.tc_fmm_buffer_bytes(100, 0, 10, 10) == 0
+    assert L.tc_fmm_buffer_bytes(100, 10, 1 << 32, 10) == 0
+    a = L.tc_fmm_buffer_bytes(100, 10, 10, 10)
+    b = L.tc_fmm_buffer_bytes(100, 10, 1000, 10)
+    assert 0 < a < b
+    assert L.tc_fmm_plan(h, 0.5, None, 1 << 20, 10, 10, 10, sizes) == T.TC_EINVAL
+    assert L.tc_fmm_plan(h, 0.5, C.c_void_p((1 << 40) + 8), 1 << 20, 10, 10, 10, sizes) == T.TC_EINVAL
+    assert L.tc_fmm_plan(h, -0.5, fake, 1 << 20, 10, 10, 10, sizes) == T.TC_EINVAL
+    assert L.tc_fmm_plan(h, float("nan"), fake, 1 << 20, 10, 10, 10, sizes) == T.TC_EINVAL
+    assert L.tc_fmm_plan(h, 0.5, fake, 1 << 20, 10, 10, 10, None) == T.TC_EINVAL
+    assert L.tc_fmm_plan(h2, 0.5, fake, 1 << 20, 10, 10, 10, sizes) == T.TC_EINVAL   # 3D only
+    assert L.tc_fmm_plan(h, 0.5, fake, 1 << 20, 10, 10, 10, sizes) == T.TC_ESTATE    # no moments yet
+    assert L.tc_fmm_forces(h, 1.0, 0.0, None, None) == T.TC_EINVAL
+    assert L.tc_fmm_forces(h, 1.0, 1e-2, C.c_void_p((1 << 40) + 2), None) == T.TC_EINVAL
+    assert L.tc_fmm_forces(h, 1.0, 1e-2, None, None) == T.TC_ESTATE                  # no plan
+    assert L.tc_fmm_get_pairs(h, None, None) == T.TC_ESTATE
+    L.tc_destroy(h)
+    L.tc_destroy(h2)
