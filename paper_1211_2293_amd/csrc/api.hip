@@ -84,7 +84,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_gscan_part = take(4 * (size_t)l.cscan_tiles);
     l.off_gbeg = take(4 * (size_t)l.gmax);
     l.off_gcnt = take(4 * (size_t)l.gmax);
-    l.off_queue = take(4 * 2 * kXcd);
+    l.off_queue = take(4 * kQueueStride * kXcd);
     l.off_lvl_off = take(4 * 64);
     l.off_inv_perm = take(4 * (size_t)n);
     l.off_rcount = take(4 * (size_t)kResidMaxTargets);

@@ -221,23 +221,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
     uint32_t* S = s_stack[wv];
     float4* LQ = s_qlist[wv];
 
-    // Persistent waves.  The groups are split into one contiguous share per
-    // XCD (blocks are dealt round-robin over the 8 XCDs, so block b runs on
-    // XCD b mod 8): neighbouring groups walk nearly the same cells and then
-    // share one L2.  A wave takes the next group of its home share, then
-    // helps the other shares; every pop advances a counter, so every wave
-    // exits once all shares are drained.
-    const uint32_t NG = prm->ngroups;
-    const int home = (int)(blockIdx.x % kXcd);
+    // Persistent waves, scheduled over the groups by GroupSched.
+    const GroupSched sched = make_sched(queue, prm->ngroups, kWavesPerBlock);
     for (int hop = 0; hop < kXcd; ++hop) {
-        const int xq = (home + hop) % kXcd;
-        const uint32_t g_lo = (uint32_t)(((uint64_t)NG * xq) / kXcd);
-        const uint32_t g_hi = (uint32_t)(((uint64_t)NG * (xq + 1)) / kXcd);
-        // every lane takes part in the pop (lane 0 adds 1, the others 0), so
-        // the loop stays uniform; lane 0's result is the counter before its
-        // own increment whatever order the lanes are served in
-        uint32_t g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
-                                (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+        const int xq = (sched.home + hop) % kXcd;
+        const uint32_t g_hi = sched.share_lo(xq + 1);
+        uint32_t g = sched.first(xq, hop);
         while (g < g_hi) {
 
             const int64_t i0 = gbeg[g];
@@ -276,8 +265,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
                 m2p_out[g] = nm2p;
                 p2p_out[g] = np2p;
             }
-            g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
-                           (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+            g = sched.pop(xq);
         }
     }
 }
@@ -410,9 +398,7 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
     }
 }
 
-__global__ void k_reset_queue(uint32_t* queue) {
-    if (threadIdx.x < kXcd) queue[threadIdx.x] = 0u;
-}
+__global__ void k_reset_queue(uint32_t* queue) { reset_sched(queue); }
 
 }  // namespace
 

@@ -156,14 +156,11 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
     const double size = prm->size;
     const double mbar = mom[0].M / (double)n;          // mean body mass (root cell)
 
-    const uint32_t NG = prm->ngroups;
-    const int home = (int)(blockIdx.x % kXcd);
+    const GroupSched sched = make_sched(queue, prm->ngroups, kWPB);
     for (int hop = 0; hop < kXcd; ++hop) {
-        const int xq = (home + hop) % kXcd;
-        const uint32_t g_lo = (uint32_t)(((uint64_t)NG * xq) / kXcd);
-        const uint32_t g_hi = (uint32_t)(((uint64_t)NG * (xq + 1)) / kXcd);
-        uint32_t g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
-                                (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+        const int xq = (sched.home + hop) % kXcd;
+        const uint32_t g_hi = sched.share_lo(xq + 1);
+        uint32_t g = sched.first(xq, hop);
         while (g < g_hi) {
             const int64_t i0 = gbeg[g];
             const int gn = gcnt[g];
@@ -375,15 +372,12 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                 learned_out[g] = nlearn;
                 fallback_out[g] = nfall;
             }
-            g = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(
-                           (int)atomicAdd(&queue[xq], lane == 0 ? 1u : 0u));
+            g = sched.pop(xq);
         }
     }
 }
 
-__global__ void k_reset_queue_l(uint32_t* queue) {
-    if (threadIdx.x < kXcd) queue[threadIdx.x] = 0u;
-}
+__global__ void k_reset_queue_l(uint32_t* queue) { reset_sched(queue); }
 
 }  // namespace
 

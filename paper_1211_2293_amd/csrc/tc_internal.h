@@ -15,6 +15,7 @@ constexpr int kScanTile = 4096;     // elements per scan tile
 constexpr int kDiagBlocks = 512;    // fixed partial count of the FP64 diagnostics
 constexpr int kCluster = 1024;      // walk groups never straddle a cell of <= kCluster bodies
 constexpr int kXcd = 8;             // XCDs per MI355X: one work queue each
+constexpr int kQueueStride = 64;    // work-queue counters 256 B apart (own cache lines)
 
 // Status bits raised by kernels into the workspace's status word.
 constexpr uint32_t kFlagNonFinite = 1u;

@@ -201,6 +201,63 @@ static __device__ __forceinline__ WalkCell load_cell(const WalkCell* __restrict_
     return wc;
 }
 
+// Scheduling of the persistent walk kernels over NG groups.  The groups are
+// cut into one contiguous share per XCD (blocks are dealt round-robin over
+// the XCDs, so block b runs on XCD b mod 8): neighbouring groups walk nearly
+// the same cells and then share one L2.  The waves resident on XCD x take
+// the first groups of share x without any atomic, one each by their rank
+// among those waves; counter x hands out the rest of share x.  A wave works
+// through its own share, then helps the others.  Each pop reads the counter
+// first and skips a share found drained (counters only grow, so a stale
+// read costs at most one extra pop), and a share no larger than its static
+// part never touches its counter: returning atomics on one address from
+// thousands of waves serialise, and the memory accesses queued behind them
+// stall the walks.
+struct GroupSched {
+    uint32_t* queue;
+    uint32_t ng;       // groups
+    uint32_t rank;     // this wave's rank among the waves of its XCD
+    int home;          // this wave's XCD
+    int wpb;           // waves per block
+
+    __device__ uint32_t share_lo(int x) const { return (uint32_t)(((uint64_t)ng * x) / kXcd); }
+    // first group of share x handed out by its counter
+    __device__ uint32_t dyn_lo(int x) const {
+        const uint32_t blocks = (gridDim.x - (uint32_t)x + kXcd - 1) / kXcd;
+        return share_lo(x) + blocks * (uint32_t)wpb;
+    }
+    // the next group of share x from its counter, or share_lo(x + 1) once it is drained
+    __device__ uint32_t pop(int x) const {
+        const uint32_t lo = dyn_lo(x), hi = share_lo(x + 1);
+        if (lo >= hi) return hi;
+        uint32_t* q = queue + x * kQueueStride;
+        const uint32_t seen = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (seen >= hi - lo) return hi;
+        // every lane takes part (lane 0 adds 1, the others 0), so the loop
+        // stays uniform; lane 0's result is the counter before its own
+        // increment whatever order the lanes are served in
+        const int lane = threadIdx.x & (kWave - 1);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)atomicAdd(q, lane == 0 ? 1u : 0u));
+        return k >= hi - lo ? hi : lo + k;
+    }
+    // the first group a wave takes in share x (hop 0 is its own share)
+    __device__ uint32_t first(int x, int hop) const {
+        if (hop == 0 && share_lo(x) + rank < share_lo(x + 1)) return share_lo(x) + rank;
+        return pop(x);
+    }
+};
+
+// Requires gridDim.x >= kXcd, so every share has waves of its own XCD.
+static __device__ __forceinline__ GroupSched make_sched(uint32_t* queue, uint32_t ng, int wpb) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    return GroupSched{queue, ng, (blockIdx.x / kXcd) * (uint32_t)wpb + (uint32_t)wv, (int)(blockIdx.x % kXcd), wpb};
+}
+
+// Zero the kXcd counters (one block of 64 threads).
+static __device__ __forceinline__ void reset_sched(uint32_t* queue) {
+    if (threadIdx.x < kXcd) queue[threadIdx.x * kQueueStride] = 0u;
+}
 
 }  // namespace walk
 }  // namespace tc
