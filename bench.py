@@ -353,8 +353,8 @@ def learned_study(w, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="plummer-3d")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)

@@ -185,10 +185,10 @@ int tc_fmm_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * NULL).  For tests. */
 int tc_fmm_get_pairs(tc_ctx *ctx, int32_t *m2l, int32_t *p2p);
 
-/* Split walks (default on): for n <= 16384 the force evaluation of
- * tc_forces and tc_leapfrog cuts each group's walk into one task per
- * (level-1 cell, child) (64 in 3D, 16 in 2D) so that no single long walk
- * bounds the time; the tasks' FP32 partial sums are added in FP64 in a
+/* Split walks (default on): for n <= 12288 in 3D and n <= 24576 in 2D the
+ * force evaluation of tc_forces and tc_leapfrog cuts each group's walk into
+ * one task per (level-1 cell, child) (64 in 3D, 16 in 2D) so that no single
+ * long walk bounds the time; the tasks' FP32 partial sums are added in FP64 in a
  * fixed order.  The interactions and counts are those of the unsplit walk;
  * only the summation order differs.  Off: one wave per group at any n. */
 int tc_set_split(tc_ctx *ctx, int on);

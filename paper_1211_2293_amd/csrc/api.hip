@@ -85,6 +85,8 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_gbeg = take(4 * (size_t)l.gmax);
     l.off_gcnt = take(4 * (size_t)l.gmax);
     l.off_queue = take(4 * kQueueStride * kXcd);
+    l.off_gorder = take(10 * (size_t)l.gmax);   // order and costs (u32), run keys (u16)
+    l.off_bcost = take(4 * (size_t)n);
     l.off_lvl_off = take(4 * 64);
     l.off_inv_perm = take(4 * (size_t)n);
     l.off_rcount = take(4 * (size_t)kResidMaxTargets);
@@ -101,7 +103,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_pb_part = take(8 * (size_t)((n + 4095) / 4096));
     l.off_walkq = take(32 * (size_t)l.cmax);
     // partial sums of the split walk (64 tasks per group in 3D, 16 in 2D)
-    l.off_split = n <= kSplitMaxN ? take(16 * (size_t)(dim == 3 ? 64 : 16) * (size_t)n) : 0;
+    l.off_split = n <= split_max_n(dim) ? take(16 * (size_t)(dim == 3 ? 64 : 16) * (size_t)n) : 0;
     l.total = off;
     return l;
 }
@@ -132,7 +134,7 @@ struct tc_ctx {
     bool use_graph = false;
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
-    bool split = true;         // split walks when n <= kSplitMaxN
+    bool split = true;         // split walks when n <= split_max_n(dim)
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
     // the fast multipole plan (tc_fmm_plan) in the caller's buffer
@@ -277,7 +279,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, launch_quad_pack(ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_pre2bfs), ctx->prm(), l.cmax,
                                      walkq, ctx->stream));
     }
-    if (ctx->n <= kSplitMaxN && ctx->split) {
+    if (ctx->n <= split_max_n(ctx->dim) && ctx->split) {
         TC_HIP(ctx, launch_walk_force_split(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
                                             ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                             ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
@@ -290,8 +292,9 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
                                       ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                       ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
-                                      ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_queue),
-                                      ctx->n, ctx->dim, ctx->leaf_cap,
+                                      ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->at<uint32_t>(l.off_gorder),
+                                      ctx->at<uint32_t>(l.off_queue), ctx->at<uint32_t>(l.off_bcost), ctx->n,
+                                      ctx->dim, ctx->leaf_cap,
                                       (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
                                       ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
                                       ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->stream));

@@ -206,7 +206,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
                                                     const float4* __restrict__ bodies32,
                                                     const uint32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ gbeg,
-                                                    const int32_t* __restrict__ gcnt, uint32_t* queue,
+                                                    const int32_t* __restrict__ gcnt,
+                                                    const uint32_t* __restrict__ order, uint32_t* queue,
+                                                    uint32_t* __restrict__ bcost,
                                                     int lpl_log2, float G, float eps2,
                                                     const DevParams* __restrict__ prm,
                                                     float* __restrict__ acc, float* __restrict__ pot,
@@ -221,7 +223,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
     uint32_t* S = s_stack[wv];
     float4* LQ = s_qlist[wv];
 
-    // Persistent waves, scheduled over the groups by GroupSched.
+    // Persistent waves, scheduled by GroupSched over the positions of
+    // order (a permutation of the groups within each XCD share).
     const GroupSched sched = make_sched(queue, prm->ngroups, kWavesPerBlock);
     for (int hop = 0; hop < kXcd; ++hop) {
         const int xq = (sched.home + hop) % kXcd;
@@ -229,8 +232,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
         uint32_t g = sched.first(xq, hop);
         while (g < g_hi) {
 
-            const int64_t i0 = gbeg[g];
-            const int gn = gcnt[g];
+            const uint32_t gi = order[g];
+            const int64_t i0 = gbeg[gi];
+            const int gn = gcnt[gi];
             const int64_t i = i0 + lane;
             const bool valid = lane < gn;
             const Body me = bodies[valid ? i : i0];
@@ -260,10 +264,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
                 acc[o * D + 1] = G * (a.sy + a.cy);
                 if (D == 3) acc[o * D + 2] = G * (a.sz + a.cz);
                 pot[o] = G * ph;
+                // the list length, for the next evaluation's schedule
+                const int64_t lc = nm2p + np2p;
+                bcost[o] = lc > 0xffffffffll ? 0xffffffffu : (uint32_t)lc;
             }
             if (lane == 0) {
-                m2p_out[g] = nm2p;
-                p2p_out[g] = np2p;
+                m2p_out[gi] = nm2p;
+                p2p_out[gi] = np2p;
             }
             g = sched.pop(xq);
         }
@@ -398,7 +405,95 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
     }
 }
 
-__global__ void k_reset_queue(uint32_t* queue) { reset_sched(queue); }
+
+// The order in which the persistent waves take the groups of each XCD
+// share: runs of kOrderChunk consecutive groups, by decreasing cost.  A
+// group's cost is the list length that its middle body had in the previous
+// force evaluation (bodies are named by their input index, so this survives
+// a rebuild; group boundaries move from step to step, so neither a group
+// index nor a group's first body, often the previous group's last, does as
+// well).  Long walks then start first and the walks still running when a
+// share drains are short ones.  Longer runs keep more neighbouring groups,
+// which read the same cells and bodies, running side by side in one XCD's
+// L2, but they lengthen the tail; on a 1M-body Plummer sphere runs of 1, 4,
+// 16, 64 and 256 groups fetched 560, 500, 400, 320 and 275 MB from HBM per
+// launch (280 GB/s at most: the kernel is ALU-bound) and took 2.0, 2.11,
+// 2.09, 2.16 and 2.19 ms, hence runs of one.  Only the schedule depends on
+// the costs: each group's walk and sums are the same in any order, so stale
+// or missing costs cost time, never accuracy.  k_group_keys gathers the
+// costs, one thread per group; k_group_order sorts the runs of one share
+// per block (and zeroes that share's work counter), by the mean cost of a
+// run in buckets of 1/16 of an octave (log2 with four fraction bits);
+// places within a bucket are taken with LDS atomics, so they may differ
+// from run to run.
+constexpr int kOrderBuckets = 512;
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderChunk = 1;
+
+__device__ __forceinline__ int cost_bucket(uint32_t v) {
+    if (v < 1) return 0;
+    const int e = 31 - __builtin_clz(v);
+    const uint32_t frac = (e >= 4 ? (v >> (e - 4)) : (v << (4 - e))) & 15u;
+    const int b = 16 * e + (int)frac;
+    return b < kOrderBuckets ? b : kOrderBuckets - 1;
+}
+
+__global__ void k_group_keys(const uint32_t* __restrict__ bcost, const uint32_t* __restrict__ perm,
+                             const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
+                             const DevParams* __restrict__ prm, uint32_t* __restrict__ gcost) {
+    const uint32_t NG = prm->ngroups;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < NG; g += gridDim.x * blockDim.x)
+        gcost[g] = bcost[perm[gbeg[g] + gcnt[g] / 2]];
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_group_order(const uint32_t* __restrict__ gcost,
+                                                               const DevParams* __restrict__ prm,
+                                                               uint16_t* __restrict__ ckey,
+                                                               uint32_t* __restrict__ order,
+                                                               uint32_t* __restrict__ queue) {
+    __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ uint32_t scan[2][kOrderBuckets];
+    const uint32_t NG = prm->ngroups;
+    const int x = (int)blockIdx.x;
+    const uint32_t lo = (uint32_t)(((uint64_t)NG * x) / kXcd), hi = (uint32_t)(((uint64_t)NG * (x + 1)) / kXcd);
+    const uint32_t nc = (hi - lo + kOrderChunk - 1) / kOrderChunk;
+    const int t = (int)threadIdx.x;
+    if (t == 0) queue[x * kQueueStride] = 0u;
+    if (t < kOrderBuckets) hist[t] = 0u;
+    __syncthreads();
+    // each run's bucket (kept at its first group's key) and the groups per bucket
+    for (uint32_t c = (uint32_t)t; c < nc; c += kOrderThreads) {
+        const uint32_t c0 = lo + c * kOrderChunk, c1 = min(hi, c0 + kOrderChunk);
+        uint64_t sum = 0;
+        for (uint32_t g = c0; g < c1; ++g) sum += gcost[g];
+        const uint64_t mean = sum / (c1 - c0);
+        const int b = cost_bucket(mean > 0xffffffffull ? 0xffffffffu : (uint32_t)mean);
+        ckey[c0] = (uint16_t)b;
+        atomicAdd(&hist[b], c1 - c0);
+    }
+    __syncthreads();
+    // inclusive scan over the buckets from the most expensive down
+    int cur = 0;
+    if (t < kOrderBuckets) scan[0][t] = hist[kOrderBuckets - 1 - t];
+    __syncthreads();
+    for (int d = 1; d < kOrderBuckets; d <<= 1) {
+        if (t < kOrderBuckets) scan[cur ^ 1][t] = scan[cur][t] + (t >= d ? scan[cur][t - d] : 0u);
+        cur ^= 1;
+        __syncthreads();
+    }
+    // hist becomes the next free place of each bucket
+    if (t < kOrderBuckets) {
+        const int r = kOrderBuckets - 1 - t;             // bucket of scan position t
+        hist[r] = scan[cur][t] - hist[r];
+    }
+    __syncthreads();
+    // the same runs as above, each read back by the thread that keyed it
+    for (uint32_t c = (uint32_t)t; c < nc; c += kOrderThreads) {
+        const uint32_t c0 = lo + c * kOrderChunk, c1 = min(hi, c0 + kOrderChunk);
+        const uint32_t at = lo + atomicAdd(&hist[ckey[c0]], c1 - c0);
+        for (uint32_t g = c0; g < c1; ++g) order[at + (g - c0)] = g;
+    }
+}
 
 }  // namespace
 
@@ -446,7 +541,8 @@ hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, co
 
 hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Body* bodies, const float4* bodies32,
                              const uint32_t* perm,
-                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
+                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* order,
+                             uint32_t* queue, uint32_t* bcost,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
                              int64_t* p2p, bool plain, hipStream_t s) {
@@ -472,10 +568,15 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     const unsigned nb = (unsigned)want;
     int lpl_log2 = 0;                                   // lanes per leaf: next power of two, <= 64
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, queue);
+    // the group order: costs and run keys (after the gmax places of order),
+    // then the counting sort of each share
+    uint32_t* gcost = order + gmax;
+    uint16_t* ckey = reinterpret_cast<uint16_t*>(order + 2 * gmax);
+    hipLaunchKernelGGL(k_group_keys, dim3(grid_for(gmax)), dim3(256), 0, s, bcost, perm, gbeg, gcnt, prm, gcost);
+    hipLaunchKernelGGL(k_group_order, dim3(kXcd), dim3(kOrderThreads), 0, s, gcost, prm, ckey, order, queue);
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
     hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
-                       gbeg, gcnt, queue, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
+                       gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
     if (dim == 3 && walkq) {
         if (plain) TC_LAUNCH_WF(3, true, true);
         else TC_LAUNCH_WF(3, false, true);

@@ -87,7 +87,7 @@ struct Layout {
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
         off_walk, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
-        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
+        off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_gorder, off_bcost, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
         off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, off_walkq, off_split, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
     int64_t gmax;        // bound on walk groups
@@ -131,10 +131,12 @@ hipError_t launch_export(const Cell* cells, const Moments* mom, int dim, int64_t
                          int32_t* count, int32_t* parent, int32_t* skip, int32_t* nch,
                          int32_t* leaf, double* M, double* com, double* Q, hipStream_t s);
 // force.hip
+// order: room for 2 gmax uint32 (places, costs) and gmax uint16 keys; bcost:
+// n uint32 per-body list lengths, written for the next call's schedule.
 hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Body* bodies, const float4* bodies32,
                              const uint32_t* perm,
-                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* queue,
-                             int64_t n, int dim, int leaf_cap, float G, float eps2,
+                             const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* order,
+                             uint32_t* queue, uint32_t* bcost, int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
                              int64_t* p2p, bool plain, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
@@ -143,10 +145,13 @@ hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_
 struct MlpState;
 hipError_t launch_direct64(const Body* bodies, const uint32_t* inv_perm, int64_t n, const int32_t* targets, int nt,
                            double eps2, double G, DevParams* prm, double* acc, double* pot, hipStream_t s);
-// Split walks pay off up to about 2e4 bodies (measured: 2.0x faster force
-// evaluations at 2,000 bodies, 1.6x at 10,000, even at 20,000, slower
-// beyond); for n at most kSplitMaxN the workspace holds their partial sums.
-constexpr int64_t kSplitMaxN = 16384;
+// Split walks pay off for small n only (measured on 3D Plummer spheres:
+// 1.6x faster force evaluations at 2,000 bodies, 1.14x at 10,000, 0.64x at
+// 16,384; on 2D disks 1.25x at 16,384, 0.90x at 32,768); for n at most
+// split_max_n(dim) they are used and the workspace holds their partial sums.
+constexpr int64_t kSplitMaxN3 = 12288;
+constexpr int64_t kSplitMaxN2 = 24576;
+inline int64_t split_max_n(int dim) { return dim == 3 ? kSplitMaxN3 : kSplitMaxN2; }
 hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, const Body* bodies,
                                    const float4* bodies32, const uint32_t* perm, const int32_t* gbeg,
                                    const int32_t* gcnt, int64_t gmax, int64_t n, int dim, int leaf_cap, float G,

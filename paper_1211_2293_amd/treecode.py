@@ -446,7 +446,7 @@ class Treecode:
         return m2l[:sizes[1]], p2p[:sizes[2]]
 
     def set_split(self, on: bool):
-        """Split walks for n <= 16384 (default on)."""
+        """Split walks for n <= 12288 in 3D, n <= 24576 in 2D (default on)."""
         _check(lib().tc_set_split(self._h, int(bool(on))))
 
     def set_multipole(self, order: int):
