@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
 
 
 // The order in which the persistent waves take the groups of each XCD
-// share: runs of kOrderChunk consecutive groups, by decreasing cost.  A
+// share: runs of consecutive groups, by decreasing cost.  A
 // group's cost is the list length that its middle body had in the previous
 // force evaluation (bodies are named by their input index, so this survives
 // a rebuild; group boundaries move from step to step, so neither a group
@@ -415,11 +415,17 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
 // well).  Long walks then start first and the walks still running when a
 // share drains are short ones.  Longer runs keep more neighbouring groups,
 // which read the same cells and bodies, running side by side in one XCD's
-// L2, but they lengthen the tail; on a 1M-body Plummer sphere runs of 1, 4,
-// 16, 64 and 256 groups fetched 560, 500, 400, 320 and 275 MB from HBM per
-// launch (280 GB/s at most: the kernel is ALU-bound) and took 2.0, 2.11,
-// 2.09, 2.16 and 2.19 ms, hence runs of one.  Only the schedule depends on
-// the costs: each group's walk and sums are the same in any order, so stale
+// L2, but they lengthen the tail, which matters less the more groups each
+// wave takes.  Runs are max(1, groups / (4 waves)) long, and from 16 groups
+// per wave on the groups are taken in key order.  Measured: on a 1M-body
+// Plummer sphere (3.5 groups per wave) runs of 1, 4, 16, 64 and 256 groups
+// fetched 560, 500, 400, 320 and 275 MB from HBM per launch (280 GB/s at
+// most: the kernel is ALU-bound) and took 2.0, 2.11, 2.09, 2.16 and
+// 2.19 ms (2.2 ms in key order); on 4.2M bodies of two Plummer spheres (14
+// groups per wave) runs of 3 took 1% less than key order; on 16.7M
+// clustered bodies (57 groups per wave) single groups took 15.7 ms, runs of
+// 14, 16 or 64 14.9-15.3 ms, key order 14.7-15.2 ms.  Only the schedule
+// depends on the costs: each group's walk and sums are the same in any order, so stale
 // or missing costs cost time, never accuracy.  k_group_keys gathers the
 // costs, one thread per group; k_group_order sorts the runs of one share
 // per block (and zeroes that share's work counter), by the mean cost of a
@@ -428,7 +434,6 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
 // from run to run.
 constexpr int kOrderBuckets = 512;
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderChunk = 1;
 
 __device__ __forceinline__ int cost_bucket(uint32_t v) {
     if (v < 1) return 0;
@@ -450,20 +455,26 @@ __global__ void __launch_bounds__(kOrderThreads) k_group_order(const uint32_t* _
                                                                const DevParams* __restrict__ prm,
                                                                uint16_t* __restrict__ ckey,
                                                                uint32_t* __restrict__ order,
-                                                               uint32_t* __restrict__ queue) {
+                                                               uint32_t* __restrict__ queue, uint32_t waves) {
     __shared__ uint32_t hist[kOrderBuckets];
     __shared__ uint32_t scan[2][kOrderBuckets];
     const uint32_t NG = prm->ngroups;
     const int x = (int)blockIdx.x;
     const uint32_t lo = (uint32_t)(((uint64_t)NG * x) / kXcd), hi = (uint32_t)(((uint64_t)NG * (x + 1)) / kXcd);
-    const uint32_t nc = (hi - lo + kOrderChunk - 1) / kOrderChunk;
+    const uint32_t W = max(waves, 1u);
     const int t = (int)threadIdx.x;
     if (t == 0) queue[x * kQueueStride] = 0u;
+    if (NG >= 16u * W) {                                 // key order
+        for (uint32_t g = lo + (uint32_t)t; g < hi; g += kOrderThreads) order[g] = g;
+        return;
+    }
+    const uint32_t run = max(1u, NG / (4u * W));
+    const uint32_t nc = (hi - lo + run - 1) / run;
     if (t < kOrderBuckets) hist[t] = 0u;
     __syncthreads();
     // each run's bucket (kept at its first group's key) and the groups per bucket
     for (uint32_t c = (uint32_t)t; c < nc; c += kOrderThreads) {
-        const uint32_t c0 = lo + c * kOrderChunk, c1 = min(hi, c0 + kOrderChunk);
+        const uint32_t c0 = lo + c * run, c1 = min(hi, c0 + run);
         uint64_t sum = 0;
         for (uint32_t g = c0; g < c1; ++g) sum += gcost[g];
         const uint64_t mean = sum / (c1 - c0);
@@ -489,7 +500,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_group_order(const uint32_t* _
     __syncthreads();
     // the same runs as above, each read back by the thread that keyed it
     for (uint32_t c = (uint32_t)t; c < nc; c += kOrderThreads) {
-        const uint32_t c0 = lo + c * kOrderChunk, c1 = min(hi, c0 + kOrderChunk);
+        const uint32_t c0 = lo + c * run, c1 = min(hi, c0 + run);
         const uint32_t at = lo + atomicAdd(&hist[ckey[c0]], c1 - c0);
         for (uint32_t g = c0; g < c1; ++g) order[at + (g - c0)] = g;
     }
@@ -573,7 +584,8 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     uint32_t* gcost = order + gmax;
     uint16_t* ckey = reinterpret_cast<uint16_t*>(order + 2 * gmax);
     hipLaunchKernelGGL(k_group_keys, dim3(grid_for(gmax)), dim3(256), 0, s, bcost, perm, gbeg, gcnt, prm, gcost);
-    hipLaunchKernelGGL(k_group_order, dim3(kXcd), dim3(kOrderThreads), 0, s, gcost, prm, ckey, order, queue);
+    hipLaunchKernelGGL(k_group_order, dim3(kXcd), dim3(kOrderThreads), 0, s, gcost, prm, ckey, order, queue,
+                       (uint32_t)(nb * kWavesPerBlock));
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
     hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
                        gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
