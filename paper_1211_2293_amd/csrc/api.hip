@@ -59,6 +59,8 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_cells = take(sizeof(Cell) * (size_t)l.cmax);
     l.off_mom = take(sizeof(Moments) * (size_t)l.cmax);
     l.off_walk = take(sizeof(WalkCell) * (size_t)l.cmax);
+    l.off_mom_lvl = take(sizeof(Moments) * (size_t)l.cmax);   // level-order copy for the moments pass
+    l.off_kids = take(8 * (size_t)l.cmax);
     l.off_acc = take(4 * (size_t)n * dim);
     l.off_pot = take(4 * (size_t)n);
     l.off_m2p = 0;   // placed after the group bound is known
@@ -247,7 +249,8 @@ int do_moments(tc_ctx* ctx, hipStream_t s) {
     const Layout& l = ctx->lay;
     TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
                                ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
-                               ctx->at<uint32_t>(l.off_lvl_off), ctx->at<Moments>(l.off_mom),
+                               ctx->at<uint32_t>(l.off_lvl_off), ctx->prm(), ctx->at<Moments>(l.off_mom),
+                               ctx->at<Moments>(l.off_mom_lvl), ctx->at<uint2>(l.off_kids),
                                ctx->at<WalkCell>(l.off_walk), s));
     ctx->state = kMoments;
     return TC_OK;

@@ -85,7 +85,7 @@ struct Layout {
     int64_t scan_tiles;
     size_t off_params, off_keys_a, off_keys_b, off_idx_a, off_idx_b, off_bodies, off_range,
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
-        off_walk, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
+        off_walk, off_mom_lvl, off_kids, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
         off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_gorder, off_bcost, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
         off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, off_walkq, off_split, total;
@@ -122,7 +122,8 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
                          hipStream_t s);
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
-                          Moments* mom, WalkCell* walk, hipStream_t s);
+                          const DevParams* prm, Moments* mom, Moments* mom_lvl, uint2* kids, WalkCell* walk,
+                          hipStream_t s);
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
                       const uint32_t* pre2bfs, WalkCell* walk, double* rc_out, const DevParams* prm,
                       hipStream_t s);
