@@ -35,7 +35,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.leaf_cap = leaf_cap;
     l.cmax = (int64_t)levels_for(dim) * (n / (leaf_cap + 1)) + n + 1;
     l.groups = (n + kGroup - 1) / kGroup;
-    l.sort_tiles = (n + kSortTile - 1) / kSortTile;
+    l.sort_tiles = sort_tiles_max(n);
     l.scan_tiles = (n + kScanTile - 1) / kScanTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -68,7 +68,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_bbox_part = take(7 * 8 * 1024);
     l.off_diag_part = take(8 * 8 * (size_t)kDiagBlocks);
     l.off_diag_out = take(8 * 8);
-    l.lvl_tiles = (l.cmax + kSortTile - 1) / kSortTile;
+    l.lvl_tiles = sort_tiles_max(l.cmax);
     l.off_lvl_keys_a = take(8 * (size_t)l.cmax);
     l.off_lvl_keys_b = take(8 * (size_t)l.cmax);
     l.off_lvl_idx_a = take(4 * (size_t)l.cmax);
@@ -219,7 +219,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     TC_HIP(ctx, launch_sort(ctx->at<uint64_t>(l.off_keys_a), ctx->at<uint32_t>(l.off_idx_a),
                             ctx->at<uint64_t>(l.off_keys_b), ctx->at<uint32_t>(l.off_idx_b), n,
                             dim * levels_for(dim), ctx->at<uint32_t>(l.off_hist),
-                            ctx->at<uint32_t>(l.off_digit_tot), l.sort_tiles, s));
+                            ctx->at<uint32_t>(l.off_digit_tot), s));
     TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
                               ctx->at<Body>(l.off_bodies), ctx->at<float4>(l.off_bodies32), s));
     TC_HIP(ctx, launch_topology(ctx->at<uint64_t>(l.off_keys_a), n, dim, leaf_cap,
@@ -230,8 +230,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
                                    ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
                                    ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
-                                   ctx->at<uint32_t>(l.off_digit_tot), l.lvl_tiles,
-                                   ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<uint32_t>(l.off_lvl_off), s));
+                                   ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<uint32_t>(l.off_lvl_off), s));
     TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
                               ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
                               l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
@@ -392,7 +391,7 @@ bool fmm_layout(int64_t C, int64_t capf, int64_t capm, int64_t capp, FmmLayout* 
     f->capm = capm;
     f->capp = capp;
     f->capk = capm > capp ? capm : capp;
-    f->tiles = (f->capk + kSortTile - 1) / kSortTile;
+    f->tiles = sort_tiles_max(f->capk);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -431,7 +430,7 @@ hipError_t fmm_sort(uint64_t* keys, int64_t n, int bits, uint8_t* buf, const Fmm
     if (n <= 0) return hipSuccess;
     return launch_sort(keys, nullptr, reinterpret_cast<uint64_t*>(buf + f.off_keys_b), nullptr, n,
                        16 * ((bits + 15) / 16), reinterpret_cast<uint32_t*>(buf + f.off_hist),
-                       reinterpret_cast<uint32_t*>(buf + f.off_digit), (n + kSortTile - 1) / kSortTile, s);
+                       reinterpret_cast<uint32_t*>(buf + f.off_digit), s);
 }
 
 }  // namespace

@@ -190,9 +190,8 @@ __global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t
 // after round: 20.2 us per pass of 1M keys, 16.0 us with the loads first).
 // Recording every round's per-wave digit counts and placing all keys after
 // one prefix pass (three barriers per tile instead of three per round) took
-// 18.4 us, and tiles of 1024 or 2048 keys 18.6 and 16.6 us.
-constexpr int kSortPer = kSortTile / 256;   // keys per thread in a tile
-
+// 18.4 us.  PER keys per thread, tiles of 256 PER keys (sort_per).
+template <int PER>
 __global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
                                                    uint32_t* __restrict__ hist, int64_t tiles) {
     __shared__ uint32_t cnt[4][256];
@@ -200,9 +199,9 @@ __global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ 
     for (int a = 0; a < 4; ++a) cnt[a][t] = 0;
     __syncthreads();
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kSortTile;
+    const int64_t base = tile * (256 * PER);
 #pragma unroll 4
-    for (int j = 0; j < kSortPer; ++j) {
+    for (int j = 0; j < PER; ++j) {
         const int64_t i = base + j * 256 + t;
         if (i < n) atomicAdd(&cnt[w][(unsigned)(keys[i] >> shift) & 255u], 1u);
     }
@@ -246,6 +245,7 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, 
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
+template <int PER>
 __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       int64_t n, int shift, const uint32_t* __restrict__ hist,
@@ -259,19 +259,19 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
     const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
     s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
     for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
-    uint64_t kr[kSortPer];
-    uint32_t vr[kSortPer];
+    uint64_t kr[PER];
+    uint32_t vr[PER];
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) {
-        const int64_t i = tile * kSortTile + r * 256 + t;
+    for (int r = 0; r < PER; ++r) {
+        const int64_t i = tile * (256 * PER) + r * 256 + t;
         kr[r] = i < n ? kin[i] : 0ull;
         vr[r] = (i < n && vin) ? vin[i] : 0u;
     }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) {
-        const bool valid = tile * kSortTile + r * 256 + t < n;
+    for (int r = 0; r < PER; ++r) {
+        const bool valid = tile * (256 * PER) + r * 256 + t < n;
         const uint64_t k = kr[r];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
@@ -829,10 +829,10 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
     return hipGetLastError();
 }
 
-hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
-                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
-                       int64_t tiles, hipStream_t s) {
-    const int passes = (key_bits + 7) / 8;    // even for 62/63-bit keys: result lands in _a
+template <int PER>
+static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, int64_t n, int passes,
+                        uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
+    const int64_t tiles = (n + 256 * PER - 1) / (256 * PER);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const bool even = (p % 2) == 0;
@@ -840,10 +840,20 @@ hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint
         const uint32_t* vin = even ? idx_a : idx_b;
         uint64_t* kout = even ? keys_b : keys_a;
         uint32_t* vout = even ? idx_b : idx_a;
-        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_sort_hist<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, shift, hist, tiles);
         hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
-        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout, n,
+        hipLaunchKernelGGL(k_sort_scatter<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout, n,
                            shift, (const uint32_t*)hist, (const uint32_t*)digit_tot, tiles);
+    }
+}
+
+hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
+                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
+    const int passes = (key_bits + 7) / 8;    // even for 62/63-bit keys: result lands in _a
+    switch (sort_per(n)) {
+        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
+        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
+        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
     }
     return hipGetLastError();
 }
@@ -888,15 +898,14 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
 
 hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
                               uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, uint32_t* lvl_off,
-                              hipStream_t s) {
+                              uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off, hipStream_t s) {
     hipLaunchKernelGGL(k_level_keys, dim3(grid_for(cmax)), dim3(256), 0, s, cells, prm, cmax, keys_a, idx_a);
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)tiles), dim3(256), 0, s, (const uint64_t*)keys_a, cmax, 0,
-                       hist, tiles);
-    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
-    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)tiles), dim3(256), 0, s, (const uint64_t*)keys_a,
-                       (const uint32_t*)idx_a, keys_b, idx_b, cmax, 0, (const uint32_t*)hist,
-                       (const uint32_t*)digit_tot, tiles);
+    // one 8-bit pass by level (stable, so pre-order within a level)
+    switch (sort_per(cmax)) {
+        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
+        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
+        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
+    }
     hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
                        pre2bfs);
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, (const uint32_t*)digit_tot, levels_for(dim),

@@ -10,7 +10,15 @@ namespace tc {
 
 constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kGroup = 64;          // bodies per walk group = one wave
-constexpr int kSortTile = 4096;     // keys per radix-sort tile (256 threads x 16)
+// Radix-sort tiles: 256 threads x sort_per(n) keys.  One block per tile
+// and few blocks leave the passes latency-bound, so smaller sorts use
+// smaller tiles (measured per pass: 1M keys 16.0 us with 4096-key tiles,
+// 16.6 with 2048, 18.6 with 1024; 262k keys 14.2 us with 4096, 9.4 with
+// 2048, 7.3 with 1024): the largest tile that still gives 256 tiles.
+inline int sort_per(int64_t n) { return n >= (int64_t)256 * 4096 ? 16 : n >= (int64_t)256 * 2048 ? 8 : 4; }
+inline int64_t sort_tiles(int64_t n) { return (n + 256 * sort_per(n) - 1) / (256 * sort_per(n)); }
+// Tiles a histogram buffer must hold for any sort of at most n keys.
+inline int64_t sort_tiles_max(int64_t n) { return (n + 1023) / 1024; }
 constexpr int kScanTile = 4096;     // elements per scan tile
 constexpr int kDiagBlocks = 512;    // fixed partial count of the FP64 diagnostics
 constexpr int kCluster = 1024;      // walk groups never straddle a cell of <= kCluster bodies
@@ -104,9 +112,9 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
                        uint64_t* keys, uint32_t* idx, hipStream_t s);
 // LSD radix sort (stable) of the low key_bits bits; idx_a / idx_b may both be
 // null for keys without a payload.
+// hist holds 256 x sort_tiles_max(n) counts.
 hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
-                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot,
-                       int64_t tiles, hipStream_t s);
+                       int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t s);
 hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
                          int dim, int f64, Body* bodies, float4* bodies32, hipStream_t s);
 hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
@@ -115,7 +123,7 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
                            int64_t cmax, DevParams* prm, hipStream_t s);
 hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
                               uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, int64_t tiles, uint32_t* pre2bfs, uint32_t* lvl_off,
+                              uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
                               hipStream_t s);
 hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
                          int64_t scan_tiles, int32_t* gbeg, int32_t* gcnt, int64_t gmax, DevParams* prm,
