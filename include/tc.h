@@ -61,7 +61,10 @@ enum tc_dtype { TC_F32 = 0, TC_F64 = 1 };
  * hipStream_t; NULL = the null stream).  *out receives the context. */
 int tc_create(tc_ctx **out, int dim, void *hip_stream);
 
-/* Destroy a context (NULL is a no-op).  Does not touch the workspace. */
+/* Destroy a context (NULL is a no-op).  Does not touch the workspace.
+ * Besides host memory, a context holds one event and 256 bytes of pinned
+ * host memory, into which each tc_build copies its tree's level offsets
+ * (the moments pass of later builds sizes its launches by that depth). */
 void tc_destroy(tc_ctx *ctx);
 
 /* Bytes of device workspace needed for n bodies in dim dimensions with the

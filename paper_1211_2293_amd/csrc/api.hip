@@ -134,6 +134,15 @@ struct tc_ctx {
     bool mlp_loaded = false;
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = false;
+    bool capturing = false;    // inside the graph capture of the pre-force part
+    // Depth of an earlier tree, for the moments pass: each build copies its
+    // level offsets to pinned host memory behind an event; a later call
+    // reads them once the event has completed.  Only launch counts depend
+    // on it, never results.
+    uint32_t* lvl_host = nullptr;
+    hipEvent_t lvl_ev = nullptr;
+    bool lvl_pending = false;
+    int lvl_depth = -1;        // deepest populated level of the last harvested build
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
     bool split = true;         // split walks when n <= split_max_n(dim)
@@ -207,6 +216,18 @@ hipEvent_t pooled_event(tc_ctx* ctx) {
 }
 
 // Everything tc_build enqueues, after its checks.
+// Take the depth of the last build whose level offsets have arrived on the
+// host (never waits).
+void harvest_depth(tc_ctx* ctx) {
+    if (!ctx->lvl_pending || hipEventQuery(ctx->lvl_ev) != hipSuccess) return;
+    const int L = levels_for(ctx->dim);
+    int deepest = 0;
+    for (int l = 0; l <= L; ++l)
+        if (ctx->lvl_host[l + 1] > ctx->lvl_host[l]) deepest = l;
+    ctx->lvl_depth = deepest;
+    ctx->lvl_pending = false;
+}
+
 int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf_cap, int dtype, hipStream_t s) {
     const int dim = ctx->dim;
     ctx->lay = make_layout(n, dim, leaf_cap);
@@ -230,7 +251,18 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
                                    ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
                                    ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
-                                   ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<uint32_t>(l.off_lvl_off), s));
+                                   ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
+                                   ctx->at<uint32_t>(l.off_lvl_off), s));
+    // the depth of this tree, for later moments passes (not inside a capture)
+    if (!ctx->capturing) {
+        harvest_depth(ctx);
+        if (!ctx->lvl_host) TC_HIP(ctx, hipHostMalloc((void**)&ctx->lvl_host, 4 * 64, hipHostMallocDefault));
+        if (!ctx->lvl_ev) TC_HIP(ctx, hipEventCreateWithFlags(&ctx->lvl_ev, hipEventDisableTiming));
+        TC_HIP(ctx, hipMemcpyAsync(ctx->lvl_host, ctx->at<uint32_t>(l.off_lvl_off),
+                                   4 * (size_t)(levels_for(dim) + 2), hipMemcpyDeviceToHost, s));
+        TC_HIP(ctx, hipEventRecord(ctx->lvl_ev, s));
+        ctx->lvl_pending = true;
+    }
     TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
                               ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
                               l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
@@ -250,7 +282,9 @@ int do_moments(tc_ctx* ctx, hipStream_t s) {
                                ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
                                ctx->at<uint32_t>(l.off_lvl_off), ctx->prm(), ctx->at<Moments>(l.off_mom),
                                ctx->at<Moments>(l.off_mom_lvl), ctx->at<uint2>(l.off_kids),
-                               ctx->at<WalkCell>(l.off_walk), s));
+                               ctx->at<WalkCell>(l.off_walk),
+                               // per-level launches down to two levels below the earlier tree's depth
+                               ctx->lvl_depth < 0 ? -1 : ctx->lvl_depth + 2, s));
     ctx->state = kMoments;
     return TC_OK;
 }
@@ -345,7 +379,9 @@ int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
     if (!ctx->g_exec || !(key == ctx->g_key)) {
         drop_graph(ctx);
         TC_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        ctx->capturing = true;
         const int rc = enqueue_pre_force(ctx, dt, pos, vel, cs);
+        ctx->capturing = false;
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(cs, &g);
         if (rc != TC_OK || e != hipSuccess) {
@@ -620,6 +656,9 @@ int tc_create(tc_ctx** out, int dim, void* hip_stream) {
 
 void tc_destroy(tc_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->lvl_ev) (void)hipEventSynchronize(ctx->lvl_ev);
+    if (ctx->lvl_ev) (void)hipEventDestroy(ctx->lvl_ev);
+    if (ctx->lvl_host) (void)hipHostFree(ctx->lvl_host);
     for (hipEvent_t e : ctx->ev_pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     drop_graph(ctx);

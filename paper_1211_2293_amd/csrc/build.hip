@@ -613,6 +613,51 @@ __global__ void __launch_bounds__(256) k_leaf_moments(const Cell* __restrict__ c
     }
 }
 
+// One internal cell of the level passes.
+template <int D>
+__device__ __forceinline__ void moments_of_internal(int64_t b, const uint32_t* __restrict__ bfs2pre,
+                                                    const uint2* __restrict__ kids, Moments* mom, Moments* mom_lvl,
+                                                    WalkCell* __restrict__ walk) {
+    const uint2 kc = kids[b];
+    if (kc.y == kLeafKids) return;
+    Moments mo;
+    internal_moments<D>(mom_lvl + kc.x, (int)kc.y, mo);
+    mom_lvl[b] = mo;
+    mom[bfs2pre[b]] = mo;
+    WalkCell w;
+    w.cx = mo.com[0];
+    w.cy = mo.com[1];
+    w.cz = mo.com[2];
+    w.rcrit2 = INFINITY;
+    w.m = (float)mo.M;
+    w.a = (int32_t)kc.x;
+    w.b = (int32_t)kc.y;
+    w.pad = 0;
+    walk[b] = w;
+}
+
+// The levels deeper than `top`, deepest first, in one block: every launch
+// costs a few microseconds even when its level is empty, and most of the
+// deepest levels are.  `top` comes from the depth of an earlier tree, so the
+// levels here are usually empty or nearly so; any cells they do hold are
+// still done (in order: a barrier separates the levels, and the block's
+// waves share one CU's L1).
+constexpr int kDeepThreads = 1024;
+
+template <int D>
+__global__ void __launch_bounds__(kDeepThreads) k_moments_deep(const uint32_t* __restrict__ bfs2pre,
+                                                               const uint32_t* __restrict__ lvl_off, int top,
+                                                               int deepest, const uint2* __restrict__ kids,
+                                                               Moments* mom, Moments* mom_lvl,
+                                                               WalkCell* __restrict__ walk) {
+    for (int l = deepest; l > top; --l) {
+        const int64_t b0 = lvl_off[l], b1 = lvl_off[l + 1];
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += kDeepThreads)
+            moments_of_internal<D>(b, bfs2pre, kids, mom, mom_lvl, walk);
+        __syncthreads();
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_moments_level(const uint32_t* __restrict__ bfs2pre,
                                                        const uint32_t* __restrict__ lvl_off, int level,
@@ -620,24 +665,8 @@ __global__ void __launch_bounds__(256) k_moments_level(const uint32_t* __restric
                                                        Moments* mom_lvl, WalkCell* __restrict__ walk) {
     const int64_t b0 = lvl_off[level], b1 = lvl_off[level + 1];
     for (int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < b1;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const uint2 kc = kids[b];
-        if (kc.y == kLeafKids) continue;
-        Moments mo;
-        internal_moments<D>(mom_lvl + kc.x, (int)kc.y, mo);
-        mom_lvl[b] = mo;
-        mom[bfs2pre[b]] = mo;
-        WalkCell w;
-        w.cx = mo.com[0];
-        w.cy = mo.com[1];
-        w.cz = mo.com[2];
-        w.rcrit2 = INFINITY;
-        w.m = (float)mo.M;
-        w.a = (int32_t)kc.x;
-        w.b = (int32_t)kc.y;
-        w.pad = 0;
-        walk[b] = w;
-    }
+         b += (int64_t)gridDim.x * blockDim.x)
+        moments_of_internal<D>(b, bfs2pre, kids, mom, mom_lvl, walk);
 }
 
 // Start of each level in level order (levels 0..L, plus the end), from the
@@ -931,7 +960,9 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
                           const DevParams* prm, Moments* mom, Moments* mom_lvl, uint2* kids, WalkCell* walk,
-                          hipStream_t s) {
+                          int top, hipStream_t s) {
+    const int L = levels_for(dim);
+    if (top < 0 || top > L) top = L;
     const unsigned nl = grid_for(cmax);
     if (dim == 3)
         hipLaunchKernelGGL(k_leaf_moments<3>, dim3(nl), dim3(256), 0, s, cells, bodies, pre2bfs, prm, cmax, mom,
@@ -939,8 +970,16 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
     else
         hipLaunchKernelGGL(k_leaf_moments<2>, dim3(nl), dim3(256), 0, s, cells, bodies, pre2bfs, prm, cmax, mom,
                            mom_lvl, kids, walk);
+    if (top < L) {
+        if (dim == 3)
+            hipLaunchKernelGGL(k_moments_deep<3>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, top, L,
+                               (const uint2*)kids, mom, mom_lvl, walk);
+        else
+            hipLaunchKernelGGL(k_moments_deep<2>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, top, L,
+                               (const uint2*)kids, mom, mom_lvl, walk);
+    }
     const unsigned nb = grid_for(cmax, 2048);
-    for (int l = levels_for(dim); l >= 0; --l) {
+    for (int l = top; l >= 0; --l) {
         if (dim == 3)
             hipLaunchKernelGGL(k_moments_level<3>, dim3(nb), dim3(256), 0, s, bfs2pre, lvl_off, l, kids, mom, mom_lvl,
                                walk);

@@ -131,7 +131,8 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
                           const DevParams* prm, Moments* mom, Moments* mom_lvl, uint2* kids, WalkCell* walk,
-                          hipStream_t s);
+                          int top, hipStream_t s);
+// Levels above top (deeper) go to one single-block launch; top < 0 = none.
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
                       const uint32_t* pre2bfs, WalkCell* walk, double* rc_out, const DevParams* prm,
                       hipStream_t s);

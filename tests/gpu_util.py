@@ -14,13 +14,15 @@ def to_dev(a, dtype=None):
     return t.cuda()
 
 
-def gpu_tree(pos, mass, leaf_cap, theta=None, G=1.0, eps=None, moments=True):
-    """Build (and optionally walk + force) on the GPU; return numpy results."""
+def gpu_tree(pos, mass, leaf_cap, theta=None, G=1.0, eps=None, moments=True, tc=None):
+    """Build (and optionally walk + force) on the GPU, in a new context or in
+    the given one; return numpy results."""
     import torch
 
     from paper_1211_2293_amd import treecode
     dim = pos.shape[1]
-    tc = treecode.Treecode(dim, leaf_cap=leaf_cap)
+    if tc is None:
+        tc = treecode.Treecode(dim, leaf_cap=leaf_cap)
     p = to_dev(pos)
     m = to_dev(mass)
     tc.build(p, m)

@@ -72,3 +72,27 @@ def test_nonfinite_is_sticky_until_next_build():
     m[3] = -1.0
     g2 = gpu_tree(pos, m, 8)
     assert g2["status"] == treecode.TC_ENONFINITE
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_context_reuse_with_a_deeper_tree(dim):
+    """A context sizes its per-level moments launches by the depth of an
+    earlier tree; deeper levels go to one single-block pass.  A shallow tree
+    first, then a much deeper one (two tight clumps), then the shallow one
+    again: every tree is still bit-exact."""
+    import torch
+
+    from paper_1211_2293_amd import treecode
+    rng = np.random.default_rng(51)
+    shallow = rng.uniform(0, 1, (4000, dim)).astype(np.float32)
+    deep = _two_clumps(3000)[:, :dim].copy()
+    deep[:50] = rng.uniform(0, 1, (50, dim))
+    tc = treecode.Treecode(dim, leaf_cap=8)
+    for pos in (shallow, deep, deep, shallow):
+        mass = np.ones(len(pos), np.float32)
+        g = gpu_tree(pos, mass, 8, tc=tc)
+        torch.cuda.synchronize()
+        assert g["status"] == treecode.TC_OK
+        t = oracle.Tree(pos.astype(np.float64), mass.astype(np.float64), 8)
+        print(f"dim={dim} n={len(pos)} depth {int(g['cells']['level'].max())}", flush=True)
+        assert_tree_equal(g, t)
