@@ -196,6 +196,8 @@ int internal_fail(const char* what) {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+static_assert(TC_MAX_LEAF_CAP == kMaxLeafCap, "the topology pass sizes its LDS window by kMaxLeafCap");
+
 bool valid_sizes(int64_t n, int dim, int leaf_cap) {
     if (n < 1 || n > TC_MAX_N) return false;
     if (dim != 2 && dim != 3) return false;

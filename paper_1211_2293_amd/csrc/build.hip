@@ -192,8 +192,11 @@ __global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t
 // one prefix pass (three barriers per tile instead of three per round) took
 // 18.4 us.  PER keys per thread, tiles of 256 PER keys (sort_per).
 template <int PER>
-__global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+// n_live (nullable, device): sort only the first min(n, *n_live) keys.
+__global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                   const uint32_t* __restrict__ n_live, int shift,
                                                    uint32_t* __restrict__ hist, int64_t tiles) {
+    if (n_live && (int64_t)*n_live < n) n = *n_live;
     __shared__ uint32_t cnt[4][256];
     const int t = threadIdx.x, w = t >> 6;
     for (int a = 0; a < 4; ++a) cnt[a][t] = 0;
@@ -248,8 +251,10 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, 
 template <int PER>
 __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                      int64_t n, int shift, const uint32_t* __restrict__ hist,
+                                                      int64_t n, const uint32_t* __restrict__ n_live, int shift,
+                                                      const uint32_t* __restrict__ hist,
                                                       const uint32_t* __restrict__ digit_tot, int64_t tiles) {
+    if (n_live && (int64_t)*n_live < n) n = *n_live;
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ uint32_t s_w[4];
@@ -383,27 +388,39 @@ __device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
     return D == 3 ? (z - 1) / 3 : (z - 2) / 2;
 }
 
+// Per body i: a = the shallowest level at which a cell starts at i (one
+// past the digits i shares with i - 1), lstar = the deepest level of a cell
+// containing i that is not a leaf, plus one (leaf_cap + 1 consecutive
+// bodies sharing c digits put an internal cell at level c).  The window
+// depths c_j = common digits of bodies j and j + leaf_cap are computed once
+// per block tile into LDS, and each body takes the maximum over the windows
+// that contain it.
+constexpr int kTopoTile = 256;
+
 template <int D>
-__global__ void __launch_bounds__(256) k_topo_count(const uint64_t* __restrict__ keys, int64_t n, int leaf_cap,
-                                                    uint32_t* __restrict__ range, uint32_t* __restrict__ nper) {
+__global__ void __launch_bounds__(kTopoTile) k_topo_count(const uint64_t* __restrict__ keys, int64_t n, int leaf_cap,
+                                                          uint32_t* __restrict__ range, uint32_t* __restrict__ nper) {
     constexpr int L = D == 3 ? 21 : 31;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int a = (i == 0) ? 0 : common_digits<D>(keys[i - 1], keys[i]) + 1;
-        // deepest level whose cell around i holds more than leaf_cap bodies
-        int deep = -1;
-        int64_t j0 = i - leaf_cap;
-        if (j0 < 0) j0 = 0;
-        int64_t j1 = n - 1 - leaf_cap;
-        if (j1 > i) j1 = i;
-        for (int64_t j = j0; j <= j1; ++j) {
-            const int c = common_digits<D>(keys[j], keys[j + leaf_cap]);
-            deep = c > deep ? c : deep;
+    __shared__ int8_t s_c[kTopoTile + kMaxLeafCap];   // c_j for j = i0 - leaf_cap .. i0 + kTopoTile - 1
+    const int t = threadIdx.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * kTopoTile; i0 < n; i0 += (int64_t)gridDim.x * kTopoTile) {
+        for (int q = t; q < kTopoTile + leaf_cap; q += kTopoTile) {
+            const int64_t j = i0 - leaf_cap + q;
+            s_c[q] = (j >= 0 && j + leaf_cap < n) ? (int8_t)common_digits<D>(keys[j], keys[j + leaf_cap]) : (int8_t)-1;
         }
-        int lstar = 0;
-        if (deep >= 0) lstar = (deep < L - 1 ? deep : L - 1) + 1;
-        range[i] = (uint32_t)a | ((uint32_t)lstar << 8);
-        nper[i] = lstar >= a ? (uint32_t)(lstar - a + 1) : 0u;
+        __syncthreads();
+        const int64_t i = i0 + t;
+        if (i < n) {
+            const int a = (i == 0) ? 0 : common_digits<D>(keys[i - 1], keys[i]) + 1;
+            // windows j = i - leaf_cap .. i (those out of range hold -1)
+            int deep = -1;
+            for (int q = t; q <= t + leaf_cap; ++q) deep = s_c[q] > deep ? s_c[q] : deep;
+            int lstar = 0;
+            if (deep >= 0) lstar = (deep < L - 1 ? deep : L - 1) + 1;
+            range[i] = (uint32_t)a | ((uint32_t)lstar << 8);
+            nper[i] = lstar >= a ? (uint32_t)(lstar - a + 1) : 0u;
+        }
+        __syncthreads();
     }
 }
 
@@ -724,17 +741,17 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
 
 // --------------------------------------------------------- level order ----
 // Level order of the cells: a stable sort of (level, pre-order index), one
-// 8-bit radix pass over all cmax slots (unused slots sort last).  Within a
-// level, pre-order keeps children of one parent adjacent.
+// 8-bit radix pass over the live cells (the sort reads their count on the
+// device; the grid covers the cmax bound).  Within a level, pre-order keeps
+// children of one parent adjacent.
 
 __global__ void __launch_bounds__(256) k_level_keys(const Cell* __restrict__ cells, const DevParams* __restrict__ prm,
                                                     int64_t cmax, uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ idx) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cmax;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        keys[k] = k < C ? (uint64_t)cells[k].level : 255ull;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C; k += (int64_t)gridDim.x * blockDim.x) {
+        keys[k] = (uint64_t)cells[k].level;
         idx[k] = (uint32_t)k;
     }
 }
@@ -859,8 +876,8 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
 }
 
 template <int PER>
-static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, int64_t n, int passes,
-                        uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
+static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, int64_t n,
+                        const uint32_t* n_live, int passes, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
     const int64_t tiles = (n + 256 * PER - 1) / (256 * PER);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
@@ -869,10 +886,11 @@ static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uin
         const uint32_t* vin = even ? idx_a : idx_b;
         uint64_t* kout = even ? keys_b : keys_a;
         uint32_t* vout = even ? idx_b : idx_a;
-        hipLaunchKernelGGL(k_sort_hist<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_sort_hist<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, n_live, shift, hist,
+                           tiles);
         hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
         hipLaunchKernelGGL(k_sort_scatter<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout, n,
-                           shift, (const uint32_t*)hist, (const uint32_t*)digit_tot, tiles);
+                           n_live, shift, (const uint32_t*)hist, (const uint32_t*)digit_tot, tiles);
     }
 }
 
@@ -880,9 +898,9 @@ hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint
                        int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
     const int passes = (key_bits + 7) / 8;    // even for 62/63-bit keys: result lands in _a
     switch (sort_per(n)) {
-        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
-        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
-        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, n, passes, hist, digit_tot, s); break;
+        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
+        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
+        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
     }
     return hipGetLastError();
 }
@@ -931,9 +949,9 @@ hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const De
     hipLaunchKernelGGL(k_level_keys, dim3(grid_for(cmax)), dim3(256), 0, s, cells, prm, cmax, keys_a, idx_a);
     // one 8-bit pass by level (stable, so pre-order within a level)
     switch (sort_per(cmax)) {
-        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
-        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
-        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, cmax, 1, hist, digit_tot, s); break;
+        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
+        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
+        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
     }
     hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
                        pre2bfs);

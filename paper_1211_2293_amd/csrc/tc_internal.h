@@ -10,6 +10,7 @@ namespace tc {
 
 constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kGroup = 64;          // bodies per walk group = one wave
+constexpr int kMaxLeafCap = 256;    // the largest leaf_cap (TC_MAX_LEAF_CAP)
 // Radix-sort tiles: 256 threads x sort_per(n) keys.  One block per tile
 // and few blocks leave the passes latency-bound, so smaller sorts use
 // smaller tiles (measured per pass: 1M keys 16.0 us with 4096-key tiles,
