@@ -324,12 +324,25 @@ __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ pos, const
 
 // ---------------------------------------------------------------- scan ----
 // Exclusive scan of u32 values: out[i] = sum_{j<i} in[j], out[n] = total.
+// With n_live (device, nullable) only the first m = min(n, *n_live) values
+// are read and written, and the total also goes to out[m]; the grids cover
+// n.
+
+__device__ __forceinline__ int64_t live_count(int64_t n, const uint32_t* n_live) {
+    return (n_live && (int64_t)*n_live < n) ? (int64_t)*n_live : n;
+}
 
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                     const uint32_t* __restrict__ n_live,
                                                      uint32_t* __restrict__ part) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
+    n = live_count(n, n_live);
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= n) {                       // the whole tile is past the live values
+        if (threadIdx.x == 0) part[blockIdx.x] = 0u;
+        return;
+    }
     uint32_t s = 0;
     for (int j = 0; j < kScanTile / 256; ++j) {
         const int64_t i = base + j * 256 + threadIdx.x;
@@ -340,7 +353,8 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict_
 }
 
 __global__ void __launch_bounds__(256) k_scan_part(uint32_t* __restrict__ part, int64_t tiles,
-                                                   uint32_t* __restrict__ out, int64_t n) {
+                                                   uint32_t* __restrict__ out, int64_t n,
+                                                   const uint32_t* __restrict__ n_live) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
     uint32_t carry = 0;
@@ -352,14 +366,20 @@ __global__ void __launch_bounds__(256) k_scan_part(uint32_t* __restrict__ part, 
         carry += s_tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) {
+        out[n] = carry;
+        out[live_count(n, n_live)] = carry;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                    const uint32_t* __restrict__ n_live,
                                                     const uint32_t* __restrict__ part,
                                                     uint32_t* __restrict__ out) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
+    n = live_count(n, n_live);
+    if ((int64_t)blockIdx.x * kScanTile >= n) return;
     constexpr int kItems = kScanTile / 256;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
@@ -780,15 +800,10 @@ __global__ void __launch_bounds__(256) k_group_count(const Cell* __restrict__ ce
                                                      int64_t cmax, uint32_t* __restrict__ gper) {
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cmax;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t v = 0;
-        if (k < C) {
-            const Cell c = cells[k];
-            const bool cluster = small_cell(c) && (k == 0 || !small_cell(cells[c.parent]));
-            if (cluster) v = (uint32_t)((c.count + kGroup - 1) / kGroup);
-        }
-        gper[k] = v;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C; k += (int64_t)gridDim.x * blockDim.x) {
+        const Cell c = cells[k];
+        const bool cluster = small_cell(c) && (k == 0 || !small_cell(cells[c.parent]));
+        gper[k] = cluster ? (uint32_t)((c.count + kGroup - 1) / kGroup) : 0u;
     }
 }
 
@@ -920,9 +935,10 @@ hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm
 
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)part, out);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)nullptr, part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n, (const uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)nullptr,
+                       (const uint32_t*)part, out);
     return hipGetLastError();
 }
 
@@ -933,9 +949,11 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     const unsigned nb = grid_for(n);
     if (dim == 3) hipLaunchKernelGGL(k_topo_count<3>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
     else hipLaunchKernelGGL(k_topo_count<2>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n, scan_part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, cstart, n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n,
+                       (const uint32_t*)nullptr, scan_part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, cstart, n, (const uint32_t*)nullptr);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n,
+                       (const uint32_t*)nullptr,
                        (const uint32_t*)scan_part, cstart);
     if (dim == 3) hipLaunchKernelGGL(k_topo_emit<3>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
     else hipLaunchKernelGGL(k_topo_emit<2>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
@@ -965,10 +983,12 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
                          hipStream_t s) {
     const unsigned nb = grid_for(cmax);
     hipLaunchKernelGGL(k_group_count, dim3(nb), dim3(256), 0, s, cells, (const DevParams*)prm, cmax, gper);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax,
+    // over the live cells only (their count is on the device)
+    const uint32_t* live = &prm->ncells;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax, live,
                        scan_part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, goff, cmax);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax,
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, goff, cmax, live);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax, live,
                        (const uint32_t*)scan_part, goff);
     hipLaunchKernelGGL(k_group_emit, dim3(nb), dim3(256), 0, s, cells, (const uint32_t*)goff, prm, cmax, gbeg,
                        gcnt, gmax);
