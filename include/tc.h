@@ -188,13 +188,18 @@ int tc_fmm_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * NULL).  For tests. */
 int tc_fmm_get_pairs(tc_ctx *ctx, int32_t *m2l, int32_t *p2p);
 
-/* Split walks (default on): for n <= 12288 in 3D and n <= 24576 in 2D the
- * force evaluation of tc_forces and tc_leapfrog cuts each group's walk into
- * one task per (level-1 cell, child) (64 in 3D, 16 in 2D) so that no single
- * long walk bounds the time; the tasks' FP32 partial sums are added in FP64 in a
- * fixed order.  The interactions and counts are those of the unsplit walk;
- * only the summation order differs.  Off: one wave per group at any n. */
-int tc_set_split(tc_ctx *ctx, int on);
+/* How a group's walk is spread over waves, for sizes with fewer walk groups
+ * than the GPU keeps waves resident, where one wave per group leaves a lone,
+ * latency-bound walk per SIMD.  mode 1 (the default): for n <= 163840 a
+ * block of 4 waves shares each group's walk (the cells of one level, 5 to 7
+ * by n and dim, dealt out among them) and adds their FP32 partial sums in
+ * FP64 in wave order.  mode 2: for n <= 12288 in 3D and n <= 24576 in 2D
+ * each group's walk is cut into one task per (level-1 cell, child) (64 in
+ * 3D, 16 in 2D) whose FP32 partial sums are added in FP64 in a fixed order,
+ * and above that as mode 1.  mode 0: one wave per group at any n.  The
+ * interactions and counts are those of the one-wave walk in every mode;
+ * only the summation order differs.  TC_EINVAL for another mode. */
+int tc_set_split(tc_ctx *ctx, int mode);
 
 /* Expansion order of accepted cells in tc_forces and tc_leapfrog: 1 (the
  * default) is the monopole of §3.1; 2 (3D only, else TC_EINVAL) adds each

@@ -145,7 +145,7 @@ struct tc_ctx {
     int lvl_depth = -1;        // deepest populated level of the last harvested build
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
-    bool split = true;         // split walks when n <= split_max_n(dim)
+    int split = 1;             // 0: one wave per group; 1: shared walks (coop); 2: split walks up to split_max_n
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
     // the fast multipole plan (tc_fmm_plan) in the caller's buffer
@@ -317,7 +317,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         TC_HIP(ctx, launch_quad_pack(ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_pre2bfs), ctx->prm(), l.cmax,
                                      walkq, ctx->stream));
     }
-    if (ctx->n <= split_max_n(ctx->dim) && ctx->split) {
+    if (ctx->split == 2 && ctx->n <= split_max_n(ctx->dim)) {
         TC_HIP(ctx, launch_walk_force_split(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
                                             ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
                                             ctx->at<uint32_t>(l.off_idx_a), ctx->at<int32_t>(l.off_gbeg),
@@ -335,7 +335,8 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
                                       ctx->dim, ctx->leaf_cap,
                                       (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
                                       ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
-                                      ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->stream));
+                                      ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->split != 0,
+                                      ctx->at<uint32_t>(l.off_lvl_off), ctx->stream));
     }
     if (ctx->timing) {
         TC_HIP(ctx, hipEventRecord(e1, ctx->stream));
@@ -783,9 +784,9 @@ int tc_lists_forces(tc_ctx* ctx, double G, double eps, uint32_t* lists, int64_t 
     return TC_OK;
 }
 
-int tc_set_split(tc_ctx* ctx, int on) {
-    if (!ctx) return TC_EINVAL;
-    ctx->split = on != 0;
+int tc_set_split(tc_ctx* ctx, int mode) {
+    if (!ctx || mode < 0 || mode > 2) return TC_EINVAL;
+    ctx->split = mode;
     return TC_OK;
 }
 

@@ -38,13 +38,20 @@ constexpr int kWavesPerBlock = 4;
 // root alone for a whole walk) and sum its list into a, counting the cell
 // entries in nm2p and the body entries in np2p.  The group's box is
 // [lo, hi], its FP32 origin (rx, ry, rz), this lane's body (xi, yi, zi).
-template <int D, bool PLAIN, bool QUAD>
+// With NP > 1 (a walk from the root shared by NP waves) this wave walks
+// part `part` of it: the cells above the deal level (level-order indices
+// below deal_lo) are tested by every part but their entries kept by part 0
+// only; the cells of the deal level ([deal_lo, deal_hi) in level order) are
+// dealt out by index modulo NP; everything deeper follows its ancestor at
+// the deal level.  The parts' lists together are the whole walk's.
+template <int D, bool PLAIN, bool QUAD, int NP = 1>
 __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, const float4* __restrict__ walkq,
                                            const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
                                            float4* L, uint32_t* S, float4* LQ, int lpl_log2, float eps2,
                                            double lox, double hix, double loy, double hiy, double loz, double hiz,
                                            double rx, double ry, double rz, float xi, float yi, float zi,
-                                           uint32_t first, int first_len, Acc& a, int64_t& nm2p, int64_t& np2p) {
+                                           uint32_t first, int first_len, Acc& a, int64_t& nm2p, int64_t& np2p,
+                                           int part = 0, uint32_t deal_lo = 0, uint32_t deal_hi = 0) {
     constexpr int R = D == 3 ? 8 : 4;                    // lanes (cells) per popped range
     constexpr int RP = kWave / R;                        // ranges per full round
     constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
@@ -61,6 +68,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
         // memory round trips of a round overlap.
         int top = 0;
         bool vc = lane < first_len;
+        uint32_t cidx = first + (uint32_t)lane;              // level-order index of the tested cell
         WalkCell wc = load_cell(walk, first + (uint32_t)lane, vc);
         float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;   // quadrupole of the tested cell
         if (QUAD && vc) {
@@ -77,10 +85,13 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 const double dzm = fmax(fmax(loz - wc.cz, 0.0), wc.cz - hiz);
                 d2 = d2 + dzm * dzm;
             }
-            const bool leaf = vc && wc.b < 0;
-            const bool accept = vc && d2 > wc.rcrit2;
-            const bool opened = vc && !accept && !leaf;
-            const bool direct = leaf && !accept;
+            const bool own = vc && (NP == 1 || cidx < deal_lo || cidx >= deal_hi || (int)(cidx % NP) == part);
+            const bool emit = NP == 1 || cidx >= deal_lo || part == 0;
+            const bool leaf = own && wc.b < 0;
+            const bool acc0 = own && d2 > wc.rcrit2;
+            const bool opened = own && !acc0 && !leaf;
+            const bool accept = acc0 && emit;
+            const bool direct = leaf && !acc0 && emit;
 
             // push the children ranges of opened cells
             const uint64_t O = __ballot(opened);
@@ -92,6 +103,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
             // reserve is free) and start loading its cells
             more = top > 0;
             bool vcn = false;
+            uint32_t cidxn = 0;
             WalkCell wcn;
             float4 q0n = make_float4(0.f, 0.f, 0.f, 0.f), q1n = q0n;
             if (more) {
@@ -102,6 +114,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 top -= nr;
                 const int rlen = (int)(packed & 7u) + 1;
                 vcn = rr < nr && j < rlen;
+                cidxn = (packed >> 3) + j;
                 wcn = load_cell(walk, (packed >> 3) + j, vcn);
                 if (QUAD && vcn) {
                     const uint32_t bq = (packed >> 3) + j;
@@ -190,6 +203,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
             wave_lds_sync();
             wc = wcn;
             vc = vcn;
+            cidx = cidxn;
             if (QUAD) {
                 q0 = q0n;
                 q1 = q1n;
@@ -274,6 +288,101 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
             }
             g = sched.pop(xq);
         }
+    }
+}
+
+// Small and mid-size problems: with fewer groups than resident waves, every
+// wave walks its group alone on its SIMD and the walk's latency sets the
+// time.  Here a block of kCoopParts waves takes one group at a time
+// (positions of the cost order of k_group_order, strided by the grid):
+// each wave walks its part of the tree (walk_group with NP parts, the cells
+// of level `deal` dealt out) and sums its own list, and the parts' FP32 sums
+// are added in FP64 in wave order.  The interactions and counts are those
+// of the one-wave walk; only the summation order differs.  The near field,
+// where most of a group's list comes from, lies in a few cells around the
+// group, so a shallow deal level leaves one part with most of the work
+// (3D Plummer, 65,536 bodies: 1.15x over one wave dealing level 3, 1.7x
+// dealing level 5 or 6); one too deep leaves the parts repeating the walk
+// above it.  coop_deal_level holds the measured choice.
+constexpr int kCoopParts = kWavesPerBlock;
+
+template <int D, bool PLAIN, bool QUAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force_coop(
+    const WalkCell* __restrict__ walk, const float4* __restrict__ walkq, const Body* __restrict__ bodies,
+    const float4* __restrict__ bodies32, const uint32_t* __restrict__ perm, const int32_t* __restrict__ gbeg,
+    const int32_t* __restrict__ gcnt, const uint32_t* __restrict__ order, uint32_t* __restrict__ bcost,
+    const uint32_t* __restrict__ lvl_off, int deal, int lpl_log2, float G, float eps2,
+    const DevParams* __restrict__ prm,
+    float* __restrict__ acc, float* __restrict__ pot, int64_t* __restrict__ m2p_out, int64_t* __restrict__ p2p_out) {
+    __shared__ float4 s_list[kWavesPerBlock][kListCap];
+    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
+    __shared__ float4 s_qlist[kWavesPerBlock][QUAD ? 3 * kQuadCap : 1];
+    __shared__ double s_part[kCoopParts - 1][4][kWave];
+    __shared__ int64_t s_cnt[kCoopParts - 1][2];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const uint32_t deal_lo = lvl_off[deal], deal_hi = lvl_off[deal + 1];   // the cells dealt out
+    // blocks take the positions of order in strides of the grid
+    for (uint32_t pos = blockIdx.x; pos < prm->ngroups; pos += gridDim.x) {
+        const uint32_t g = order[pos];
+        const int64_t i0 = gbeg[g];
+        const int gn = gcnt[g];
+        const int64_t i = i0 + lane;
+        const bool valid = lane < gn;
+        const Body me = bodies[valid ? i : i0];
+        const double lox = uniform(wave_min(me.x)), hix = uniform(wave_max(me.x));
+        const double loy = uniform(wave_min(me.y)), hiy = uniform(wave_max(me.y));
+        const double loz = D == 3 ? uniform(wave_min(me.z)) : 0.0;
+        const double hiz = D == 3 ? uniform(wave_max(me.z)) : 0.0;
+        const double rx = (lox + hix) * 0.5, ry = (loy + hiy) * 0.5, rz = (loz + hiz) * 0.5;
+        const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
+
+        Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int64_t nm2p = 0, np2p = 0;
+        walk_group<D, PLAIN, QUAD, kCoopParts>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv],
+                                               lpl_log2, eps2, lox, hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi,
+                                               0u, 1, a, nm2p, np2p, wv, deal_lo, deal_hi);
+        double px = (double)a.sx + (double)a.cx, py = (double)a.sy + (double)a.cy;
+        double pz = (double)a.sz + (double)a.cz, pp = (double)a.sp + (double)a.cp;
+        if (wv > 0) {
+            s_part[wv - 1][0][lane] = px;
+            s_part[wv - 1][1][lane] = py;
+            s_part[wv - 1][2][lane] = pz;
+            s_part[wv - 1][3][lane] = pp;
+            if (lane == 0) {
+                s_cnt[wv - 1][0] = nm2p;
+                s_cnt[wv - 1][1] = np2p;
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            for (int w = 0; w < kCoopParts - 1; ++w) {
+                px += s_part[w][0][lane];
+                py += s_part[w][1][lane];
+                pz += s_part[w][2][lane];
+                pp += s_part[w][3][lane];
+                nm2p += s_cnt[w][0];
+                np2p += s_cnt[w][1];
+            }
+            if (valid) {
+                // the body met itself once as a direct entry (in one of the
+                // parts): its -m/eps potential term is removed as in the
+                // one-wave kernel
+                const float mself = (float)me.m;
+                pp += (double)(mself * __builtin_amdgcn_rsqf(eps2));
+                const int64_t o = perm[i];
+                acc[o * D + 0] = (float)((double)G * px);
+                acc[o * D + 1] = (float)((double)G * py);
+                if (D == 3) acc[o * D + 2] = (float)((double)G * pz);
+                pot[o] = (float)((double)G * pp);
+                const int64_t lc = nm2p + np2p;
+                bcost[o] = lc > 0xffffffffll ? 0xffffffffu : (uint32_t)lc;
+            }
+            if (lane == 0) {
+                m2p_out[g] = nm2p;
+                p2p_out[g] = np2p;
+            }
+        }
+        __syncthreads();                                  // s_part is reused by the next group
     }
 }
 
@@ -556,8 +665,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
                              uint32_t* queue, uint32_t* bcost,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, bool plain, hipStream_t s) {
-    (void)n;
+                             int64_t* p2p, bool plain, bool share, const uint32_t* lvl_off, hipStream_t s) {
     // as many blocks as can be resident at once (the waves are persistent)
     static int resident[3] = {0, 0, 0};                // 2D, 3D, 3D with quadrupoles
     const int kind = dim == 3 ? (walkq ? 2 : 1) : 0;
@@ -586,6 +694,26 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     hipLaunchKernelGGL(k_group_keys, dim3(grid_for(gmax)), dim3(256), 0, s, bcost, perm, gbeg, gcnt, prm, gcost);
     hipLaunchKernelGGL(k_group_order, dim3(kXcd), dim3(kOrderThreads), 0, s, gcost, prm, ckey, order, queue,
                        (uint32_t)(nb * kWavesPerBlock));
+    if (share && n <= coop_max_n(dim)) {
+        // one block per group at a time, as many blocks as can be resident
+        const int deal = coop_deal_level(n, dim);
+#define TC_LAUNCH_COOP(DIM, PL, QU)                                                                                 \
+    hipLaunchKernelGGL((k_walk_force_coop<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies,               \
+                       bodies32, perm, gbeg, gcnt, order, bcost, lvl_off, deal, lpl_log2, G, eps2, prm, acc, pot,  \
+                       m2p, p2p)
+        if (dim == 3 && walkq) {
+            if (plain) TC_LAUNCH_COOP(3, true, true);
+            else TC_LAUNCH_COOP(3, false, true);
+        } else if (dim == 3) {
+            if (plain) TC_LAUNCH_COOP(3, true, false);
+            else TC_LAUNCH_COOP(3, false, false);
+        } else {
+            if (plain) TC_LAUNCH_COOP(2, true, false);
+            else TC_LAUNCH_COOP(2, false, false);
+        }
+#undef TC_LAUNCH_COOP
+        return hipGetLastError();
+    }
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
     hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
                        gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)

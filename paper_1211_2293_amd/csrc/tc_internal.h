@@ -149,7 +149,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* order,
                              uint32_t* queue, uint32_t* bcost, int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, bool plain, hipStream_t s);
+                             int64_t* p2p, bool plain, bool share, const uint32_t* lvl_off, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
                            hipStream_t s);
 // closure.hip
@@ -158,11 +158,29 @@ hipError_t launch_direct64(const Body* bodies, const uint32_t* inv_perm, int64_t
                            double eps2, double G, DevParams* prm, double* acc, double* pot, hipStream_t s);
 // Split walks pay off for small n only (measured on 3D Plummer spheres:
 // 1.6x faster force evaluations at 2,000 bodies, 1.14x at 10,000, 0.64x at
-// 16,384; on 2D disks 1.25x at 16,384, 0.90x at 32,768); for n at most
-// split_max_n(dim) they are used and the workspace holds their partial sums.
+// 16,384; on 2D disks 1.25x at 16,384, 0.90x at 32,768).  The shared walks
+// below are faster still, so split walks are used only when asked for
+// (tc_set_split(ctx, 2)), for n at most split_max_n(dim); the workspace holds
+// their partial sums.
 constexpr int64_t kSplitMaxN3 = 12288;
 constexpr int64_t kSplitMaxN2 = 24576;
 inline int64_t split_max_n(int dim) { return dim == 3 ? kSplitMaxN3 : kSplitMaxN2; }
+// Up to coop_max_n(dim), one block of waves shares each group's walk
+// (k_walk_force_coop), dealing out the cells of level coop_deal_level;
+// beyond, one wave per group.  Measured (force evaluation, one wave / shared):
+// 3D Plummer 0.160 / 0.073 ms at 2,000 bodies, 0.402 / 0.168 at 10,000,
+// 0.473 / 0.278 at 65,536, 0.494 / 0.450 at 131,072, 0.663 / 0.807 at
+// 262,144; 2D disk 0.111 / 0.052 at 5,000, 0.098 / 0.049 at 32,768,
+// 0.118 / 0.103 at 131,072, 0.125 / 0.179 at 262,144.  tc_set_split(ctx, 0)
+// turns it off; tc_set_split(ctx, 2) uses the split walks (above) for
+// n <= split_max_n(dim) instead.
+constexpr int64_t kCoopMaxN3 = 163840;
+constexpr int64_t kCoopMaxN2 = 163840;
+inline int64_t coop_max_n(int dim) { return dim == 3 ? kCoopMaxN3 : kCoopMaxN2; }
+inline int coop_deal_level(int64_t n, int dim) {
+    if (dim == 3) return n < 8192 ? 5 : 6;
+    return n < 8192 ? 5 : n < 65536 ? 6 : 7;
+}
 hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, const Body* bodies,
                                    const float4* bodies32, const uint32_t* perm, const int32_t* gbeg,
                                    const int32_t* gcnt, int64_t gmax, int64_t n, int dim, int leaf_cap, float G,

@@ -445,9 +445,13 @@ class Treecode:
         _check(lib().tc_fmm_get_pairs(self._h, _ptr(m2l), _ptr(p2p)))
         return m2l[:sizes[1]], p2p[:sizes[2]]
 
-    def set_split(self, on: bool):
-        """Split walks for n <= 12288 in 3D, n <= 24576 in 2D (default on)."""
-        _check(lib().tc_set_split(self._h, int(bool(on))))
+    def set_split(self, mode):
+        """How a group's walk is spread over waves: 1 or True (default) a
+        block of 4 waves shares each group's walk for n <= 163840; 2 split
+        walks for n <= 12288 in 3D and n <= 24576 in 2D, else as 1; 0 or
+        False one wave per group at any n."""
+        mode = int(mode)
+        _check(lib().tc_set_split(self._h, mode))
 
     def set_multipole(self, order: int):
         """1: monopole cells (default); 2: add quadrupole terms (3D)."""

@@ -100,6 +100,10 @@ def test_closure_direct_lists_and_modes_check_arguments_first(L):
     assert L.tc_set_accumulation(h, 2) == T.TC_EINVAL
     assert L.tc_set_accumulation(h, T.TC_ACC_PLAIN) == T.TC_OK
     assert L.tc_set_split(None, 1) == T.TC_EINVAL
+    assert L.tc_set_split(h, 3) == T.TC_EINVAL
+    assert L.tc_set_split(h, -1) == T.TC_EINVAL
+    for mode in (0, 2, 1):
+        assert L.tc_set_split(h, mode) == T.TC_OK
     assert L.tc_set_graph(None, 1) == T.TC_EINVAL
     # direct sum
     assert L.tc_direct(h, fake, 0, 1.0, 1e-2, fake, fake) == T.TC_EINVAL

@@ -183,37 +183,45 @@ def test_quadrupole_cells_match_oracle(theta):
     np.testing.assert_array_equal(b1.cpu().numpy(), a1)
 
 
-@pytest.mark.parametrize("case", ["plummer", "disk", "root-leaf", "quadrupole"])
-def test_split_walk_matches_unsplit(case):
-    """For small n each group's walk is cut into tasks over the level-1
-    cells and their children; the interactions and counts must equal the
-    unsplit walk's and the forces agree to summation order."""
+@pytest.mark.parametrize("case", ["plummer", "disk", "root-leaf", "quadrupole", "plummer-mid", "disk-mid",
+                                  "quadrupole-mid"])
+def test_shared_walks_match_one_wave(case):
+    """Walks spread over several waves against one wave per group: split
+    walks (tc_set_split mode 2, small n: one task per level-1 cell and
+    child) and walks shared by a block of waves (mode 1, the default: the
+    cells of one level dealt out); the interactions and counts must equal
+    the one-wave walk's and the forces agree to summation order."""
     from paper_1211_2293_amd import treecode
     from tests.gpu_util import to_dev
-    # split walks are used up to 12,288 bodies in 3D, 24,576 in 2D
+    # split walks exist up to 12,288 bodies in 3D and 24,576 in 2D; shared
+    # walks up to 163,840
     w = {"plummer": lambda: workloads.plummer_sphere(12000, seed=67),
          "disk": lambda: workloads.gaussian_disk(24000, seed=68),
          "root-leaf": lambda: workloads.plummer_sphere(12, seed=69),
-         "quadrupole": lambda: workloads.plummer_sphere(12000, seed=67)}[case]()
+         "quadrupole": lambda: workloads.plummer_sphere(12000, seed=67),
+         "plummer-mid": lambda: workloads.plummer_sphere(100000, seed=82),
+         "disk-mid": lambda: workloads.gaussian_disk(100000, seed=83),
+         "quadrupole-mid": lambda: workloads.plummer_sphere(40000, seed=82)}[case]()
     tc = treecode.Treecode(w.pos.shape[1], leaf_cap=16)
     keep = (to_dev(w.pos), to_dev(w.mass))
     tc.build(*keep)
     tc.moments()
     tc.walk(0.6)
-    if case == "quadrupole":
+    if case.startswith("quadrupole"):
         tc.set_multipole(2)
     out = {}
-    for split in (True, False):
-        tc.set_split(split)
+    for mode in (0, 1, 2):
+        tc.set_split(mode)
         acc, pot = tc.forces(1.0, 1e-2)
         m2p, p2p = (v.cpu().numpy() for v in tc.counts())
-        out[split] = (acc.cpu().numpy(), pot.cpu().numpy(), m2p, p2p)
-    np.testing.assert_array_equal(out[True][2], out[False][2])
-    np.testing.assert_array_equal(out[True][3], out[False][3])
-    ea, ep = oracle.rel_l2(out[True][0], out[False][0]), oracle.rel_l2(out[True][1], out[False][1])
-    print(f"{case}: split vs unsplit acc {ea:.2e} pot {ep:.2e}", flush=True)
-    assert ea < 2e-6 and ep < 2e-6
-    # run-to-run identical
-    tc.set_split(True)
-    again, _ = tc.forces(1.0, 1e-2)
-    np.testing.assert_array_equal(again.cpu().numpy(), out[True][0])
+        out[mode] = (acc.cpu().numpy(), pot.cpu().numpy(), m2p, p2p)
+    for mode in (1, 2):
+        np.testing.assert_array_equal(out[mode][2], out[0][2])
+        np.testing.assert_array_equal(out[mode][3], out[0][3])
+        ea, ep = oracle.rel_l2(out[mode][0], out[0][0]), oracle.rel_l2(out[mode][1], out[0][1])
+        print(f"{case}: mode {mode} vs one wave acc {ea:.2e} pot {ep:.2e}", flush=True)
+        assert ea < 2e-6 and ep < 2e-6
+        # run-to-run identical
+        tc.set_split(mode)
+        again, _ = tc.forces(1.0, 1e-2)
+        np.testing.assert_array_equal(again.cpu().numpy(), out[mode][0])
