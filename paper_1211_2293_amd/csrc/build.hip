@@ -708,15 +708,14 @@ __global__ void __launch_bounds__(256) k_moments_level(const uint32_t* __restric
 
 // Start of each level in level order (levels 0..L, plus the end), from the
 // per-level counts the level sort produced.
-__global__ void k_level_offsets(const uint32_t* __restrict__ digit_tot, int L, uint32_t* __restrict__ lvl_off) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        uint32_t run = 0;
-        for (int l = 0; l <= L; ++l) {
-            lvl_off[l] = run;
-            run += digit_tot[l];
-        }
-        lvl_off[L + 1] = run;
+__device__ __forceinline__ void level_offsets(const uint32_t* __restrict__ digit_tot, int L,
+                                              uint32_t* __restrict__ lvl_off) {
+    uint32_t run = 0;
+    for (int l = 0; l <= L; ++l) {
+        lvl_off[l] = run;
+        run += digit_tot[l];
     }
+    lvl_off[L + 1] = run;
 }
 
 // ----------------------------------------------------------------- mac ----
@@ -776,9 +775,14 @@ __global__ void __launch_bounds__(256) k_level_keys(const Cell* __restrict__ cel
     }
 }
 
+// The inverse of the level order, and (one thread) the start of each level
+// from the per-level counts of the sort.
 __global__ void __launch_bounds__(256) k_level_inverse(const uint32_t* __restrict__ bfs2pre,
                                                        const DevParams* __restrict__ prm, int64_t cmax,
-                                                       uint32_t* __restrict__ pre2bfs) {
+                                                       uint32_t* __restrict__ pre2bfs,
+                                                       const uint32_t* __restrict__ digit_tot, int L,
+                                                       uint32_t* __restrict__ lvl_off) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) level_offsets(digit_tot, L, lvl_off);
     int64_t C = prm->ncells;
     if (C > cmax) C = cmax;
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < C;
@@ -972,9 +976,7 @@ hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const De
         default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
     }
     hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
-                       pre2bfs);
-    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, (const uint32_t*)digit_tot, levels_for(dim),
-                       lvl_off);
+                       pre2bfs, (const uint32_t*)digit_tot, levels_for(dim), lvl_off);
     return hipGetLastError();
 }
 

@@ -225,3 +225,29 @@ def test_shared_walks_match_one_wave(case):
         tc.set_split(mode)
         again, _ = tc.forces(1.0, 1e-2)
         np.testing.assert_array_equal(again.cpu().numpy(), out[mode][0])
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_plain_accumulation_in_shared_walks(dim):
+    """The uncompensated running sums of the precision study, in the walk
+    shared by a block of waves (the default below 163,840 bodies): counts
+    as in the oracle, forces within the parity bound."""
+    from paper_1211_2293_amd import treecode
+    from tests.gpu_util import to_dev
+    w = workloads.plummer_sphere(30000, seed=84) if dim == 3 else workloads.gaussian_disk(30000, seed=85)
+    tc = treecode.Treecode(dim, leaf_cap=16)
+    tc.build(to_dev(w.pos), to_dev(w.mass))
+    tc.moments()
+    tc.walk(0.6)
+    tc.set_accumulation(False)
+    acc, pot = tc.forces(1.0, 1e-2)
+    m2p, p2p = (v.cpu().numpy() for v in tc.counts())
+    gb, gc = (v.cpu().numpy() for v in tc.groups())
+    t = oracle.Tree(w.pos.astype(np.float64), w.mass.astype(np.float64), 16)
+    om, op = t.walk_counts_groups(0.6, gb, gc)
+    np.testing.assert_array_equal(m2p, om)
+    np.testing.assert_array_equal(p2p, op)
+    a, p = t.forces_groups(0.6, gb, gc, G=1.0, eps=1e-2)
+    ea, ep = oracle.rel_l2(acc.cpu().numpy(), a), oracle.rel_l2(pot.cpu().numpy(), p)
+    print(f"dim={dim} plain accumulation: acc {ea:.2e} pot {ep:.2e}", flush=True)
+    assert ea < TOL and ep < TOL
