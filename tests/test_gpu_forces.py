@@ -251,3 +251,11 @@ def test_plain_accumulation_in_shared_walks(dim):
     ea, ep = oracle.rel_l2(acc.cpu().numpy(), a), oracle.rel_l2(pot.cpu().numpy(), p)
     print(f"dim={dim} plain accumulation: acc {ea:.2e} pot {ep:.2e}", flush=True)
     assert ea < TOL and ep < TOL
+
+
+def test_shared_walk_at_its_largest_size():
+    """163,840 bodies, the largest size that shares a group's walk among a
+    block of waves: interaction counts equal to the oracle's and forces
+    within the parity bound."""
+    w = workloads.plummer_sphere(163840, seed=86)
+    _check_against_oracle(w.pos, w.mass, 16, 0.5, w.eps)
