@@ -135,14 +135,15 @@ struct tc_ctx {
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = false;
     bool capturing = false;    // inside the graph capture of the pre-force part
-    // Depth of an earlier tree, for the moments pass: each build copies its
-    // level offsets to pinned host memory behind an event; a later call
-    // reads them once the event has completed.  Only launch counts depend
-    // on it, never results.
+    // Level sizes of an earlier tree, for the moments pass: each build copies
+    // its level offsets to pinned host memory behind an event; a later call
+    // takes them once the event has completed.  Only launch shapes depend
+    // on them, never results.
     uint32_t* lvl_host = nullptr;
     hipEvent_t lvl_ev = nullptr;
     bool lvl_pending = false;
-    int lvl_depth = -1;        // deepest populated level of the last harvested build
+    bool have_hint = false;    // lvl_hint holds the last harvested build's level offsets
+    uint32_t lvl_hint[64] = {};
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
     int split = 1;             // 0: one wave per group; 1: shared walks (coop); 2: split walks up to split_max_n
@@ -218,15 +219,13 @@ hipEvent_t pooled_event(tc_ctx* ctx) {
 }
 
 // Everything tc_build enqueues, after its checks.
-// Take the depth of the last build whose level offsets have arrived on the
+// Take the level offsets of the last build whose copy has arrived on the
 // host (never waits).
 void harvest_depth(tc_ctx* ctx) {
     if (!ctx->lvl_pending || hipEventQuery(ctx->lvl_ev) != hipSuccess) return;
     const int L = levels_for(ctx->dim);
-    int deepest = 0;
-    for (int l = 0; l <= L; ++l)
-        if (ctx->lvl_host[l + 1] > ctx->lvl_host[l]) deepest = l;
-    ctx->lvl_depth = deepest;
+    for (int l = 0; l <= L + 1; ++l) ctx->lvl_hint[l] = ctx->lvl_host[l];
+    ctx->have_hint = true;
     ctx->lvl_pending = false;
 }
 
@@ -284,9 +283,7 @@ int do_moments(tc_ctx* ctx, hipStream_t s) {
                                ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
                                ctx->at<uint32_t>(l.off_lvl_off), ctx->prm(), ctx->at<Moments>(l.off_mom),
                                ctx->at<Moments>(l.off_mom_lvl), ctx->at<uint2>(l.off_kids),
-                               ctx->at<WalkCell>(l.off_walk),
-                               // per-level launches down to two levels below the earlier tree's depth
-                               ctx->lvl_depth < 0 ? -1 : ctx->lvl_depth + 2, s));
+                               ctx->at<WalkCell>(l.off_walk), ctx->have_hint ? ctx->lvl_hint : nullptr, s));
     ctx->state = kMoments;
     return TC_OK;
 }

@@ -673,12 +673,12 @@ __device__ __forceinline__ void moments_of_internal(int64_t b, const uint32_t* _
     walk[b] = w;
 }
 
-// The levels deeper than `top`, deepest first, in one block: every launch
-// costs a few microseconds even when its level is empty, and most of the
-// deepest levels are.  `top` comes from the depth of an earlier tree, so the
-// levels here are usually empty or nearly so; any cells they do hold are
-// still done (in order: a barrier separates the levels, and the block's
-// waves share one CU's L1).
+// Levels `deepest` down to top + 1, deepest first, in one block: a launch
+// costs a few microseconds even when its level is nearly empty, and most of
+// the deepest levels are.  Which levels come here follows from an earlier
+// tree, so they usually hold few cells; any cells they do hold are still
+// done (in order: a barrier separates the levels, and the block's waves
+// share one CU's L1).
 constexpr int kDeepThreads = 1024;
 
 template <int D>
@@ -1000,9 +1000,23 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
                           const DevParams* prm, Moments* mom, Moments* mom_lvl, uint2* kids, WalkCell* walk,
-                          int top, hipStream_t s) {
+                          const uint32_t* hint, hipStream_t s) {
     const int L = levels_for(dim);
-    if (top < 0 || top > L) top = L;
+    // levels L..top+1 go to one single-block launch, top..0 to one launch
+    // each.  (The top levels hold few cells too, but there one launch per
+    // level is the faster: a level's cost is a chain of dependent loads and
+    // stores either way, and the single block adds its barrier waits.)
+    int top = L;
+    int64_t cnt[66] = {};
+    if (hint) {
+        for (int l = 0; l <= L; ++l) cnt[l] = (int64_t)hint[l + 1] - (int64_t)hint[l];
+        top = 0;
+        for (int l = L; l > 0; --l)
+            if (cnt[l] > kDeepThreads) {
+                top = l;
+                break;
+            }
+    }
     const unsigned nl = grid_for(cmax);
     if (dim == 3)
         hipLaunchKernelGGL(k_leaf_moments<3>, dim3(nl), dim3(256), 0, s, cells, bodies, pre2bfs, prm, cmax, mom,
@@ -1018,8 +1032,9 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
             hipLaunchKernelGGL(k_moments_deep<2>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, top, L,
                                (const uint2*)kids, mom, mom_lvl, walk);
     }
-    const unsigned nb = grid_for(cmax, 2048);
     for (int l = top; l >= 0; --l) {
+        // an earlier count plus a quarter: a grid-stride loop covers any more
+        const unsigned nb = hint ? grid_for(cnt[l] + cnt[l] / 4, 2048) : grid_for(cmax, 2048);
         if (dim == 3)
             hipLaunchKernelGGL(k_moments_level<3>, dim3(nb), dim3(256), 0, s, bfs2pre, lvl_off, l, kids, mom, mom_lvl,
                                walk);

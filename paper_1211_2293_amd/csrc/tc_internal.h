@@ -132,8 +132,11 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
 hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_t cmax,
                           const uint32_t* bfs2pre, const uint32_t* pre2bfs, const uint32_t* lvl_off,
                           const DevParams* prm, Moments* mom, Moments* mom_lvl, uint2* kids, WalkCell* walk,
-                          int top, hipStream_t s);
-// Levels above top (deeper) go to one single-block launch; top < 0 = none.
+                          const uint32_t* hint, hipStream_t s);
+// hint (host, nullable): the level offsets (levels 0..L and the end) of an
+// earlier tree.  They shape the launches only: the deepest levels that held
+// few cells go to one single-block launch, the others get grids sized by
+// their earlier counts.  Any tree is still done in full.
 hipError_t launch_mac(const Cell* cells, const Moments* mom, int dim, double theta, int64_t cmax,
                       const uint32_t* pre2bfs, WalkCell* walk, double* rc_out, const DevParams* prm,
                       hipStream_t s);
