@@ -397,6 +397,98 @@ __global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__
     }
 }
 
+// Short arrays in one block of 1024 threads, one launch instead of three.
+// A segment is kScanSmallRows rows of 4096 values; thread t loads values
+// 4t..4t+3 of each row with one 16-byte load, and the rows of a segment are
+// scanned together between one pair of barriers, with a running carry from
+// segment to segment.  in and out must be 16-byte aligned.
+constexpr int kScanSmallRows = 4;
+constexpr int64_t kScanSmallSeg = kScanSmallRows * 4096;
+constexpr int64_t kScanSmallMax = 8 * kScanSmallSeg;   // longest array sent here
+
+__global__ void __launch_bounds__(1024) k_scan_small(const uint32_t* __restrict__ in, int64_t n,
+                                                     const uint32_t* __restrict__ n_live,
+                                                     uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_w[kScanSmallRows][16];
+    const int64_t m = live_count(n, n_live);
+    const int t = threadIdx.x, lane = wave_lane(), w = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < m; c += kScanSmallSeg) {
+        uint4 q[kScanSmallRows];
+        uint32_t x[kScanSmallRows], sum[kScanSmallRows];
+#pragma unroll
+        for (int r = 0; r < kScanSmallRows; ++r) {
+            const int64_t i = c + r * 4096 + 4 * t;
+            if (i + 3 < m) {
+                q[r] = *reinterpret_cast<const uint4*>(in + i);
+            } else {
+                q[r].x = i < m ? in[i] : 0u;
+                q[r].y = i + 1 < m ? in[i + 1] : 0u;
+                q[r].z = i + 2 < m ? in[i + 2] : 0u;
+                q[r].w = 0u;
+            }
+            sum[r] = q[r].x + q[r].y + q[r].z + q[r].w;
+            x[r] = sum[r];
+        }
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+#pragma unroll
+            for (int r = 0; r < kScanSmallRows; ++r) {
+                const uint32_t y = __shfl_up(x[r], o, kWave);
+                if (lane >= o) x[r] += y;
+            }
+        }
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int r = 0; r < kScanSmallRows; ++r) s_w[r][w] = x[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kScanSmallRows; ++r) {
+            uint32_t pre = 0, tot = 0;
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = s_w[r][k];
+                if (k < w) pre += v;
+                tot += v;
+            }
+            const int64_t i = c + r * 4096 + 4 * t;
+            uint4 e;
+            e.x = carry + pre + x[r] - sum[r];
+            e.y = e.x + q[r].x;
+            e.z = e.y + q[r].y;
+            e.w = e.z + q[r].z;
+            if (i + 3 < m) {
+                *reinterpret_cast<uint4*>(out + i) = e;
+            } else {
+                if (i < m) out[i] = e.x;
+                if (i + 1 < m) out[i + 1] = e.y;
+                if (i + 2 < m) out[i + 2] = e.z;
+            }
+            carry += tot;
+        }
+        __syncthreads();    // s_w is rewritten by the next segment
+    }
+    if (t == 0) {
+        out[n] = carry;
+        out[m] = carry;
+    }
+}
+
+// Exclusive scan of n values (the first min(n, *n_live) with n_live) into
+// out, with out[n] and out[live] the total; part holds `tiles` partial sums.
+static void scan_u32(const uint32_t* in, int64_t n, const uint32_t* n_live, uint32_t* out, uint32_t* part,
+                     int64_t tiles, hipStream_t s) {
+    if (n <= kScanSmallMax && (reinterpret_cast<uintptr_t>(in) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, n, n_live, out);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live, part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n, n_live);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live, (const uint32_t*)part,
+                       out);
+}
+
 // ------------------------------------------------------------ topology ----
 
 // Number of leading Morton digits two keys share (L if equal).
@@ -939,10 +1031,7 @@ hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm
 
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)nullptr, part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n, (const uint32_t*)nullptr);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(256), 0, s, in, n, (const uint32_t*)nullptr,
-                       (const uint32_t*)part, out);
+    scan_u32(in, n, nullptr, out, part, tiles, s);
     return hipGetLastError();
 }
 
@@ -953,12 +1042,7 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     const unsigned nb = grid_for(n);
     if (dim == 3) hipLaunchKernelGGL(k_topo_count<3>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
     else hipLaunchKernelGGL(k_topo_count<2>, dim3(nb), dim3(256), 0, s, keys, n, leaf_cap, range, nper);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n,
-                       (const uint32_t*)nullptr, scan_part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, cstart, n, (const uint32_t*)nullptr);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)nper, n,
-                       (const uint32_t*)nullptr,
-                       (const uint32_t*)scan_part, cstart);
+    scan_u32(nper, n, nullptr, cstart, scan_part, scan_tiles, s);
     if (dim == 3) hipLaunchKernelGGL(k_topo_emit<3>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
     else hipLaunchKernelGGL(k_topo_emit<2>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
     hipLaunchKernelGGL(k_topo_link, dim3(grid_for(cmax)), dim3(256), 0, s, cells, (const DevParams*)prm, cmax);
@@ -987,11 +1071,7 @@ hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32
     hipLaunchKernelGGL(k_group_count, dim3(nb), dim3(256), 0, s, cells, (const DevParams*)prm, cmax, gper);
     // over the live cells only (their count is on the device)
     const uint32_t* live = &prm->ncells;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax, live,
-                       scan_part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, scan_part, scan_tiles, goff, cmax, live);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_tiles), dim3(256), 0, s, (const uint32_t*)gper, cmax, live,
-                       (const uint32_t*)scan_part, goff);
+    scan_u32(gper, cmax, live, goff, scan_part, scan_tiles, s);
     hipLaunchKernelGGL(k_group_emit, dim3(nb), dim3(256), 0, s, cells, (const uint32_t*)goff, prm, cmax, gbeg,
                        gcnt, gmax);
     return hipGetLastError();
