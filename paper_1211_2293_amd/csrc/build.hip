@@ -248,12 +248,18 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, 
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-template <int PER>
+// SCAN: hist holds the raw per-tile counts (no k_sort_scan before it), and
+// each block sums its digit's row itself: the earlier tiles' counts and the
+// total, which block 0 also stores in digit_tot.  For a few tiles (at most
+// kSortScanInScatter) this costs less than the scan's own launch.
+constexpr int64_t kSortScanInScatter = 128;
+
+template <int PER, bool SCAN = false>
 __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       int64_t n, const uint32_t* __restrict__ n_live, int shift,
                                                       const uint32_t* __restrict__ hist,
-                                                      const uint32_t* __restrict__ digit_tot, int64_t tiles) {
+                                                      uint32_t* __restrict__ digit_tot, int64_t tiles) {
     if (n_live && (int64_t)*n_live < n) n = *n_live;
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wcnt[4][256];
@@ -261,8 +267,21 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
     __shared__ uint32_t s_tot;
     const int t = threadIdx.x, w = t >> 6, lane = wave_lane();
     const int64_t tile = blockIdx.x;
-    const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
-    s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
+    if (SCAN) {
+        const uint32_t* row = hist + (int64_t)t * tiles;
+        uint32_t pre = 0, tot = 0;
+#pragma unroll 8
+        for (int64_t k = 0; k < tiles; ++k) {
+            const uint32_t v = row[k];
+            tot += v;
+            if (k < tile) pre += v;
+        }
+        if (tile == 0) digit_tot[t] = tot;
+        s_base[t] = block_exscan_u32(tot, s_w, &s_tot) + pre;
+    } else {
+        const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
+        s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
+    }
     for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
     uint64_t kr[PER];
     uint32_t vr[PER];
@@ -999,9 +1018,14 @@ static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uin
         uint32_t* vout = even ? idx_b : idx_a;
         hipLaunchKernelGGL(k_sort_hist<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, n_live, shift, hist,
                            tiles);
+        if (tiles <= kSortScanInScatter) {
+            hipLaunchKernelGGL((k_sort_scatter<PER, true>), dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout,
+                               vout, n, n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
+            continue;
+        }
         hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
-        hipLaunchKernelGGL(k_sort_scatter<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout, n,
-                           n_live, shift, (const uint32_t*)hist, (const uint32_t*)digit_tot, tiles);
+        hipLaunchKernelGGL((k_sort_scatter<PER, false>), dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout,
+                           n, n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
     }
 }
 
