@@ -43,6 +43,15 @@ CASES = {
                                  np.ones(17, np.float32), 16),
     "leafcap-256": lambda: (np.random.default_rng(49).uniform(0, 1, (3000, 3)).astype(np.float32),
                             np.ones(3000, np.float32), 256),
+    # 131,072 keys: the last size whose radix passes scan their digits inside
+    # the scatter (128 tiles) and whose body-count scan is one block; one
+    # more body takes the separate scan launches for both
+    "plummer-131072": lambda: (workloads.plummer_sphere(131072, seed=50).pos,
+                               workloads.plummer_sphere(131072, seed=50).mass, 16),
+    "plummer-131073": lambda: (workloads.plummer_sphere(131073, seed=50).pos,
+                               workloads.plummer_sphere(131073, seed=50).mass, 16),
+    "disk2d-131073": lambda: (workloads.gaussian_disk(131073, seed=51).pos,
+                              workloads.gaussian_disk(131073, seed=51).mass, 16),
 }
 
 
