@@ -761,15 +761,10 @@ __global__ void __launch_bounds__(256) k_leaf_moments(const Cell* __restrict__ c
     }
 }
 
-// One internal cell of the level passes.
-template <int D>
-__device__ __forceinline__ void moments_of_internal(int64_t b, const uint32_t* __restrict__ bfs2pre,
-                                                    const uint2* __restrict__ kids, Moments* mom, Moments* mom_lvl,
-                                                    WalkCell* __restrict__ walk) {
-    const uint2 kc = kids[b];
-    if (kc.y == kLeafKids) return;
-    Moments mo;
-    internal_moments<D>(mom_lvl + kc.x, (int)kc.y, mo);
+// The outputs of internal cell b (level order) with children kc.
+__device__ __forceinline__ void store_internal(int64_t b, uint2 kc, const Moments& mo,
+                                               const uint32_t* __restrict__ bfs2pre, Moments* mom,
+                                               Moments* mom_lvl, WalkCell* __restrict__ walk) {
     mom_lvl[b] = mo;
     mom[bfs2pre[b]] = mo;
     WalkCell w;
@@ -782,6 +777,18 @@ __device__ __forceinline__ void moments_of_internal(int64_t b, const uint32_t* _
     w.b = (int32_t)kc.y;
     w.pad = 0;
     walk[b] = w;
+}
+
+// One internal cell of the level passes.
+template <int D>
+__device__ __forceinline__ void moments_of_internal(int64_t b, const uint32_t* __restrict__ bfs2pre,
+                                                    const uint2* __restrict__ kids, Moments* mom, Moments* mom_lvl,
+                                                    WalkCell* __restrict__ walk) {
+    const uint2 kc = kids[b];
+    if (kc.y == kLeafKids) return;
+    Moments mo;
+    internal_moments<D>(mom_lvl + kc.x, (int)kc.y, mo);
+    store_internal(b, kc, mo, bfs2pre, mom, mom_lvl, walk);
 }
 
 // Levels `deepest` down to top + 1, deepest first, in one block: a launch
@@ -815,6 +822,40 @@ __global__ void __launch_bounds__(256) k_moments_level(const uint32_t* __restric
     for (int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < b1;
          b += (int64_t)gridDim.x * blockDim.x)
         moments_of_internal<D>(b, bfs2pre, kids, mom, mom_lvl, walk);
+}
+
+// Levels `head` down to 0 in one block, their moments kept in LDS: these
+// levels occupy level-order indices 0 .. lvl_off[head + 1] - 1, so a cell's
+// LDS slot is its level-order index, and each level reads its children from
+// LDS instead of going round through memory (the head level's children
+// come from the level below, done by an earlier launch).  Which levels come
+// here follows from an earlier tree; if the current one holds more than
+// kHeadCells cells in them, the block reads the children from memory
+// instead, as the per-level passes do.
+constexpr int kHeadCells = 512;
+
+template <int D>
+__global__ void __launch_bounds__(kDeepThreads) k_moments_head(const uint32_t* __restrict__ bfs2pre,
+                                                               const uint32_t* __restrict__ lvl_off, int head,
+                                                               const uint2* __restrict__ kids, Moments* mom,
+                                                               Moments* mom_lvl, WalkCell* __restrict__ walk) {
+    __shared__ Moments s_m[kHeadCells];
+    const bool fit = lvl_off[head + 1] <= (uint32_t)kHeadCells;
+    for (int l = head; l >= 0; --l) {
+        const int64_t b0 = lvl_off[l], b1 = lvl_off[l + 1];
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += kDeepThreads) {
+            const uint2 kc = kids[b];
+            if (kc.y == kLeafKids) {
+                if (fit) s_m[b] = mom_lvl[b];
+                continue;
+            }
+            Moments mo;
+            internal_moments<D>((fit && l < head ? s_m : mom_lvl) + kc.x, (int)kc.y, mo);
+            if (fit) s_m[b] = mo;
+            store_internal(b, kc, mo, bfs2pre, mom, mom_lvl, walk);
+        }
+        __syncthreads();
+    }
 }
 
 // Start of each level in level order (levels 0..L, plus the end), from the
@@ -1121,6 +1162,11 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
                 break;
             }
     }
+    // levels head..0 (at most kHeadCells cells together, and at most down
+    // from top) go to one single-block launch with their moments in LDS
+    int head = -1;
+    if (hint)
+        while (head + 1 <= top && (int64_t)hint[head + 2] <= kHeadCells) ++head;
     const unsigned nl = grid_for(cmax);
     if (dim == 3)
         hipLaunchKernelGGL(k_leaf_moments<3>, dim3(nl), dim3(256), 0, s, cells, bodies, pre2bfs, prm, cmax, mom,
@@ -1136,7 +1182,7 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
             hipLaunchKernelGGL(k_moments_deep<2>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, top, L,
                                (const uint2*)kids, mom, mom_lvl, walk);
     }
-    for (int l = top; l >= 0; --l) {
+    for (int l = top; l > head; --l) {
         // an earlier count plus a quarter: a grid-stride loop covers any more
         const unsigned nb = hint ? grid_for(cnt[l] + cnt[l] / 4, 2048) : grid_for(cmax, 2048);
         if (dim == 3)
@@ -1145,6 +1191,14 @@ hipError_t launch_moments(const Cell* cells, const Body* bodies, int dim, int64_
         else
             hipLaunchKernelGGL(k_moments_level<2>, dim3(nb), dim3(256), 0, s, bfs2pre, lvl_off, l, kids, mom, mom_lvl,
                                walk);
+    }
+    if (head >= 0) {
+        if (dim == 3)
+            hipLaunchKernelGGL(k_moments_head<3>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, head,
+                               (const uint2*)kids, mom, mom_lvl, walk);
+        else
+            hipLaunchKernelGGL(k_moments_head<2>, dim3(1), dim3(kDeepThreads), 0, s, bfs2pre, lvl_off, head,
+                               (const uint2*)kids, mom, mom_lvl, walk);
     }
     return hipGetLastError();
 }
