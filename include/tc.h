@@ -229,6 +229,14 @@ int tc_set_graph(tc_ctx *ctx, int on);
  * build dtype; out is HOST memory.  Synchronises.  Requires tc_forces. */
 int tc_diag(tc_ctx *ctx, const void *vel, double out[8]);
 
+/* The same diagnostics (same kernels, same values), enqueued on the
+ * context's stream without a copy to the host or a wait: out is a DEVICE
+ * array of 8 doubles owned by the caller (8-byte aligned), written when the
+ * stream reaches the call.  For loops that keep a record per step and read
+ * it later.  TC_EINVAL for a NULL or misaligned pointer; requires
+ * tc_forces. */
+int tc_diag_async(tc_ctx *ctx, const void *vel, double *out);
+
 /* Synchronise the stream and return TC_OK, the sticky TC_ENONFINITE raised
  * by a build, or TC_EHIP if an earlier call recorded a HIP failure. */
 int tc_status(tc_ctx *ctx);

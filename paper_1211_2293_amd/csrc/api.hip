@@ -822,6 +822,16 @@ int tc_diag(tc_ctx* ctx, const void* vel, double out[8]) {
     return TC_OK;
 }
 
+int tc_diag_async(tc_ctx* ctx, const void* vel, double* out) {
+    if (!ctx || !vel || !out) return TC_EINVAL;
+    if (!aligned(vel, ctx->dtype == TC_F64 ? 8 : 4) || !aligned(out, 8)) return TC_EINVAL;
+    if (ctx->state < kForced) return TC_ESTATE;
+    const Layout& l = ctx->lay;
+    TC_HIP(ctx, launch_diag(ctx->mass, vel, ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), ctx->n,
+                            ctx->dim, ctx->dtype == TC_F64, ctx->at<double>(l.off_diag_part), out, ctx->stream));
+    return TC_OK;
+}
+
 int tc_status(tc_ctx* ctx) {
     if (!ctx) return TC_EINVAL;
     TC_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -54,6 +54,7 @@ def lib():
         "tc_forces": (i32, [P, dbl, dbl, P, P]),
         "tc_leapfrog": (i32, [P, dbl, P, P]),
         "tc_diag": (i32, [P, P, P]),
+        "tc_diag_async": (i32, [P, P, P]),
         "tc_status": (i32, [P]),
         "tc_strerror": (C.c_char_p, [i32]),
         "tc_num_cells": (i32, [P, C.POINTER(C.c_int64)]),
@@ -211,6 +212,14 @@ class Treecode:
         out = np.zeros(8)
         _check(lib().tc_diag(self._h, _ptr(vel), out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def diag_async(self, vel: torch.Tensor, out: torch.Tensor) -> None:
+        """Enqueue the diagnostics into `out` (8 float64 on the device), no wait."""
+        self._dev(vel, "vel")
+        self._dev(out, "out")
+        if out.dtype != torch.float64 or out.numel() != 8 or not out.is_contiguous():
+            raise TypeError("out must be 8 contiguous float64 values on the device")
+        _check(lib().tc_diag_async(self._h, _ptr(vel), _ptr(out)))
 
     def status(self) -> int:
         return int(lib().tc_status(self._h))

@@ -54,6 +54,9 @@ def test_call_order_and_arguments(L):
     assert L.tc_leapfrog(h, 1e-3, fake, fake) == T.TC_ESTATE
     out = (C.c_double * 8)()
     assert L.tc_diag(h, fake, out) == T.TC_ESTATE
+    assert L.tc_diag_async(h, fake, fake) == T.TC_ESTATE
+    assert L.tc_diag_async(h, fake, None) == T.TC_EINVAL
+    assert L.tc_diag_async(h, fake, C.c_void_p((1 << 40) + 4)) == T.TC_EINVAL    # out not 8-byte aligned
     n = C.c_int64()
     assert L.tc_num_cells(h, C.byref(n)) == T.TC_ESTATE
     # argument checks come first

@@ -44,6 +44,12 @@ def test_uniform_cube_one_force_and_one_step():
     # diagnostics of the new state: FP64 reductions of the GPU's own values
     # are exact to rounding; against the oracle's forces within 1e-5
     d = tc.diag(vel)
+    # the enqueued form runs the same kernels on the same values
+    d_dev = torch.full((8,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    tc.diag_async(vel, d_dev)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d_dev.cpu().numpy(), d)
     acc1 = torch.empty((4096, 3), dtype=torch.float32, device="cuda")
     pot1 = torch.empty(4096, dtype=torch.float32, device="cuda")
     # re-run the force call to fetch the kept results (same tree, same theta)
