@@ -85,10 +85,10 @@ def test_nonfinite_is_sticky_until_next_build():
 
 @pytest.mark.parametrize("dim", [3, 2])
 def test_context_reuse_with_a_deeper_tree(dim):
-    """A context sizes its per-level moments launches by the depth of an
-    earlier tree; deeper levels go to one single-block pass.  A shallow tree
-    first, then a much deeper one (two tight clumps), then the shallow one
-    again: every tree is still bit-exact."""
+    """A context shapes its moments launches by the level sizes of an
+    earlier tree; the deepest small levels go to one single-block pass.  A
+    shallow tree first, then a much deeper one (two tight clumps), then the
+    shallow one again: every tree is still bit-exact."""
     import torch
 
     from paper_1211_2293_amd import treecode
@@ -104,4 +104,31 @@ def test_context_reuse_with_a_deeper_tree(dim):
         assert g["status"] == treecode.TC_OK
         t = oracle.Tree(pos.astype(np.float64), mass.astype(np.float64), 8)
         print(f"dim={dim} n={len(pos)} depth {int(g['cells']['level'].max())}", flush=True)
+        assert_tree_equal(g, t)
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_context_reuse_when_the_top_levels_no_longer_fit_in_lds(dim):
+    """Two tight clumps far apart have a long chain of one or two cells per
+    level at the top (levels 0..14 in 3D hold under 512 cells), so the next
+    moments pass keeps those levels in LDS; a centrally concentrated tree
+    built next holds over 17,000 cells there, and the pass must read the
+    children from memory instead.  Then the clumps again.  All bit-exact."""
+    import torch
+
+    from paper_1211_2293_amd import treecode
+    rng = np.random.default_rng(52)
+    a = rng.normal(0.0, 1e-4, (50000, dim))
+    b = rng.normal(1.0, 1e-4, (50000, dim))
+    clumps = np.concatenate([a, b]).astype(np.float32)
+    w = workloads.plummer_sphere(100000, seed=53) if dim == 3 else workloads.gaussian_disk(100000, seed=53)
+    spread = np.asarray(w.pos, np.float32)
+    tc = treecode.Treecode(dim, leaf_cap=16)
+    for name, pos in (("clumps", clumps), ("spread", spread), ("clumps", clumps)):
+        mass = np.ones(len(pos), np.float32)
+        print(f"dim={dim} {name} n={len(pos)}", flush=True)
+        g = gpu_tree(pos, mass, 16, tc=tc)
+        torch.cuda.synchronize()
+        assert g["status"] == treecode.TC_OK
+        t = oracle.Tree(pos.astype(np.float64), mass.astype(np.float64), 16)
         assert_tree_equal(g, t)
