@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
 
 // Small and mid-size problems: with fewer groups than resident waves, every
 // wave walks its group alone on its SIMD and the walk's latency sets the
-// time.  Here a block of kCoopParts waves takes one group at a time
+// time.  Here a block of NW waves takes one group at a time
 // (positions of the cost order of k_group_order, strided by the grid):
 // each wave walks its part of the tree (walk_group with NP parts, the cells
 // of level `deal` dealt out) and sums its own list, and the parts' FP32 sums
@@ -303,22 +303,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
 // group, so a shallow deal level leaves one part with most of the work
 // (3D Plummer, 65,536 bodies: 1.15x over one wave dealing level 3, 1.7x
 // dealing level 5 or 6); one too deep leaves the parts repeating the walk
-// above it.  coop_deal_level holds the measured choice.
-constexpr int kCoopParts = kWavesPerBlock;
-
-template <int D, bool PLAIN, bool QUAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force_coop(
+// above it.  coop_deal_level holds the measured choice, coop_waves the
+// number of waves (NW) per group.
+template <int D, bool PLAIN, bool QUAD, int NW>
+__global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force_coop(
     const WalkCell* __restrict__ walk, const float4* __restrict__ walkq, const Body* __restrict__ bodies,
     const float4* __restrict__ bodies32, const uint32_t* __restrict__ perm, const int32_t* __restrict__ gbeg,
     const int32_t* __restrict__ gcnt, const uint32_t* __restrict__ order, uint32_t* __restrict__ bcost,
     const uint32_t* __restrict__ lvl_off, int deal, int lpl_log2, float G, float eps2,
     const DevParams* __restrict__ prm,
     float* __restrict__ acc, float* __restrict__ pot, int64_t* __restrict__ m2p_out, int64_t* __restrict__ p2p_out) {
-    __shared__ float4 s_list[kWavesPerBlock][kListCap];
-    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
-    __shared__ float4 s_qlist[kWavesPerBlock][QUAD ? 3 * kQuadCap : 1];
-    __shared__ double s_part[kCoopParts - 1][4][kWave];
-    __shared__ int64_t s_cnt[kCoopParts - 1][2];
+    constexpr int kCoopParts = NW;
+    __shared__ float4 s_list[NW][kListCap];
+    __shared__ uint32_t s_stack[NW][kStackCap];
+    __shared__ float4 s_qlist[NW][QUAD ? 3 * kQuadCap : 1];
+    __shared__ double s_part[NW - 1][4][kWave];
+    __shared__ int64_t s_cnt[NW - 1][2];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     const uint32_t deal_lo = lvl_off[deal], deal_hi = lvl_off[deal + 1];   // the cells dealt out
     // blocks take the positions of order in strides of the grid
@@ -697,13 +697,19 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     if (share && n <= coop_max_n(dim)) {
         // one block per group at a time, as many blocks as can be resident
         const int deal = coop_deal_level(n, dim);
-#define TC_LAUNCH_COOP(DIM, PL, QU)                                                                                 \
-    hipLaunchKernelGGL((k_walk_force_coop<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies,               \
+        const int nw = coop_waves(n, dim);
+#define TC_LAUNCH_COOP_NW(DIM, PL, QU, NW)                                                                          \
+    hipLaunchKernelGGL((k_walk_force_coop<DIM, PL, QU, NW>), dim3(nb), dim3(NW * kWave), 0, s, walk, walkq, bodies,  \
                        bodies32, perm, gbeg, gcnt, order, bcost, lvl_off, deal, lpl_log2, G, eps2, prm, acc, pot,  \
                        m2p, p2p)
-        if (dim == 3 && walkq) {
-            if (plain) TC_LAUNCH_COOP(3, true, true);
-            else TC_LAUNCH_COOP(3, false, true);
+#define TC_LAUNCH_COOP(DIM, PL, QU)                                                                                 \
+    do {                                                                                                            \
+        if (nw == 8) TC_LAUNCH_COOP_NW(DIM, PL, QU, 8);                                                             \
+        else TC_LAUNCH_COOP_NW(DIM, PL, QU, 4);                                                                     \
+    } while (0)
+        if (dim == 3 && walkq) {    // quadrupole lists: four waves (eight would take 82 KB of LDS)
+            if (plain) TC_LAUNCH_COOP_NW(3, true, true, 4);
+            else TC_LAUNCH_COOP_NW(3, false, true, 4);
         } else if (dim == 3) {
             if (plain) TC_LAUNCH_COOP(3, true, false);
             else TC_LAUNCH_COOP(3, false, false);
@@ -712,6 +718,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
             else TC_LAUNCH_COOP(2, false, false);
         }
 #undef TC_LAUNCH_COOP
+#undef TC_LAUNCH_COOP_NW
         return hipGetLastError();
     }
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
