@@ -183,8 +183,8 @@ def test_quadrupole_cells_match_oracle(theta):
     np.testing.assert_array_equal(b1.cpu().numpy(), a1)
 
 
-@pytest.mark.parametrize("case", ["plummer", "disk", "root-leaf", "quadrupole", "plummer-mid", "disk-mid",
-                                  "quadrupole-mid"])
+@pytest.mark.parametrize("case", ["plummer", "disk", "disk-small", "root-leaf", "quadrupole", "plummer-mid",
+                                  "disk-mid", "quadrupole-mid"])
 def test_shared_walks_match_one_wave(case):
     """Walks spread over several waves against one wave per group: split
     walks (tc_set_split mode 2, small n: one task per level-1 cell and
@@ -194,9 +194,11 @@ def test_shared_walks_match_one_wave(case):
     from paper_1211_2293_amd import treecode
     from tests.gpu_util import to_dev
     # split walks exist up to 12,288 bodies in 3D and 24,576 in 2D; shared
-    # walks up to 163,840
+    # walks up to 163,840, by eight waves per group up to 20,000 bodies
+    # (without quadrupole lists) and by four above
     w = {"plummer": lambda: workloads.plummer_sphere(12000, seed=67),
          "disk": lambda: workloads.gaussian_disk(24000, seed=68),
+         "disk-small": lambda: workloads.gaussian_disk(16000, seed=84),
          "root-leaf": lambda: workloads.plummer_sphere(12, seed=69),
          "quadrupole": lambda: workloads.plummer_sphere(12000, seed=67),
          "plummer-mid": lambda: workloads.plummer_sphere(100000, seed=82),
