@@ -180,13 +180,15 @@ inline int64_t split_max_n(int dim) { return dim == 3 ? kSplitMaxN3 : kSplitMaxN
 constexpr int64_t kCoopMaxN3 = 163840;
 constexpr int64_t kCoopMaxN2 = 163840;
 inline int64_t coop_max_n(int dim) { return dim == 3 ? kCoopMaxN3 : kCoopMaxN2; }
-// Waves sharing each group's walk: eight for the smallest systems, where
+// Waves sharing each group's walk: eight for the smaller systems, where
 // even a block per group leaves most of the GPU idle, else four.  Measured
 // (force kernel, four / eight waves): 3D Plummer 0.175 / 0.123 ms at 10,000
-// bodies, 0.238 / 0.258 at 50,000, 0.536 / 0.690 at 163,840; 2D disk
-// 0.063 / 0.063 at 50,000, 0.121 / 0.159 at 163,840.  Walks with quadrupole
-// lists always use four (eight would need 82 KB of LDS).
-inline int coop_waves(int64_t n, int dim) { return n <= 20000 ? 8 : 4; }
+// bodies, 0.196 / 0.147 at 20,000, 0.213 / 0.183 at 30,000, 0.238 / 0.258
+// at 50,000, 0.536 / 0.690 at 163,840; 2D disk 0.046 / 0.038 at 20,000,
+// 0.048 / 0.044 at 30,000, 0.063 / 0.063 at 50,000, 0.121 / 0.159 at
+// 163,840.  Walks with quadrupole lists always use four (eight would need
+// 82 KB of LDS).
+inline int coop_waves(int64_t n, int dim) { return n <= 36000 ? 8 : 4; }
 inline int coop_deal_level(int64_t n, int dim) {
     if (dim == 3) return n < 8192 ? 5 : 6;
     return n < 8192 ? 5 : n < 65536 ? 6 : 7;

@@ -194,7 +194,7 @@ def test_shared_walks_match_one_wave(case):
     from paper_1211_2293_amd import treecode
     from tests.gpu_util import to_dev
     # split walks exist up to 12,288 bodies in 3D and 24,576 in 2D; shared
-    # walks up to 163,840, by eight waves per group up to 20,000 bodies
+    # walks up to 163,840, by eight waves per group up to 36,000 bodies
     # (without quadrupole lists) and by four above
     w = {"plummer": lambda: workloads.plummer_sphere(12000, seed=67),
          "disk": lambda: workloads.gaussian_disk(24000, seed=68),
