@@ -55,7 +55,7 @@ def log(*a):
 
 
 def make_workload(name: str, n: int | None):
-    from paper_1211_2293_amd import workloads
+    import workloads
     gen = workloads.BY_NAME[name]
     return gen() if n is None else gen(n)
 
@@ -187,7 +187,8 @@ def learned_study(w, args):
     build.  Errors are against the FP64 direct sum on the seeded sample."""
     import torch
 
-    from paper_1211_2293_amd import closure, treecode, workloads
+    import workloads
+    from paper_1211_2293_amd import closure, treecode
     dev = torch.device("cuda:0")
     pos = torch.from_numpy(w.pos).to(dev)
     mass = torch.from_numpy(w.mass).to(dev)
@@ -313,8 +314,9 @@ def learned_study(w, args):
     torch.cuda.synchronize()
     t_res = time.perf_counter() - t0
     t0 = time.perf_counter()
-    stats = closure.train(tc, f_tr, y_tr, epochs=args.epochs, batch=4096, lr=args.lr, lr_final=args.lr / 100,
-                          val=(f_va, y_va), log=log)
+    p0, order = workloads.training_draws(f_tr.shape[0], args.epochs, 4096)
+    stats = closure.train(tc, f_tr, y_tr, p0, order, epochs=args.epochs, batch=4096, lr=args.lr,
+                          lr_final=args.lr / 100, val=(f_va, y_va), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     stats.update({"residual_seconds": t_res, "train_seconds": t_train, "theta": 0.9,
@@ -396,7 +398,8 @@ def main():
 
     import torch
 
-    from paper_1211_2293_amd import treecode, workloads
+    import workloads
+    from paper_1211_2293_amd import treecode
 
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda:0")

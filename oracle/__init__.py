@@ -2,7 +2,9 @@
 
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
-(``paper_1211_2293_amd``) and never imports it.
+(``paper_1211_2293_amd``) and never imports it; the only module it shares with
+that side is the seeded input generator ``workloads`` (random draws only: the
+network's initial parameters come from there).
 
 Contents
 --------

@@ -13,8 +13,10 @@
 //            one below the deepest level at which a run of leaf_cap+1
 //            consecutive keys around i still shares a prefix; their
 //            exclusive scan is the depth-first pre-order index
-//   moments  FP64, leaves over bodies in order, parents over children in
-//            digit order, driven bottom-up by arrival counters
+//   moments  FP64, leaves over bodies in order (one launch), then internal
+//            cells level by level from the deepest up, each over its
+//            children in digit order read from level-order copies (the top
+//            and the deepest levels each in one single-block launch)
 //   mac      opening radius per cell for the current theta
 //
 // Every expression that decides an integer (keys, topology, opening radii)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from oracle import mlp
-from paper_1211_2293_amd import workloads
+import workloads
 from tests.gpu_util import assert_tree_equal, gpu_tree, to_dev
 
 pytestmark = pytest.mark.gpu

@@ -8,7 +8,8 @@ import pytest
 import torch
 
 import oracle
-from paper_1211_2293_amd import treecode, workloads
+import workloads
+from paper_1211_2293_amd import treecode
 
 pytestmark = pytest.mark.gpu
 

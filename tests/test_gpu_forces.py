@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1211_2293_amd import workloads
+import workloads
 from tests.gpu_util import gpu_tree
 
 pytestmark = pytest.mark.gpu

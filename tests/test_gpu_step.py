@@ -5,7 +5,8 @@ import pytest
 import torch
 
 import oracle
-from paper_1211_2293_amd import treecode, workloads
+import workloads
+from paper_1211_2293_amd import treecode
 from tests.gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu

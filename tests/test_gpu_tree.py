@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1211_2293_amd import workloads
+import workloads
 from tests.gpu_util import assert_tree_equal, gpu_tree
 
 pytestmark = pytest.mark.gpu

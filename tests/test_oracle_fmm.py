@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1211_2293_amd import workloads
+import workloads
 
 
 def test_m2l_two_body_quadrupole_closed_form():

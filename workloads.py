@@ -189,6 +189,14 @@ def batch_order(npairs, steps, batch, seed=0):
     return np.concatenate([rng.permutation(npairs) for _ in range(reps)]).astype(np.int32)
 
 
+def training_draws(npairs, epochs=40, batch=4096, init_seed=0, order_seed=0):
+    """The random draws of one training run: the initial parameters
+    (mlp_params(init_seed)) and a minibatch order long enough for
+    max(1, epochs * npairs // batch) steps of `batch` samples."""
+    steps = max(1, epochs * int(npairs) // batch)
+    return mlp_params(init_seed), batch_order(npairs, steps, batch, order_seed)
+
+
 BY_NAME = {
     "uniform-cube": uniform_cube,
     "gaussian-disk-2d": gaussian_disk,
