@@ -7,7 +7,10 @@ trained by mean squared error with Adam).  The paper's treecode stops at the
 monopole (§3.1); the closure is this project's extension of it.
 
 Network:  z1 = f W1 + b1, h1 = gelu(z1), z2 = h1 W2 + b2, h2 = gelu(z2),
-          y = h2 W3 + b3,  gelu(z) = z (1 + erf(z / sqrt 2)) / 2.
+          y = h2 W3 + b3,
+          gelu(z) = z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))) / 2,
+the tanh form of the Gaussian error linear unit (Hendrycks and Gimpel,
+2016), within 5e-4 of z Phi(z) everywhere.
 Parameters, canonical flat order (5059 values): W1 [10][64], b1 [64],
 W2 [64][64], b2 [64], W3 [64][3], b3 [3].
 
@@ -20,7 +23,6 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erf as _erf
 
 SHAPES = [("W1", (10, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64, 3)),
           ("b3", (3,))]
@@ -44,7 +46,7 @@ def flatten(p):
 def init_params(seed=0):
     """Seeded initial parameters (the shared input generator's draw):
     weights uniform in +-1/sqrt(fan_in), biases zero."""
-    from paper_1211_2293_amd import workloads
+    import workloads
     return workloads.mlp_params(seed)
 
 
@@ -61,12 +63,21 @@ def bf16(x):
     return r.reshape(np.shape(x)) if np.ndim(x) else r[0]
 
 
+_GC = math.sqrt(2.0 / math.pi)
+_GA = 0.044715
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+    z = np.asarray(z, np.float64)
+    return 0.5 * z * (1.0 + np.tanh(_GC * (z + _GA * z ** 3)))
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    """d gelu / dz: (1 + t)/2 + z (1 - t^2) c (1 + 3 a z^2) / 2 with
+    t = tanh(c (z + a z^3))."""
+    z = np.asarray(z, np.float64)
+    t = np.tanh(_GC * (z + _GA * z ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * _GC * (1.0 + 3.0 * _GA * z * z)
 
 
 def forward(theta, f, bf16_ops=False):
@@ -197,3 +208,143 @@ def learned_corrections(tree, theta_l, theta_p, params, G=1.0, gs=64, cluster=10
     if rows:
         run()
     return dict(corr=corr, per_group=per_group, pair_group=pair_group, pair_gmax=pair_gmax)
+
+
+def _soft_sum(xt, ex, em, G, eps):
+    """FP64 softened sums at the targets xt [k][3] over the entries (points
+    ex [E][3], masses em [E]): acceleration G sum m d / (|d|^2 + eps^2)^(3/2)
+    and potential -G sum m / (|d|^2 + eps^2)^(1/2), d = x_e - x_t.  An entry
+    at the target itself adds nothing to the acceleration; its potential
+    term is left in (the caller removes it)."""
+    d = ex[None, :, :] - xt[:, None, :]
+    r2 = (d * d).sum(-1) + eps * eps
+    inv = 1.0 / np.sqrt(r2)
+    w = em[None, :] * inv
+    acc = G * ((w * inv * inv)[:, :, None] * d).sum(1)
+    pot = -G * w.sum(1)
+    return acc, pot
+
+
+def learned_walk(tree, theta_l, theta_p, tau, params, G=1.0, eps=1e-2, gs=64, cluster=1024, groups=None,
+                 chunk=1 << 17):
+    """The learned walk with its per-cell fallback, step by step in FP64.
+
+    For every walk group (runs of at most gs sorted bodies inside cluster
+    cells of at most `cluster` bodies), the walk at theta_l (the opening test
+    of §3.1 on the group's box) gives accepted cells and opened leaves.  An
+    accepted cell that the test at theta_p would open is a learned cell: the
+    network (bfloat16 operands as on the GPU) predicts yhat for each of the
+    group's bodies, and the group's largest |yhat| s^2 / |x - C|^2 is the
+    cell's statistic.  If it exceeds tau the cell falls back: its subtree is
+    walked at theta_p, i.e. it is replaced by the items of the plain theta_p
+    walk that lie in its subtree (every ancestor of a learned cell is opened
+    at theta_p as well, since theta_p < theta_l widens the opening radius).
+    Otherwise the cell stays a monopole and each body gets G M s^2 yhat /
+    |x - C|^4 on top.  Cells accepted at both radii are monopoles, opened
+    leaves give their bodies directly.  Forces are FP64 softened sums over
+    these entries (self excluded); the potential keeps the monopoles only.
+
+    Returns a dict: acc [n][3], pot [n] (original order; bodies outside
+    `groups` zero), kept and fell [groups] (learned cells kept / fallen back
+    per walk group), pair_group, pair_cell and pair_gmax per learned
+    (group, cell) pair (in group order), and entries: per computed group
+    (monopole cells, opened leaves) as pre-order index arrays."""
+    n = tree.n
+    c = tree.cells()
+    _, size = tree.root()
+    perm = tree.bodies()["perm"]
+    xs = tree.pos[perm]
+    ms = tree.mass[perm]
+    rcp = tree.mac_radii(theta_p)
+    mbar = c["M"][0] / n
+    gb, gc = tree.groups(gs, cluster)
+    todo = list(range(len(gb))) if groups is None else sorted(int(g) for g in groups)
+    walks = {}
+    pairs = []                                        # (group, cell), in group order
+    for g in todo:
+        b, k = int(gb[g]), int(gc[g])
+        items_l = tree.walk_items_range(theta_l, b, b + k)
+        acc_cells = items_l[items_l >= 0]
+        lo, hi = xs[b:b + k].min(0), xs[b:b + k].max(0)
+        com = c["com"][acc_cells]
+        d = np.maximum(np.maximum(lo[None] - com, 0.0), com - hi[None])
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        learned = acc_cells[~(d2 > rcp[acc_cells])]
+        walks[g] = (items_l, learned)
+        pairs.extend((g, int(cl)) for cl in learned)
+    pair_group = np.array([p[0] for p in pairs], np.int64)
+    pair_cell = np.array([p[1] for p in pairs], np.int64)
+    pair_gmax = np.zeros(len(pairs))
+    pair_corr = {}
+    rows, meta = [], []
+
+    def run():
+        F = np.concatenate([r[0] for r in rows])
+        y, _ = forward(params, F, bf16_ops=True)
+        o = 0
+        for (_, w, ratio), (j, b, k) in zip(rows, meta):
+            yy = y[o:o + k]
+            o += k
+            pair_gmax[j] = float((np.sqrt((yy * yy).sum(1)) * ratio).max())
+            pair_corr[j] = G * w[:, None] * yy
+        rows.clear(), meta.clear()
+
+    held = 0
+    for j, (g, cl) in enumerate(pairs):
+        b, k = int(gb[g]), int(gc[g])
+        x = xs[b:b + k]
+        s = size / 2.0 ** c["level"][cl]
+        M = c["M"][cl]
+        f = np.zeros((k, 10))
+        f[:, :3] = (x - c["com"][cl]) / s
+        f[:, 3:9] = c["Q"][cl] / (M * s * s)
+        f[:, 9] = math.log(M / mbar)
+        dd = x - c["com"][cl]
+        d2 = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+        rows.append((f.astype(np.float32), M * s * s / (d2 * d2), s * s / d2))
+        meta.append((j, b, k))
+        held += k
+        if held >= chunk:
+            run()
+            held = 0
+    if rows:
+        run()
+
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    kept = np.zeros(len(gb), np.int64)
+    fell = np.zeros(len(gb), np.int64)
+    entries = {}
+    first_pair = np.searchsorted(pair_group, todo)       # pairs are in group order
+    for gi, g in enumerate(todo):
+        b, k = int(gb[g]), int(gc[g])
+        items_l, learned = walks[g]
+        j0 = int(first_pair[gi])
+        gm = pair_gmax[j0:j0 + len(learned)]
+        falls = np.sort(learned[gm > tau])
+        keep_j = j0 + np.flatnonzero(~(gm > tau))
+        cells = items_l[items_l >= 0]
+        cells = cells[~np.isin(cells, falls)]
+        leaves = -1 - items_l[items_l < 0]
+        if len(falls):
+            items_p = tree.walk_items_range(theta_p, b, b + k)
+            cc = np.where(items_p >= 0, items_p, -1 - items_p)
+            slot = np.searchsorted(falls, cc, side="right") - 1
+            inside = (slot >= 0) & (cc < c["skip"][falls[np.maximum(slot, 0)]])
+            cells = np.concatenate([cells, items_p[inside & (items_p >= 0)]])
+            leaves = np.concatenate([leaves, cc[inside & (items_p < 0)]])
+        kept[g] = len(keep_j)
+        fell[g] = len(falls)
+        entries[g] = (cells, leaves)
+        nb = c["count"][leaves]
+        bodies = np.repeat(c["begin"][leaves] - np.cumsum(nb) + nb, nb) + np.arange(nb.sum())
+        ex = np.concatenate([c["com"][cells], xs[bodies]])
+        em = np.concatenate([c["M"][cells], ms[bodies]])
+        a, p = _soft_sum(xs[b:b + k], ex, em, G, eps)
+        p += G * ms[b:b + k] / eps                        # the body's own term
+        for j in keep_j:
+            a += pair_corr[j]
+        acc[perm[b:b + k]] = a
+        pot[perm[b:b + k]] = p
+    return dict(acc=acc, pot=pot, kept=kept, fell=fell, pair_group=pair_group, pair_cell=pair_cell,
+                pair_gmax=pair_gmax, entries=entries)

@@ -9,10 +9,10 @@
 // The training target is the residual in units of the quadrupole scale
 //   y = (a_exact - a_mono) |x - C|^4 / (M s^2)   (G = 1),
 // where a_exact sums the cell's bodies directly.  The network is
-// 10-64-64-3 with GELU (erf form, erf by Abramowitz and Stegun 7.1.26);
-// its products run on BF16
-// matrix-core instructions (16x16x16 tiles, FP32 accumulation) with FP32
-// master weights, trained by mean squared error and Adam.
+// 10-64-64-3 with GELU (tanh form); its products run on BF16 matrix-core
+// instructions with FP32 accumulation (training: 16x16x16 tiles through
+// LDS; inference: net_tile in closure.h) with FP32 master weights, trained
+// by mean squared error and Adam.
 //
 // This file: residual generation (one wave per target body; the walk is the
 // batched level-order walk of the force kernel with the box shrunk to the
@@ -23,9 +23,6 @@
 #include <math.h>
 
 namespace tc {
-
-typedef short short4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -280,21 +277,37 @@ __device__ void load_features(const float* __restrict__ feat, int64_t nrows, con
     for (int q = 0; q < 16; ++q) L.x[l * 16 + q] = (valid && q < kNIn) ? f2bf(feat[src * kNIn + q]) : (uint16_t)0;
 }
 
-__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ feat, int64_t nrows,
-                                                    const int32_t* __restrict__ idx, int64_t nb,
-                                                    const MlpState* __restrict__ st, float* __restrict__ yhat,
-                                                    uint32_t* status) {
-    __shared__ NetLds L;
-    load_net(st, L);
-    int64_t src;
-    bool valid;
-    const int64_t s0 = (int64_t)blockIdx.x * kMlpBlock;
-    load_features(feat, nrows, idx, nb, s0, L, src, valid, status);
+// Inference on rows of stored features, with the matrix-core routine of
+// the learned walk (net_tile): one wave per 64 samples, 16 at a time.
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ feat, int64_t nrows,
+                                                     const int32_t* __restrict__ idx, int64_t nb,
+                                                     const MlpState* __restrict__ st, float* __restrict__ yhat,
+                                                     uint32_t* status) {
+    __shared__ NetF N;
+    load_net_frags(st, N, threadIdx.x, blockDim.x);
     __syncthreads();
-    net_forward(L);
-    const int l = threadIdx.x;
-    if (valid)
-        for (int q = 0; q < kNOut; ++q) yhat[(s0 + l) * kNOut + q] = L.yh[l * 16 + q];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & (kWave - 1), g = l >> 4, r = l & 15;
+    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * kWave;
+    if (s0 >= nb) return;
+    for (int tile = 0; tile < 4; ++tile) {
+        const int64_t s = s0 + 16 * tile + r;
+        bool valid = s < nb;
+        int64_t src = valid ? (idx ? (int64_t)idx[s] : s) : 0;
+        if (valid && (src < 0 || src >= nrows)) {  // a row outside feat: left out, flagged
+            atomicOr(status, kFlagBadIndex);
+            valid = false;
+            src = 0;
+        }
+        short4_t x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            x[j] = (valid && k < kNIn) ? bf16_bits(feat[src * kNIn + k]) : (short)0;
+        }
+        const float4_t y = net_tile(N, x);
+        if (g == 0 && valid)
+            for (int q = 0; q < kNOut; ++q) yhat[s * kNOut + q] = y[q];
+    }
 }
 
 // One training block: forward, squared error, backward for 64 samples;
@@ -498,8 +511,8 @@ hipError_t launch_mlp_get(const MlpState* st, float* params, hipStream_t s) {
 
 hipError_t launch_mlp_forward(const MlpState* st, const float* feat, int64_t nrows, const int32_t* idx, int64_t nb,
                               float* yhat, uint32_t* status, hipStream_t s) {
-    const unsigned blocks = (unsigned)((nb + kMlpBlock - 1) / kMlpBlock);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(kMlpBlock), 0, s, feat, nrows, idx, nb, st, yhat, status);
+    const unsigned blocks = (unsigned)((nb + 4 * kWave - 1) / (4 * kWave));
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, s, feat, nrows, idx, nb, st, yhat, status);
     return hipGetLastError();
 }
 

@@ -18,11 +18,13 @@
 // walk at theta_P; with tau = inf it is the plain walk at theta_L plus the
 // corrections.  The potential keeps the monopoles.
 //
-// The network runs on 16x16x16 BF16 matrix-core tiles.  Each layer is
-// computed transposed, Z^T = W^T H^T, so the FP32 output tile a lane holds
-// (rows 4(l/16)+q, column l%16) is exactly the B operand of the next layer:
-// activations never leave registers, and only the transposed BF16 weights
-// (about 12 KiB per block) sit in LDS.
+// A learned cell costs the wave one network pass over its 64 bodies, in
+// four tiles of 16 samples (net_tile in closure.h: activations stay in
+// registers, weights are matrix-core fragments in LDS shared by the block's
+// eight waves, biases start the accumulators).  Sample tiles past the
+// group's last body are skipped.  Each lane computes the features of the
+// samples its lane group feeds to the matrix cores from the group's FP64
+// positions, staged in LDS once per group.
 #include "tc_internal.h"
 #include "closure.h"
 #include "walk_common.h"
@@ -33,99 +35,10 @@ namespace tc {
 namespace {
 
 using namespace walk;
-typedef short short4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kWPB = 4;                               // waves per block
+constexpr int kWPB = 8;                               // waves per block (one copy of the weights each)
 
-struct NetT {                                         // transposed BF16 weights
-    short4_t w1t[kNHid * 16 / 4];                     // W1^T [64 hidden][16 inputs]
-    short4_t w2t[kNHid * kNHid / 4];                  // W2^T [64 out][64 in]
-    short4_t w3t[16 * kNHid / 4];                     // W3^T [16 outputs][64 hidden]
-    float b1[kNHid], b2[kNHid], b3[16];
-};
-
-__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest, ties to even
-    return __builtin_bit_cast(uint16_t, (__bf16)f);
-}
-
-__device__ __forceinline__ float gelu(float z) { return gelu_f(z); }
-
-__device__ __forceinline__ short4_t pack_gelu(float4_t z, const float* b, int h0) {
-    short4_t r;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = (short)f2bf(gelu(z[q] + b[h0 + q]));
-    return r;
-}
-
-__device__ void load_net_t(const MlpState* __restrict__ st, NetT& N) {
-    uint16_t* w1t = reinterpret_cast<uint16_t*>(N.w1t);
-    uint16_t* w2t = reinterpret_cast<uint16_t*>(N.w2t);
-    uint16_t* w3t = reinterpret_cast<uint16_t*>(N.w3t);
-    for (int i = threadIdx.x; i < kNHid * 16; i += blockDim.x) {
-        const int h = i / 16, in = i % 16;
-        w1t[i] = st->w1[in * kNHid + h];
-    }
-    for (int i = threadIdx.x; i < kNHid * kNHid; i += blockDim.x) {
-        const int o = i / kNHid, in = i % kNHid;
-        w2t[i] = st->w2[in * kNHid + o];
-    }
-    for (int i = threadIdx.x; i < 16 * kNHid; i += blockDim.x) {
-        const int o = i / kNHid, h = i % kNHid;
-        w3t[i] = st->w3[h * 16 + o];
-    }
-    for (int i = threadIdx.x; i < kNHid; i += blockDim.x) {
-        N.b1[i] = st->b1[i];
-        N.b2[i] = st->b2[i];
-    }
-    if (threadIdx.x < 16) N.b3[threadIdx.x] = st->b3[threadIdx.x];
-}
-
-// Network outputs for the wave's 64 samples; xs holds one BF16 feature row
-// (16 entries, 10 used) per sample.  Returns lane l's outputs in y[0..2].
-__device__ void net_infer(const NetT& N, const short4_t* xs, float4_t* ys, float y[3]) {
-    const int l = threadIdx.x & (kWave - 1);
-    const int r = l & 15, g = l >> 4;
-    short4_t h1[4][4], h2[4][4];                      // [hidden tile][sample tile]
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-        const short4_t b = xs[(16 * st + r) * 4 + g];  // X^T rows 4g..4g+3, column 16st+r
-#pragma unroll
-        for (int ht = 0; ht < 4; ++ht) {
-            const short4_t a = N.w1t[(16 * ht + r) * 4 + g];
-            float4_t z = {0.f, 0.f, 0.f, 0.f};
-            z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, z, 0, 0, 0);
-            h1[ht][st] = pack_gelu(z, N.b1, 16 * ht + 4 * g);
-        }
-    }
-#pragma unroll
-    for (int ht = 0; ht < 4; ++ht)
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            float4_t z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc)
-                z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w2t[(16 * ht + r) * 16 + 4 * kc + g], h1[kc][st],
-                                                            z, 0, 0, 0);
-            h2[ht][st] = pack_gelu(z, N.b2, 16 * ht + 4 * g);
-        }
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-        float4_t z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
-            z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w3t[r * 16 + 4 * kc + g], h2[kc][st], z, 0, 0, 0);
-        if (g == 0) ys[16 * st + r] = z;               // outputs 0..3 of sample 16st+r
-    }
-    wave_lds_sync();
-    const float4_t o = ys[l];
-    y[0] = o[0] + N.b3[0];
-    y[1] = o[1] + N.b3[1];
-    y[2] = o[2] + N.b3[2];
-    wave_lds_sync();
-}
-
-__global__ void __launch_bounds__(256) k_walk_force_learned(
+__global__ void __launch_bounds__(kWPB * 64, 4) k_walk_force_learned(
     const WalkCell* __restrict__ walk, const double* __restrict__ rcp2, const Body* __restrict__ bodies,
     const float4* __restrict__ bodies32, const Cell* __restrict__ cells, const Moments* __restrict__ mom,
     const uint32_t* __restrict__ bfs2pre, const uint32_t* __restrict__ perm, const int32_t* __restrict__ gbeg,
@@ -137,19 +50,22 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
     constexpr int kReserve = (R - 1) * 21 + R;
     static_assert(kStackCap >= kWave + kReserve + kWave, "stack too small for its bound");
 
-    __shared__ NetT N;
+    __shared__ NetF N;
     __shared__ float4 s_list[kWPB][kListCap];
     __shared__ uint32_t s_stack[kWPB][kStackCap];
-    __shared__ short4_t s_x[kWPB][kWave * 4];
-    __shared__ float4_t s_y[kWPB][kWave];
-    load_net_t(st, N);
+    __shared__ double s_pos[kWPB][3][kWave];          // the group's FP64 positions
+    __shared__ float4_t s_y[kWPB][kWave];              // network outputs per body
+    load_net_frags(st, N, threadIdx.x, blockDim.x);
     __syncthreads();
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int lg = lane >> 4, lr = lane & 15;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     float4* L = s_list[wv];
     uint32_t* S = s_stack[wv];
-    short4_t* xs = s_x[wv];
+    double* PX = s_pos[wv][0];
+    double* PY = s_pos[wv][1];
+    double* PZ = s_pos[wv][2];
     float4_t* ys = s_y[wv];
     const int lpl = 1 << lpl_log2;
     const int slot = lane >> lpl_log2, jj = lane & (lpl - 1);
@@ -172,11 +88,15 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
             const double loz = uniform(wave_min(me.z)), hiz = uniform(wave_max(me.z));
             const double rx = (lox + hix) * 0.5, ry = (loy + hiy) * 0.5, rz = (loz + hiz) * 0.5;
             const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
+            const int ntiles = (gn + 15) >> 4;              // sample tiles holding bodies
 
             Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float kx = 0.f, ky = 0.f, kz = 0.f, ckx = 0.f, cky = 0.f, ckz = 0.f;  // closure corrections
             int len = 0;
             int64_t nm2p = 0, np2p = 0, nlearn = 0, nfall = 0;
+            PX[lane] = me.x;
+            PY[lane] = me.y;
+            PZ[lane] = me.z;
             if (lane == 0) S[0] = 0u;                    // root, mode L
             wave_lds_sync();
             int top = 1;
@@ -294,32 +214,36 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                     const double s = ldexp(size, -lev);
                     const double inv_s = ldexp(1.0 / size, lev);   // exact: size is a power of two
                     const double iq = 1.0 / (M * s * s);
-                    short4_t f4[4];
-                    {
-                        float f[16];
-                        f[0] = (float)((me.x - cx) * inv_s);
-                        f[1] = (float)((me.y - cy) * inv_s);
-                        f[2] = (float)((me.z - cz) * inv_s);
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) f[3 + q] = (float)(mo.Q[q] * iq);
-                        f[9] = (float)log(M / mbar);
-#pragma unroll
-                        for (int q = 10; q < 16; ++q) f[q] = 0.f;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            f4[q] = short4_t{(short)f2bf(f[4 * q]), (short)f2bf(f[4 * q + 1]),
-                                             (short)f2bf(f[4 * q + 2]), (short)f2bf(f[4 * q + 3])};
+                    // features the lane group feeds: g = 0: u (3) and Q_xx; g = 1: Q_yy, Q_zz,
+                    // Q_xy, Q_xz; g = 2: Q_yz and ln(M / mbar); g = 3: zero padding
+                    short4_t xc = {0, 0, 0, 0};
+                    if (lg == 1)
+                        xc = short4_t{bf16_bits((float)(mo.Q[1] * iq)), bf16_bits((float)(mo.Q[2] * iq)),
+                                      bf16_bits((float)(mo.Q[3] * iq)), bf16_bits((float)(mo.Q[4] * iq))};
+                    else if (lg == 2)
+                        xc = short4_t{bf16_bits((float)(mo.Q[5] * iq)), bf16_bits((float)log(M / mbar)), 0, 0};
+                    const short qxx = bf16_bits((float)(mo.Q[0] * iq));
+                    for (int t = 0; t < ntiles; ++t) {
+                        // the weight fragments are read from LDS per tile, not held in registers
+                        __asm__ volatile("" ::: "memory");
+                        short4_t x = xc;
+                        if (lg == 0) {
+                            const int sb = 16 * t + lr;
+                            x = short4_t{bf16_bits((float)((PX[sb] - cx) * inv_s)),
+                                         bf16_bits((float)((PY[sb] - cy) * inv_s)),
+                                         bf16_bits((float)((PZ[sb] - cz) * inv_s)), qxx};
+                        }
+                        const float4_t yt = net_tile(N, x);
+                        if (lg == 0) ys[16 * t + lr] = yt;
                     }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) xs[lane * 4 + q] = f4[q];
                     wave_lds_sync();
-                    float yh[3];
-                    net_infer(N, xs, ys, yh);
+                    const float4_t yo = ys[lane];
+                    wave_lds_sync();
                     // predicted residual relative to the monopole: |yhat| s^2 / |x - C|^2
                     const double ex = me.x - cx, ey = me.y - cy, ez = me.z - cz;
                     const double dd = (ex * ex + ey * ey) + ez * ez;
                     const float ratio =
-                        valid ? sqrtf(yh[0] * yh[0] + yh[1] * yh[1] + yh[2] * yh[2]) * (float)(s * s / dd) : 0.f;
+                        valid ? sqrtf(yo[0] * yo[0] + yo[1] * yo[1] + yo[2] * yo[2]) * (float)(s * s / dd) : 0.f;
                     float gmax = ratio;
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, kWave));
@@ -347,9 +271,9 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                             L[len] = make_float4((float)(cx - rx), (float)(cy - ry), (float)(cz - rz), (float)M);
                         len += 1;
                         const float w = (float)(M * s * s / (dd * dd));   // quadrupole scale
-                        comp_add(kx, ckx, w * yh[0]);
-                        comp_add(ky, cky, w * yh[1]);
-                        comp_add(kz, ckz, w * yh[2]);
+                        comp_add(kx, ckx, w * yo[0]);
+                        comp_add(ky, cky, w * yo[1]);
+                        comp_add(kz, ckz, w * yo[2]);
                     }
                 }
                 wave_lds_sync();
@@ -372,6 +296,7 @@ __global__ void __launch_bounds__(256) k_walk_force_learned(
                 learned_out[g] = nlearn;
                 fallback_out[g] = nfall;
             }
+            wave_lds_sync();                          // positions are rewritten by the next group
             g = sched.pop(xq);
         }
     }
@@ -393,7 +318,8 @@ hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, c
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force_learned, 256, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force_learned, kWPB * 64, 0);
         if (e != hipSuccess) return e;
         resident = cus * (per_cu > 0 ? per_cu : 1);
     }
@@ -403,9 +329,9 @@ hipError_t launch_walk_force_learned(const WalkCell* walk, const double* rcp2, c
     int lpl_log2 = 0;
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     hipLaunchKernelGGL(k_reset_queue_l, dim3(1), dim3(64), 0, s, queue);
-    hipLaunchKernelGGL(k_walk_force_learned, dim3((unsigned)want), dim3(256), 0, s, walk, rcp2, bodies, bodies32, cells,
-                       mom, bfs2pre, perm, gbeg, gcnt, queue, st, lpl_log2, G, eps2, tau, n, prm, acc, pot, m2p,
-                       p2p, learned, fallback);
+    hipLaunchKernelGGL(k_walk_force_learned, dim3((unsigned)want), dim3(kWPB * 64), 0, s, walk, rcp2, bodies,
+                       bodies32, cells, mom, bfs2pre, perm, gbeg, gcnt, queue, st, lpl_log2, G, eps2, tau, n, prm, acc,
+                       pot, m2p, p2p, learned, fallback);
     return hipGetLastError();
 }
 

@@ -24,16 +24,22 @@ def test_bf16_matches_library_cast():
 
 
 def test_gelu_closed_form():
-    z = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
-    ref = np.array([0.5 * v * (1 + math.erf(v / math.sqrt(2))) for v in z])
-    np.testing.assert_allclose(mlp.gelu(z), ref, rtol=1e-15)
+    """The tanh form of GELU: 0 and slope 1/2 at the origin, gelu(z) -
+    gelu(-z) = z exactly (tanh is odd), the identity and zero far out,
+    within the approximation's 5e-4 of the erf form z Phi(z), and the
+    derivative equal to central differences."""
+    z = np.linspace(-6.0, 6.0, 2401)
+    g = mlp.gelu(z)
     assert mlp.gelu(np.array([0.0]))[0] == 0.0
     assert abs(mlp.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
+    np.testing.assert_allclose(g - mlp.gelu(-z), z, rtol=0, atol=1e-15)
+    assert abs(mlp.gelu(np.array([12.0]))[0] - 12.0) < 1e-14 and abs(mlp.gelu(np.array([-12.0]))[0]) < 1e-14
+    erf_form = np.array([0.5 * v * (1 + math.erf(v / math.sqrt(2))) for v in z])
+    assert np.abs(g - erf_form).max() < 5e-4
     h = 1e-6
-    for v in z:
+    for v in (-3.0, -1.0, -0.2, 0.5, 2.0):
         fd = (mlp.gelu(np.array([v + h]))[0] - mlp.gelu(np.array([v - h]))[0]) / (2 * h)
         assert abs(fd - mlp.gelu_grad(np.array([v]))[0]) < 1e-8
-
 
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(81)
@@ -139,7 +145,7 @@ def test_learned_corrections_with_a_constant_network():
     theta_p = 0 every cell the theta_l walk accepts is learned, so the x
     correction of a body is the sum of M s^2 / |x - C|^4 over the accepted
     cells of its group's walk (brute force from the walk items)."""
-    from paper_1211_2293_amd import workloads
+    import workloads
     w = workloads.plummer_sphere(1500, seed=85)
     t = oracle.Tree(w.pos, w.mass, 8)
     p = mlp.unflatten(mlp.init_params(seed=10).astype(np.float64))
@@ -171,3 +177,70 @@ def test_learned_corrections_with_a_constant_network():
     # theta_p close to theta_l leaves few learned cells, never more
     r2 = mlp.learned_corrections(t, 0.7, 0.69, mlp.flatten(p))
     assert np.all(r2["per_group"] <= r["per_group"]) and r2["per_group"].sum() < r["per_group"].sum()
+
+
+def _walk_case():
+    import workloads
+    w = workloads.plummer_sphere(2500, seed=86)
+    t = oracle.Tree(w.pos, w.mass, 16)
+    p = mlp.unflatten(mlp.init_params(seed=11).astype(np.float64))
+    p["W3"] *= 0.2
+    return w, t, mlp.flatten(p)
+
+
+def _covered_once(t, ent):
+    c = t.cells()
+    cover = np.zeros(t.n, np.int64)
+    for i in np.concatenate(ent):
+        cover[c["begin"][i]:c["begin"][i] + c["count"][i]] += 1
+    return np.all(cover == 1)
+
+
+def test_learned_walk_extremes_and_partition():
+    """tau = 0: every learned cell falls back and the walk is the plain walk
+    at theta_p (forces of the C oracle's group walk); tau = inf: every
+    learned cell is kept, the walk is the plain theta_l walk plus the
+    corrections of learned_corrections.  At any tau each group's entries
+    cover every body exactly once (the fallback replaces a cell by its
+    subtree's theta_p items, nothing more, nothing less)."""
+    w, t, theta = _walk_case()
+    gb, gc = t.groups(64, 1024)
+    eps = 1e-2
+    r0 = mlp.learned_walk(t, 0.9, 0.5, 0.0, theta, eps=eps)
+    a_p, p_p = t.forces_groups(0.5, gb, gc, eps=eps)
+    np.testing.assert_allclose(r0["acc"], a_p, rtol=1e-11, atol=1e-11 * np.abs(a_p).max())
+    np.testing.assert_allclose(r0["pot"], p_p, rtol=1e-11)
+    assert np.all(r0["kept"] == 0) and r0["fell"].sum() > 100
+    ri = mlp.learned_walk(t, 0.9, 0.5, np.inf, theta, eps=eps)
+    a_l, p_l = t.forces_groups(0.9, gb, gc, eps=eps)
+    corr = mlp.learned_corrections(t, 0.9, 0.5, theta)
+    np.testing.assert_allclose(ri["acc"], a_l + corr["corr"], rtol=1e-11, atol=1e-11 * np.abs(a_l).max())
+    np.testing.assert_allclose(ri["pot"], p_l, rtol=1e-11)
+    np.testing.assert_array_equal(ri["kept"], corr["per_group"])
+    np.testing.assert_allclose(ri["pair_gmax"], corr["pair_gmax"], rtol=1e-12)
+    tau = float(np.median(ri["pair_gmax"]))
+    rm = mlp.learned_walk(t, 0.9, 0.5, tau, theta, eps=eps)
+    np.testing.assert_array_equal(rm["kept"] + rm["fell"], corr["per_group"])
+    fell_ref = np.bincount(ri["pair_group"][ri["pair_gmax"] > tau], minlength=len(gb))
+    np.testing.assert_array_equal(rm["fell"], fell_ref)
+    assert rm["kept"].sum() > 0 and rm["fell"].sum() > 0
+    for r in (r0, ri, rm):
+        for g, ent in r["entries"].items():
+            assert _covered_once(t, ent), g
+    # the mixed walk lies between the two plain walks in cost and error
+    d, _ = oracle.direct(w.pos, w.mass, eps=eps)
+    e0, em, ei = (oracle.rel_l2(r["acc"], d) for r in (r0, rm, ri))
+    print(f"E vs direct: tau=0 {e0:.3e}, median tau {em:.3e}, tau=inf {ei:.3e}")
+
+
+def test_learned_walk_fallback_of_a_leaf_gives_its_bodies():
+    """A learned leaf that falls back contributes its bodies directly (its
+    subtree's theta_p items are the opened leaf itself)."""
+    w, t, theta = _walk_case()
+    r = mlp.learned_walk(t, 0.9, 0.5, 0.0, theta, eps=1e-2)
+    c = t.cells()
+    leaves = [(g, cl) for g, cl in zip(r["pair_group"], r["pair_cell"]) if c["leaf"][cl]]
+    assert leaves
+    for g, cl in leaves[:50]:
+        cells, opened = r["entries"][g]
+        assert cl in opened and cl not in cells
