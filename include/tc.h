@@ -112,7 +112,11 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
 /* One kick-drift-kick leapfrog step of size dt (finite) on pos and vel (in
  * place, dtype of tc_build, caller order): v += dt/2 a(x); x += dt v;
  * rebuild, moments, walk and forces at the new x with the last theta, G and
- * eps; v += dt/2 a(x').  Requires a previous tc_forces.
+ * eps (or the learned walk set by tc_set_closure, with the network of the
+ * last tc_mlp_load); v += dt/2 a(x').  Requires a previous tc_forces or
+ * tc_forces_learned (it supplies a(x), G and eps); the plain walk also
+ * requires a tc_walk (its theta), the learned walk a tc_mlp_load, else
+ * TC_ESTATE.
  * With tc_set_graph(ctx, 1) everything before the force kernel (about 70
  * short kernels) is recorded once as a HIP graph and replayed: on the
  * context's stream if it is a created stream, else (the null stream cannot
@@ -324,9 +328,19 @@ int tc_mlp_step(tc_ctx *ctx, const float *feat, const float *y, int64_t nrows, c
  * plain walk at theta_l plus every correction.  The potential keeps the
  * monopoles.  acc/pot as tc_forces (device, FP32, either may be NULL).
  * Requires tc_moments and tc_mlp_load; TC_EINVAL for parameters outside
- * the ranges above or dim != 3. */
+ * the ranges above or dim != 3.  The theta of the last tc_walk stays the
+ * plain walk's: a later tc_forces, tc_lists_count or plain tc_leapfrog
+ * walks at that theta again (its opening radii are recomputed first). */
 int tc_forces_learned(tc_ctx *ctx, double G, double eps, double theta_l, double theta_p, double tau,
                       void *acc, void *pot);
+
+/* Make tc_leapfrog evaluate its forces with the learned walk of
+ * tc_forces_learned at (theta_l, theta_p, tau), same ranges, 3D only; every
+ * step then rebuilds the tree, computes both opening radii and runs the
+ * learned walk with the network last loaded by tc_mlp_load (that network's
+ * parameters are read when the step runs).  theta_l = 0 switches back to
+ * the plain walk at the theta of the last tc_walk.  Off by default. */
+int tc_set_closure(tc_ctx *ctx, double theta_l, double theta_p, double tau);
 
 /* Per walk group, the learned cells of the last tc_forces_learned that
  * were kept (learned) and that fell back (fallback): device int64 buffers
@@ -377,6 +391,27 @@ int tc_set_timing(tc_ctx *ctx, int on);
 /* Total milliseconds and launch count of the timed force kernels since
  * timing was switched on.  Synchronises. */
 int tc_get_timing(tc_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* Stages of a force evaluation and of a leapfrog step, for per-stage
+ * timing: the kick + drift, the build (root cube, Morton keys, radix sort,
+ * gather, topology, level order, walk groups), the moments, the opening
+ * radii, the walk + force kernels (plain or learned, with their schedule
+ * kernels), the closing kick, and the diagnostics. */
+enum tc_stage {
+    TC_STAGE_KICK_DRIFT = 0, TC_STAGE_BBOX, TC_STAGE_KEYS, TC_STAGE_SORT, TC_STAGE_GATHER,
+    TC_STAGE_TOPOLOGY, TC_STAGE_LEVELS, TC_STAGE_GROUPS, TC_STAGE_MOMENTS, TC_STAGE_RADII,
+    TC_STAGE_FORCES, TC_STAGE_KICK, TC_STAGE_DIAG, TC_NSTAGES
+};
+
+/* Switch per-stage timing on or off (and reset its totals): when on, every
+ * call records a pair of HIP events on the context's stream around each
+ * stage it enqueues (not inside the graph replay of tc_set_graph, whose
+ * stages are not timed). */
+int tc_set_stage_timing(tc_ctx *ctx, int on);
+
+/* Milliseconds and occurrences per stage (host arrays of TC_NSTAGES, indexed
+ * by tc_stage) since stage timing was switched on.  Synchronises. */
+int tc_get_stage_timing(tc_ctx *ctx, double ms[TC_NSTAGES], int64_t count[TC_NSTAGES]);
 
 #ifdef __cplusplus
 }

@@ -124,8 +124,22 @@ struct tc_ctx {
     int64_t n = 0;
     int leaf_cap = 0;
     double theta = 0.0, G = 1.0, eps = 0.0;
+    bool theta_set = false;    // a tc_walk fixed theta (the plain walk's)
+    bool radii_plain = false;  // the walk records hold the opening radii of theta
+    // the learned walk in tc_leapfrog (tc_set_closure)
+    bool closure = false;
+    double cl_theta_l = 0.0, cl_theta_p = 0.0, cl_tau = 0.0;
     bool timing = false;
     std::vector<hipEvent_t> ev_pending;   // (start, stop) pairs not yet summed
+    // per-stage timing (tc_set_stage_timing): events around each stage
+    struct StageEv {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool stage_timing = false;
+    std::vector<StageEv> st_pending;
+    double st_ms[TC_NSTAGES] = {};
+    int64_t st_count[TC_NSTAGES] = {};
     std::vector<hipEvent_t> ev_pool;
     double t_total_ms = 0.0;
     int64_t t_launches = 0;
@@ -163,9 +177,12 @@ struct tc_ctx {
         int64_t n;
         int dim, dtype, leaf_cap;
         double dt, theta;
+        bool closure;
+        double theta_l, theta_p;
         bool operator==(const GraphKey& o) const {
             return pos == o.pos && vel == o.vel && mass == o.mass && ws == o.ws && n == o.n && dim == o.dim &&
-                   dtype == o.dtype && leaf_cap == o.leaf_cap && dt == o.dt && theta == o.theta;
+                   dtype == o.dtype && leaf_cap == o.leaf_cap && dt == o.dt && theta == o.theta &&
+                   closure == o.closure && theta_l == o.theta_l && theta_p == o.theta_p;
         }
     } g_key{};
 
@@ -218,6 +235,33 @@ hipEvent_t pooled_event(tc_ctx* ctx) {
     return e;
 }
 
+// Events around one stage's launches on stream s when stage timing is on
+// (not inside a graph capture); summed by tc_get_stage_timing.
+struct StageScope {
+    tc_ctx* ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageScope(tc_ctx* c, int st, hipStream_t s_) : ctx(c), stage(st), s(s_) {
+        if (!ctx->stage_timing || ctx->capturing) return;
+        a = pooled_event(ctx);
+        if (a && hipEventRecord(a, s) != hipSuccess) {
+            ctx->ev_pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~StageScope() {
+        if (!a) return;
+        hipEvent_t b = pooled_event(ctx);
+        if (b && hipEventRecord(b, s) == hipSuccess) {
+            ctx->st_pending.push_back({stage, a, b});
+            return;
+        }
+        ctx->ev_pool.push_back(a);
+        if (b) ctx->ev_pool.push_back(b);
+    }
+};
+
 // Everything tc_build enqueues, after its checks.
 // Take the level offsets of the last build whose copy has arrived on the
 // host (never waits).
@@ -235,25 +279,43 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     const Layout& l = ctx->lay;
     const int f64 = dtype == TC_F64;
     DevParams* prm = ctx->prm();
-    TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part), prm, s));
-    TC_HIP(ctx, launch_keys(pos, n, dim, f64, prm, ctx->at<uint64_t>(l.off_keys_a),
-                            ctx->at<uint32_t>(l.off_idx_a), s));
-    TC_HIP(ctx, launch_sort(ctx->at<uint64_t>(l.off_keys_a), ctx->at<uint32_t>(l.off_idx_a),
-                            ctx->at<uint64_t>(l.off_keys_b), ctx->at<uint32_t>(l.off_idx_b), n,
-                            dim * levels_for(dim), ctx->at<uint32_t>(l.off_hist),
-                            ctx->at<uint32_t>(l.off_digit_tot), s));
-    TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
-                              ctx->at<Body>(l.off_bodies), ctx->at<float4>(l.off_bodies32), s));
-    TC_HIP(ctx, launch_topology(ctx->at<uint64_t>(l.off_keys_a), n, dim, leaf_cap,
-                                ctx->at<uint32_t>(l.off_range), ctx->at<uint32_t>(l.off_nper),
-                                ctx->at<uint32_t>(l.off_cstart), ctx->at<uint32_t>(l.off_scan_part),
-                                l.scan_tiles, ctx->at<Cell>(l.off_cells),
-                                l.cmax, prm, s));
-    TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
-                                   ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
-                                   ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
-                                   ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
-                                   ctx->at<uint32_t>(l.off_lvl_off), s));
+    {
+        StageScope st_(ctx, TC_STAGE_BBOX, s);
+        TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part), prm, s));
+    }
+    {
+        StageScope st_(ctx, TC_STAGE_KEYS, s);
+        TC_HIP(ctx, launch_keys(pos, n, dim, f64, prm, ctx->at<uint64_t>(l.off_keys_a),
+                                ctx->at<uint32_t>(l.off_idx_a), s));
+    }
+    {
+        StageScope st_(ctx, TC_STAGE_SORT, s);
+        TC_HIP(ctx, launch_sort(ctx->at<uint64_t>(l.off_keys_a), ctx->at<uint32_t>(l.off_idx_a),
+                                ctx->at<uint64_t>(l.off_keys_b), ctx->at<uint32_t>(l.off_idx_b), n,
+                                dim * levels_for(dim), ctx->at<uint32_t>(l.off_hist),
+                                ctx->at<uint32_t>(l.off_digit_tot), s));
+    }
+    {
+        StageScope st_(ctx, TC_STAGE_GATHER, s);
+        TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
+                                  ctx->at<Body>(l.off_bodies), ctx->at<float4>(l.off_bodies32), s));
+    }
+    {
+        StageScope st_(ctx, TC_STAGE_TOPOLOGY, s);
+        TC_HIP(ctx, launch_topology(ctx->at<uint64_t>(l.off_keys_a), n, dim, leaf_cap,
+                                    ctx->at<uint32_t>(l.off_range), ctx->at<uint32_t>(l.off_nper),
+                                    ctx->at<uint32_t>(l.off_cstart), ctx->at<uint32_t>(l.off_scan_part),
+                                    l.scan_tiles, ctx->at<Cell>(l.off_cells),
+                                    l.cmax, prm, s));
+    }
+    {
+        StageScope st_(ctx, TC_STAGE_LEVELS, s);
+        TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
+                                       ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
+                                       ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
+                                       ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
+                                       ctx->at<uint32_t>(l.off_lvl_off), s));
+    }
     // the depth of this tree, for later moments passes (not inside a capture)
     if (!ctx->capturing) {
         harvest_depth(ctx);
@@ -264,10 +326,13 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
         TC_HIP(ctx, hipEventRecord(ctx->lvl_ev, s));
         ctx->lvl_pending = true;
     }
-    TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
-                              ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
-                              l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
-                              l.gmax, prm, s));
+    {
+        StageScope st_(ctx, TC_STAGE_GROUPS, s);
+        TC_HIP(ctx, launch_groups(ctx->at<Cell>(l.off_cells), l.cmax, ctx->at<uint32_t>(l.off_gper),
+                                  ctx->at<uint32_t>(l.off_goff), ctx->at<uint32_t>(l.off_gscan_part),
+                                  l.cscan_tiles, ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt),
+                                  l.gmax, prm, s));
+    }
     ctx->mass = mass;
     ctx->n = n;
     ctx->leaf_cap = leaf_cap;
@@ -279,6 +344,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
 
 int do_moments(tc_ctx* ctx, hipStream_t s) {
     const Layout& l = ctx->lay;
+    StageScope st_(ctx, TC_STAGE_MOMENTS, s);
     TC_HIP(ctx, launch_moments(ctx->at<Cell>(l.off_cells), ctx->at<Body>(l.off_bodies), ctx->dim, l.cmax,
                                ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_pre2bfs),
                                ctx->at<uint32_t>(l.off_lvl_off), ctx->prm(), ctx->at<Moments>(l.off_mom),
@@ -290,17 +356,73 @@ int do_moments(tc_ctx* ctx, hipStream_t s) {
 
 int do_walk(tc_ctx* ctx, double theta, hipStream_t s) {
     const Layout& l = ctx->lay;
+    StageScope st_(ctx, TC_STAGE_RADII, s);
     TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta, l.cmax,
                            ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), nullptr, ctx->prm(),
                            s));
     ctx->theta = theta;
+    ctx->theta_set = true;
+    ctx->radii_plain = true;
     ctx->state = kWalked;
     ctx->pb_counted = false;
     return TC_OK;
 }
 
+// Opening radii of the learned walk: theta_l into the walk records,
+// theta_p into the second radius array.  The plain walk's theta is kept.
+int do_learned_radii(tc_ctx* ctx, double theta_l, double theta_p, hipStream_t s) {
+    const Layout& l = ctx->lay;
+    StageScope st_(ctx, TC_STAGE_RADII, s);
+    TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta_l, l.cmax,
+                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk), nullptr, ctx->prm(),
+                           s));
+    TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta_p, l.cmax,
+                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk),
+                           ctx->at<double>(l.off_rcp2), ctx->prm(), s));
+    ctx->radii_plain = false;
+    ctx->pb_counted = false;
+    return TC_OK;
+}
+
+// The learned walk and forces (after do_learned_radii with the same thetas).
+int do_forces_learned(tc_ctx* ctx, double G, double eps, double tau) {
+    const Layout& l = ctx->lay;
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        e0 = pooled_event(ctx);
+        e1 = pooled_event(ctx);
+        if (!e0 || !e1) return hip_fail(ctx, hipErrorOutOfMemory);
+        TC_HIP(ctx, hipEventRecord(e0, s));
+    }
+    const float tauf = isinf(tau) ? INFINITY : (float)tau;
+    StageScope st_(ctx, TC_STAGE_FORCES, s);
+    TC_HIP(ctx, launch_walk_force_learned(
+                    ctx->at<WalkCell>(l.off_walk), ctx->at<double>(l.off_rcp2), ctx->at<Body>(l.off_bodies),
+                    ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr, ctx->at<Cell>(l.off_cells),
+                    ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_idx_a),
+                    ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt), l.gmax,
+                    ctx->at<uint32_t>(l.off_queue), ctx->at<MlpState>(l.off_mlp), ctx->leaf_cap, (float)G,
+                    (float)(eps * eps), tauf, ctx->n, ctx->prm(), ctx->at<float>(l.off_acc),
+                    ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p),
+                    ctx->at<int64_t>(l.off_nlearn), ctx->at<int64_t>(l.off_nfall), s));
+    if (ctx->timing) {
+        TC_HIP(ctx, hipEventRecord(e1, s));
+        ctx->ev_pending.push_back(e0);
+        ctx->ev_pending.push_back(e1);
+    }
+    ctx->G = G;
+    ctx->eps = eps;
+    ctx->state = kForced;
+    return TC_OK;
+}
+
 int do_forces(tc_ctx* ctx, double G, double eps) {
     const Layout& l = ctx->lay;
+    if (!ctx->radii_plain) {   // a learned walk left its own radii in the walk records
+        int rc = do_walk(ctx, ctx->theta, ctx->stream);
+        if (rc != TC_OK) return rc;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
         e0 = pooled_event(ctx);
@@ -308,6 +430,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
         if (!e0 || !e1) return hip_fail(ctx, hipErrorOutOfMemory);
         TC_HIP(ctx, hipEventRecord(e0, ctx->stream));
     }
+    StageScope st_(ctx, TC_STAGE_FORCES, ctx->stream);
     float4* walkq = nullptr;
     if (ctx->mp_order == 2 && ctx->dim == 3) {
         walkq = ctx->at<float4>(l.off_walkq);
@@ -350,10 +473,14 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
 // moments, opening radii: about 70 short kernels) on stream s.
 int enqueue_pre_force(tc_ctx* ctx, double dt, void* pos, void* vel, hipStream_t s) {
     const int f64 = ctx->dtype == TC_F64;
-    TC_HIP(ctx, launch_kick_drift(pos, vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, f64, dt, s));
+    {
+        StageScope st_(ctx, TC_STAGE_KICK_DRIFT, s);
+        TC_HIP(ctx, launch_kick_drift(pos, vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, f64, dt, s));
+    }
     int rc = do_build(ctx, pos, ctx->mass, ctx->n, ctx->leaf_cap, ctx->dtype, s);
     if (rc == TC_OK) rc = do_moments(ctx, s);
-    if (rc == TC_OK) rc = do_walk(ctx, ctx->theta, s);
+    if (rc == TC_OK)
+        rc = ctx->closure ? do_learned_radii(ctx, ctx->cl_theta_l, ctx->cl_theta_p, s) : do_walk(ctx, ctx->theta, s);
     return rc;
 }
 
@@ -368,7 +495,10 @@ void drop_graph(tc_ctx* ctx) {
 // (re)captured whenever anything it bakes in (buffers, sizes, dt, theta)
 // changes.  Returns TC_OK, or an error with nothing enqueued.
 int pre_force_graph(tc_ctx* ctx, double dt, void* pos, void* vel) {
-    tc_ctx::GraphKey key{pos, vel, ctx->mass, ctx->ws, ctx->n, ctx->dim, ctx->dtype, ctx->leaf_cap, dt, ctx->theta};
+    tc_ctx::GraphKey key{pos,          vel,           ctx->mass,          ctx->ws,
+                         ctx->n,       ctx->dim,      ctx->dtype,         ctx->leaf_cap,
+                         dt,           ctx->theta,    ctx->closure,       ctx->closure ? ctx->cl_theta_l : 0.0,
+                         ctx->closure ? ctx->cl_theta_p : 0.0};
     const bool own = ctx->stream != nullptr;
     if (!own && !ctx->gstream) {
         TC_HIP(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
@@ -660,6 +790,10 @@ void tc_destroy(tc_ctx* ctx) {
     if (ctx->lvl_ev) (void)hipEventDestroy(ctx->lvl_ev);
     if (ctx->lvl_host) (void)hipHostFree(ctx->lvl_host);
     for (hipEvent_t e : ctx->ev_pending) (void)hipEventDestroy(e);
+    for (const auto& e : ctx->st_pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     drop_graph(ctx);
     if (ctx->g_in) (void)hipEventDestroy(ctx->g_in);
@@ -709,7 +843,7 @@ int tc_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
     if (!ctx) return TC_EINVAL;
     if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
     if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
-    if (ctx->state < kWalked) return TC_ESTATE;
+    if (ctx->state < kWalked || !ctx->theta_set) return TC_ESTATE;
     int rc = do_forces(ctx, G, eps);
     if (rc != TC_OK) return rc;
     const Layout& l = ctx->lay;
@@ -727,11 +861,13 @@ int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
     const size_t es = ctx->dtype == TC_F64 ? 8 : 4;
     if (!aligned(pos, es) || !aligned(vel, es)) return TC_EINVAL;
     if (ctx->state < kForced) return TC_ESTATE;
+    if (ctx->closure ? !ctx->mlp_loaded : !ctx->theta_set) return TC_ESTATE;
     int rc = ctx->use_graph ? pre_force_graph(ctx, dt, pos, vel) : enqueue_pre_force(ctx, dt, pos, vel, ctx->stream);
     if (rc != TC_OK) return rc;
     ctx->state = kWalked;
-    rc = do_forces(ctx, ctx->G, ctx->eps);
+    rc = ctx->closure ? do_forces_learned(ctx, ctx->G, ctx->eps, ctx->cl_tau) : do_forces(ctx, ctx->G, ctx->eps);
     if (rc != TC_OK) return rc;
+    StageScope st_(ctx, TC_STAGE_KICK, ctx->stream);
     TC_HIP(ctx, launch_kick(vel, ctx->at<float>(ctx->lay.off_acc), ctx->n, ctx->dim, ctx->dtype == TC_F64, dt,
                             ctx->stream));
     return TC_OK;
@@ -740,7 +876,11 @@ int tc_leapfrog(tc_ctx* ctx, double dt, void* pos, void* vel) {
 int tc_lists_count(tc_ctx* ctx, int64_t* total, uint32_t* counts) {
     if (!ctx || !total) return TC_EINVAL;
     if (counts && !aligned(counts, 4)) return TC_EINVAL;
-    if (ctx->state < kWalked) return TC_ESTATE;
+    if (ctx->state < kWalked || !ctx->theta_set) return TC_ESTATE;
+    if (!ctx->radii_plain) {   // a learned walk left its own radii in the walk records
+        int rc = do_walk(ctx, ctx->theta, ctx->stream);
+        if (rc != TC_OK) return rc;
+    }
     const Layout& l = ctx->lay;
     hipStream_t s = ctx->stream;
     uint64_t* offs = ctx->at<uint64_t>(l.off_pb_off);
@@ -812,6 +952,7 @@ int tc_diag(tc_ctx* ctx, const void* vel, double out[8]) {
     if (ctx->state < kForced) return TC_ESTATE;
     const Layout& l = ctx->lay;
     double* dout = ctx->at<double>(l.off_diag_out);
+    StageScope st_(ctx, TC_STAGE_DIAG, ctx->stream);
     TC_HIP(ctx, launch_diag(ctx->mass, vel, ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), ctx->n,
                             ctx->dim, ctx->dtype == TC_F64, ctx->at<double>(l.off_diag_part), dout,
                             ctx->stream));
@@ -827,6 +968,7 @@ int tc_diag_async(tc_ctx* ctx, const void* vel, double* out) {
     if (!aligned(vel, ctx->dtype == TC_F64 ? 8 : 4) || !aligned(out, 8)) return TC_EINVAL;
     if (ctx->state < kForced) return TC_ESTATE;
     const Layout& l = ctx->lay;
+    StageScope st_(ctx, TC_STAGE_DIAG, ctx->stream);
     TC_HIP(ctx, launch_diag(ctx->mass, vel, ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot), ctx->n,
                             ctx->dim, ctx->dtype == TC_F64, ctx->at<double>(l.off_diag_part), out, ctx->stream));
     return TC_OK;
@@ -953,32 +1095,33 @@ int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double 
     if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
     if (ctx->dim != 3) return TC_EINVAL;
     if (ctx->state < kMoments || !ctx->mlp_loaded) return TC_ESTATE;
-    int rc = do_walk(ctx, theta_l, ctx->stream);
+    int rc = do_learned_radii(ctx, theta_l, theta_p, ctx->stream);
+    if (rc == TC_OK) rc = do_forces_learned(ctx, G, eps, tau);
     if (rc != TC_OK) return rc;
     const Layout& l = ctx->lay;
     hipStream_t s = ctx->stream;
-    TC_HIP(ctx, launch_mac(ctx->at<Cell>(l.off_cells), ctx->at<Moments>(l.off_mom), ctx->dim, theta_p, l.cmax,
-                           ctx->at<uint32_t>(l.off_pre2bfs), ctx->at<WalkCell>(l.off_walk),
-                           ctx->at<double>(l.off_rcp2), ctx->prm(), s));
-    const float tauf = isinf(tau) ? INFINITY : (float)tau;
-    TC_HIP(ctx, launch_walk_force_learned(
-                    ctx->at<WalkCell>(l.off_walk), ctx->at<double>(l.off_rcp2), ctx->at<Body>(l.off_bodies),
-                    ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr, ctx->at<Cell>(l.off_cells),
-                    ctx->at<Moments>(l.off_mom), ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_idx_a),
-                    ctx->at<int32_t>(l.off_gbeg), ctx->at<int32_t>(l.off_gcnt), l.gmax,
-                    ctx->at<uint32_t>(l.off_queue), ctx->at<MlpState>(l.off_mlp), ctx->leaf_cap, (float)G,
-                    (float)(eps * eps), tauf, ctx->n, ctx->prm(), ctx->at<float>(l.off_acc),
-                    ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p),
-                    ctx->at<int64_t>(l.off_nlearn), ctx->at<int64_t>(l.off_nfall), s));
-    ctx->G = G;
-    ctx->eps = eps;
-    ctx->state = kForced;
     if (acc)
         TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * 3,
                                    hipMemcpyDeviceToDevice, s));
     if (pot)
         TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n,
                                    hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+int tc_set_closure(tc_ctx* ctx, double theta_l, double theta_p, double tau) {
+    if (!ctx) return TC_EINVAL;
+    if (theta_l == 0.0) {
+        ctx->closure = false;
+        return TC_OK;
+    }
+    if (ctx->dim != 3) return TC_EINVAL;
+    if (!(theta_l > 0.0 && theta_l <= 1.0) || !(theta_p >= 0.0 && theta_p < theta_l) || !(tau >= 0.0))
+        return TC_EINVAL;
+    ctx->closure = true;
+    ctx->cl_theta_l = theta_l;
+    ctx->cl_theta_p = theta_p;
+    ctx->cl_tau = tau;
     return TC_OK;
 }
 
@@ -1092,6 +1235,41 @@ int tc_set_timing(tc_ctx* ctx, int on) {
     ctx->timing = on != 0;
     ctx->t_total_ms = 0.0;
     ctx->t_launches = 0;
+    return TC_OK;
+}
+
+int tc_set_stage_timing(tc_ctx* ctx, int on) {
+    if (!ctx) return TC_EINVAL;
+    for (const auto& e : ctx->st_pending) {
+        (void)hipEventSynchronize(e.b);
+        ctx->ev_pool.push_back(e.a);
+        ctx->ev_pool.push_back(e.b);
+    }
+    ctx->st_pending.clear();
+    ctx->stage_timing = on != 0;
+    for (int k = 0; k < TC_NSTAGES; ++k) {
+        ctx->st_ms[k] = 0.0;
+        ctx->st_count[k] = 0;
+    }
+    return TC_OK;
+}
+
+int tc_get_stage_timing(tc_ctx* ctx, double ms[TC_NSTAGES], int64_t count[TC_NSTAGES]) {
+    if (!ctx || !ms || !count) return TC_EINVAL;
+    for (const auto& e : ctx->st_pending) {
+        TC_HIP(ctx, hipEventSynchronize(e.b));
+        float t = 0.f;
+        TC_HIP(ctx, hipEventElapsedTime(&t, e.a, e.b));
+        ctx->st_ms[e.stage] += t;
+        ctx->st_count[e.stage] += 1;
+        ctx->ev_pool.push_back(e.a);
+        ctx->ev_pool.push_back(e.b);
+    }
+    ctx->st_pending.clear();
+    for (int k = 0; k < TC_NSTAGES; ++k) {
+        ms[k] = ctx->st_ms[k];
+        count[k] = ctx->st_count[k];
+    }
     return TC_OK;
 }
 

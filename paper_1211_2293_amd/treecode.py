@@ -23,6 +23,9 @@ TC_F32, TC_F64 = 0, 1
 GROUP = 64
 CLUSTER = 1024
 MLP_NPARAM = 5059
+# tc_stage order
+STAGES = ("kick_drift", "bbox", "keys", "sort", "gather", "topology", "levels", "groups", "moments", "radii",
+          "forces", "kick", "diag")
 
 _LIB = None
 
@@ -68,6 +71,9 @@ def lib():
         "tc_get_timing": (i32, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tc_forces_learned": (i32, [P, dbl, dbl, dbl, dbl, dbl, P, P]),
         "tc_get_learned_counts": (i32, [P, P, P]),
+        "tc_set_closure": (i32, [P, dbl, dbl, dbl]),
+        "tc_set_stage_timing": (i32, [P, i32]),
+        "tc_get_stage_timing": (i32, [P, P, P]),
         "tc_residuals": (i32, [P, dbl, dbl, P, i32, P, P, P, i64, C.POINTER(C.c_int64)]),
         "tc_mlp_load": (i32, [P, P]),
         "tc_mlp_get": (i32, [P, P]),
@@ -328,6 +334,11 @@ class Treecode:
                                        float(tau), _ptr(acc), _ptr(pot)))
         return acc, pot
 
+    def set_closure(self, theta_l: float | None, theta_p: float = 0.5, tau: float = float("inf")):
+        """Learned walk (theta_l, theta_p, tau) in leapfrog steps; None (or 0)
+        switches back to the plain walk."""
+        _check(lib().tc_set_closure(self._h, float(theta_l or 0.0), float(theta_p), float(tau)))
+
     def learned_counts(self):
         """Per walk group: (learned cells kept, learned cells that fell back)."""
         G = self.num_groups()
@@ -476,6 +487,17 @@ class Treecode:
 
     def set_timing(self, on: bool):
         _check(lib().tc_set_timing(self._h, int(bool(on))))
+
+    def set_stage_timing(self, on: bool):
+        """Events around every stage of the following calls (see stage_timing)."""
+        _check(lib().tc_set_stage_timing(self._h, int(bool(on))))
+
+    def stage_timing(self) -> dict:
+        """{stage name: (total ms, occurrences)} since set_stage_timing(True)."""
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().tc_get_stage_timing(self._h, ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p)))
+        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(STAGES)}
 
     def timing(self):
         ms, k = C.c_double(), C.c_int64()

@@ -172,3 +172,32 @@ def test_fmm_checks_arguments_first(L):
     assert L.tc_fmm_get_pairs(h, None, None) == T.TC_ESTATE
     L.tc_destroy(h)
     L.tc_destroy(h2)
+
+
+def test_closure_mode_and_stage_timing_check_arguments_first(L):
+    h = _ctx(L)
+    fake = C.c_void_p(1 << 40)
+    dbl = C.c_double
+    assert L.tc_set_closure(None, dbl(0.8), dbl(0.5), dbl(1e-3)) == T.TC_EINVAL
+    assert L.tc_set_closure(h, dbl(1.2), dbl(0.5), dbl(1e-3)) == T.TC_EINVAL     # theta_l > 1
+    assert L.tc_set_closure(h, dbl(0.5), dbl(0.5), dbl(1e-3)) == T.TC_EINVAL     # theta_p not below theta_l
+    assert L.tc_set_closure(h, dbl(0.8), dbl(-0.1), dbl(1e-3)) == T.TC_EINVAL
+    assert L.tc_set_closure(h, dbl(0.8), dbl(0.5), dbl(-1.0)) == T.TC_EINVAL
+    assert L.tc_set_closure(h, dbl(0.8), dbl(0.5), dbl(float("nan"))) == T.TC_EINVAL
+    assert L.tc_set_closure(h, dbl(0.8), dbl(0.5), dbl(float("inf"))) == T.TC_OK
+    # the learned walk in a step still needs a force evaluation first
+    assert L.tc_leapfrog(h, dbl(1e-3), fake, fake) == T.TC_ESTATE
+    assert L.tc_set_closure(h, dbl(0.0), dbl(0.0), dbl(0.0)) == T.TC_OK          # off
+    h2 = _ctx(L, dim=2)
+    assert L.tc_set_closure(h2, dbl(0.8), dbl(0.5), dbl(1e-3)) == T.TC_EINVAL    # 3D only
+    assert L.tc_set_closure(h2, dbl(0.0), dbl(0.0), dbl(0.0)) == T.TC_OK
+    ms = (C.c_double * len(T.STAGES))()
+    cnt = (C.c_int64 * len(T.STAGES))()
+    assert L.tc_set_stage_timing(None, 1) == T.TC_EINVAL
+    assert L.tc_set_stage_timing(h, 1) == T.TC_OK
+    assert L.tc_get_stage_timing(h, None, cnt) == T.TC_EINVAL
+    assert L.tc_get_stage_timing(h, ms, cnt) == T.TC_OK
+    assert list(cnt) == [0] * len(T.STAGES)
+    assert L.tc_set_stage_timing(h, 0) == T.TC_OK
+    L.tc_destroy(h)
+    L.tc_destroy(h2)

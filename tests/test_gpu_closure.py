@@ -9,7 +9,8 @@ import torch
 
 import oracle
 from oracle import mlp
-from paper_1211_2293_amd import treecode, workloads
+import workloads
+from paper_1211_2293_amd import treecode
 from tests.gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu
@@ -98,17 +99,39 @@ def test_adam_step_matches_oracle(plummer):
     np.testing.assert_allclose(tc.mlp_get().cpu().numpy(), ref, rtol=0, atol=2e-6)
 
 
-def test_training_on_residuals_lowers_the_loss():
+def test_training_on_residuals_lowers_the_loss_and_the_force_error():
+    """Train on the method's own residuals (a 65,536-body Plummer sphere,
+    pairs at theta = 0.9), then show what the network gains at force level:
+    the learned walk at theta_L = 0.8 (every learned cell kept) has a
+    relative force error against the FP64 direct sum well below the plain
+    walk's at the same theta_L."""
     from paper_1211_2293_amd import closure
     w = workloads.plummer_sphere(65536, seed=95)
     tc, keep = _ctx(w)
     f_tr, y_tr = closure.residual_pairs(tc, 0.9, 1e-2, workloads.sample_indices(w.n, 512, seed=203))
     f_va, y_va = closure.residual_pairs(tc, 0.9, 1e-2, workloads.sample_indices(w.n, 128, seed=204))
-    st = closure.train(tc, f_tr, y_tr, epochs=40, val=(f_va, y_va))
+    p0, order = workloads.training_draws(f_tr.shape[0], 200, 4096)
+    st = closure.train(tc, f_tr, y_tr, p0, order, epochs=200, lr=1e-2, lr_final=1e-5, val=(f_va, y_va))
+    quad = float(((closure.quadrupole_prediction(f_va) - y_va) ** 2).mean())
     print(f"pairs {st['pairs']}, {st['steps']} steps; loss {st['loss_first']:.3e} -> {st['loss_last']:.3e}; "
-          f"validation {st['val_mse']:.3e} vs zero predictor {st['val_mse_zero']:.3e}", flush=True)
+          f"validation {st['val_mse']:.3e} vs zero predictor {st['val_mse_zero']:.3e}, "
+          f"analytic quadrupole {quad:.3e}", flush=True)
     assert st["loss_last"] < 0.5 * st["loss_first"]
-    assert st["val_mse"] < 0.5 * st["val_mse_zero"]
+    assert st["val_mse"] < 0.2 * st["val_mse_zero"]
+    sample = workloads.sample_indices(w.n, 2048, seed=104)
+    ref, _ = tc.direct(to_dev(sample.astype(np.int32)), G=1.0, eps=1e-2)
+    ref = ref.cpu().numpy()
+    tc.walk(0.8)
+    plain, _ = tc.forces(1.0, 1e-2)
+    learned, _ = tc.forces_learned(0.8, 0.5, float("inf"), eps=1e-2)
+    tc.walk(0.5)
+    plain_p, _ = tc.forces(1.0, 1e-2)
+    e_plain = oracle.rel_l2(plain.cpu().numpy()[sample], ref)
+    e_learn = oracle.rel_l2(learned.cpu().numpy()[sample], ref)
+    e_p = oracle.rel_l2(plain_p.cpu().numpy()[sample], ref)
+    print(f"E vs direct: plain theta 0.8 {e_plain:.3e}, learned 0.8/0.5 {e_learn:.3e}, plain 0.5 {e_p:.3e}",
+          flush=True)
+    assert e_learn < 0.8 * e_plain
 
 
 @pytest.fixture(scope="module")
@@ -165,20 +188,116 @@ def test_learned_walk_tau_inf_is_theta_l_plus_corrections(learned_case):
     assert corr < 1e-2 and total < 1e-5 + 1e-2 * size and ep < 1e-5
 
 
-def test_learned_walk_fallback_decisions(learned_case):
-    """For a tau between the extremes every learned cell is either kept or
-    falls back (their sum per group does not depend on tau), and a cell
-    falls back exactly when the group's largest |yhat| exceeds tau (up to
-    ties within the network's rounding)."""
-    w, tc, _, t, _, ref = learned_case
-    gm, pg = ref["pair_gmax"], ref["pair_group"]
+def _median_tau_case(w, tc, t, theta, theta_l=0.9, theta_p=0.5, min_size=1e-3):
+    """The GPU's learned walk at the median of the oracle's fallback
+    statistics against the oracle's learned walk with the same tau: kept and
+    fallen-back counts per group, and forces element by element, on every
+    group whose learned cells all lie clear of tau (the statistic comes out
+    of a BF16 network, FP32 on the GPU and FP64 in the oracle, so cells
+    within 2% of tau may decide either way)."""
+    ri = mlp.learned_walk(t, theta_l, theta_p, np.inf, theta, eps=w.eps)
+    gm, pg = ri["pair_gmax"], ri["pair_group"]
     tau = float(np.median(gm))
-    acc, _ = tc.forces_learned(0.9, 0.5, tau, eps=1e-2)
+    ref = mlp.learned_walk(t, theta_l, theta_p, tau, theta, eps=w.eps)
+    acc, pot = tc.forces_learned(theta_l, theta_p, tau, eps=w.eps)
     kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
-    np.testing.assert_array_equal(kept + fell, ref["per_group"])
-    sure_fall = np.bincount(pg[gm > tau * 1.01], minlength=len(kept))
-    sure_keep = np.bincount(pg[gm < tau * 0.99], minlength=len(kept))
-    assert np.all(fell >= sure_fall) and np.all(kept >= sure_keep)
-    print(f"tau={tau:.3f}: kept {kept.sum()} fell {fell.sum()}", flush=True)
-    assert kept.sum() > 0 and fell.sum() > 0
-    assert np.all(np.isfinite(acc.cpu().numpy()))
+    np.testing.assert_array_equal(kept + fell, ref["kept"] + ref["fell"])
+    near = np.zeros(len(kept), bool)
+    near[pg[np.abs(gm - tau) <= 0.02 * tau]] = True
+    safe = ~near
+    np.testing.assert_array_equal(kept[safe], ref["kept"][safe])
+    np.testing.assert_array_equal(fell[safe], ref["fell"][safe])
+    assert kept[safe].sum() > 0 and fell[safe].sum() > 0
+    gb, gc = t.groups(64, 1024)
+    perm = t.bodies()["perm"]
+    sel = np.concatenate([perm[b:b + k] for b, k, ok in zip(gb, gc, safe) if ok])
+    g_acc, g_pot = acc.cpu().numpy()[sel], pot.cpu().numpy()[sel]
+    a, ph = ref["acc"][sel], ref["pot"][sel]
+    a_plain, _ = t.forces_groups(theta_l, gb, gc, eps=w.eps)
+    size = np.linalg.norm(ri["acc"][sel] - a_plain[sel]) / np.linalg.norm(a)
+    ea, ep = oracle.rel_l2(g_acc, a), oracle.rel_l2(g_pot, ph)
+    print(f"tau={tau:.3e}: kept {kept.sum()} fell {fell.sum()}; {safe.sum()}/{len(safe)} groups compared; "
+          f"acc {ea:.2e} (|corr|/|acc| {size:.2e}), pot {ep:.2e}", flush=True)
+    assert size > min_size
+    assert ea < 1e-5 + 1e-2 * size and ep < 1e-5
+
+
+def test_learned_walk_median_tau_plummer(learned_case):
+    w, tc, _, t, theta, _ = learned_case
+    _median_tau_case(w, tc, t, theta)
+
+
+def test_learned_walk_median_tau_clustered_pareto_masses():
+    """32 clumps with Pareto(2.35) masses: ln(M / mbar) of the learned cells
+    spreads far wider than in an equal-mass sphere."""
+    w = workloads.clustered(20000, seed=98)
+    tc, keep = _ctx(w)
+    theta = mlp.init_params(seed=12).astype(np.float32)
+    tc.mlp_load(to_dev(theta))
+    t = oracle.Tree(w.pos, w.mass, 16)
+    # eps = 1e-3 and compact clumps: the learned cells' share of the force is
+    # smaller than in the sphere, the bar 1e-5 + 1e-2 |corr| tighter
+    _median_tau_case(w, tc, t, theta, theta_l=0.8, min_size=3e-4)
+
+
+def test_plain_walk_theta_survives_a_learned_call(learned_case):
+    """A learned evaluation computes its own opening radii; a later plain
+    tc_forces walks at the theta of the last tc_walk again, bit for bit."""
+    w, tc, _, _, _, _ = learned_case
+    tc.walk(0.6)
+    a1, p1 = tc.forces(1.0, 1e-2)
+    a1, p1 = a1.cpu().numpy(), p1.cpu().numpy()
+    tc.forces_learned(0.9, 0.5, float("inf"), eps=1e-2)
+    a2, p2 = tc.forces(1.0, 1e-2)
+    np.testing.assert_array_equal(a2.cpu().numpy(), a1)
+    np.testing.assert_array_equal(p2.cpu().numpy(), p1)
+
+
+def test_learned_leapfrog_step_matches_oracle():
+    """One kick-drift-kick step with the learned walk (tc_set_closure) on
+    FP64 state against oracle.kdk driven by the oracle's learned walk, then
+    a plain step after switching the closure off."""
+    w = workloads.plummer_sphere(4000, seed=99)
+    x0, v0, m = (a.astype(np.float64) for a in (w.pos, w.vel, w.mass))
+    pos, vel, mass = to_dev(x0), to_dev(v0), to_dev(m)
+    tc = treecode.Treecode(3, leaf_cap=16)
+    tc.build(pos, mass)
+    tc.moments()
+    p = mlp.unflatten(mlp.init_params(seed=13).astype(np.float64))
+    p["W3"] *= 0.2
+    theta = mlp.flatten(p).astype(np.float32)
+    tc.mlp_load(to_dev(theta))
+    tl, tp, eps, dt = 0.9, 0.5, 1e-2, 1e-3
+    tc.set_closure(tl, tp, float("inf"))
+    with pytest.raises(treecode.TcError):          # no force evaluation yet
+        tc.leapfrog(dt, pos, vel)
+    tc.forces_learned(tl, tp, float("inf"), eps=eps)
+    tc.leapfrog(dt, pos, vel)
+    acc1, _ = tc.forces_learned(tl, tp, float("inf"), eps=eps)
+    kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
+    assert tc.status() == treecode.TC_OK
+
+    def f(x):
+        return mlp.learned_walk(oracle.Tree(x, m, 16), tl, tp, np.inf, theta, eps=eps)["acc"]
+
+    a0 = f(x0)
+    x1, v1, a1 = oracle.kdk(x0, v0, a0, dt, f)
+    gx, gv = pos.cpu().numpy(), vel.cpu().numpy()
+    ex, ev, ea = oracle.rel_l2(gx, x1), oracle.rel_l2(gv, v1), oracle.rel_l2(acc1.cpu().numpy(), a1)
+    print(f"learned step: x {ex:.2e}, v {ev:.2e}, a(x') {ea:.2e}; kept {kept.sum()} fell {fell.sum()}", flush=True)
+    t1 = oracle.Tree(x1, m, 16)
+    plain_l, _ = t1.walk_forces(tl, eps=eps)
+    size = oracle.rel_l2(a1, plain_l)                # corrections relative to the force
+    assert kept.sum() > 0 and fell.sum() == 0 and size > 1e-3
+    assert ex < 1e-10 and ev < 1e-6 and ea < 1e-5 + 1e-2 * size
+    # switched off: the next step is the plain walk at the last tc_walk's theta
+    tc.set_closure(None)
+    with pytest.raises(treecode.TcError):          # no tc_walk has fixed a plain theta
+        tc.leapfrog(dt, pos, vel)
+    tc.walk(0.5)
+    tc.forces(1.0, eps)
+    tc.leapfrog(dt, pos, vel)
+    a_pl, _ = tc.forces(1.0, eps)
+    t2 = oracle.Tree(pos.cpu().numpy(), m, 16)
+    ref, _ = t2.walk_forces(0.5, eps=eps)
+    assert oracle.rel_l2(a_pl.cpu().numpy(), ref) < 1e-5
