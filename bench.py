@@ -46,6 +46,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, published
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E, published
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 matrix cores, published
+MLP_FLOPS_PER_SAMPLE = 2 * (10 * 64 + 64 * 64 + 64 * 3)    # 9,856: the network's products
 FLOPS_PER_INTERACTION = {3: 20, 2: 15}
 METRIC = "force-evals/s & interactions/s at fixed rel. force error, learned vs plain"
 
@@ -84,23 +87,72 @@ def traffic_from_profile(w, theta: float):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, theta: float, min_seconds: float):
+def build_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("build.hip", "tc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1211_2293_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def build_traffic_from_profile(w, theta: float):
+    """Calibrated HBM bytes per stage of one step from the committed counter
+    summary, when taken on the current build source and on this workload;
+    else None."""
+    p = os.path.join(ROOT, "profiles", "build_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f).get(f"{w.name} N={w.n} theta={theta} eps={w.eps} leaf_cap={w.leaf_cap}")
+    if not d or d.get("source_hash") != build_source_hash():
+        return None
+    return d
+
+
+def cpu_model() -> str | None:
+    """The host CPU's model name from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, theta: float, min_seconds: float, sample=None):
     """The FP64 oracle timed on this host: whole force evaluations of the
     same workload (tree build, walk groups, walk and forces of every body),
-    repeated until min_seconds have passed."""
+    repeated until min_seconds have passed, with the split between the build
+    (tree and moments) and the walk + force summation; the FP64 direct sum
+    on the error sample is timed once."""
     import oracle
     n = w.n
-    times = []
+    times, t_builds, t_walks = [], [], []
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
         tree = oracle.Tree(w.pos, w.mass, w.leaf_cap)
+        t1 = time.perf_counter()
         tree.walk_forces(theta, G=w.G, eps=w.eps)
-        times.append(time.perf_counter() - t0)
+        t2 = time.perf_counter()
+        times.append(t2 - t0)
+        t_builds.append(t1 - t0)
+        t_walks.append(t2 - t1)
         del tree
         if time.perf_counter() - t_start >= min_seconds or len(times) >= 50:
             break
     t_eval = float(np.median(times))
+    t_build, t_walk = float(np.median(t_builds)), float(np.median(t_walks))
+    direct = None
+    if sample is not None:
+        t0 = time.perf_counter()
+        oracle.direct(w.pos, w.mass, G=w.G, eps=w.eps, targets=sample)
+        td = time.perf_counter() - t0
+        direct = {"seconds": td, "pair_terms": int(len(sample)) * n,
+                  "pair_terms_per_s": len(sample) * n / td,
+                  "sample": f"{len(sample)} seeded bodies (seed 104) against all {n}"}
     cores = oracle.num_threads()
     # one core: the tree build plus a seeded sample of 1/32 of the walk groups,
     # scaled to the whole evaluation
@@ -121,9 +173,15 @@ def cpu_baseline(w, theta: float, min_seconds: float):
         "value": 1.0 / t_eval,
         "unit": "force-evals/s",
         "cores": cores,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"FP64 oracle, {len(times)} whole force evaluation(s) of all {n} bodies (build + walk + "
                    f"forces, theta={theta}, OpenMP over walk groups), median {t_eval:.2f} s each"),
+        "stages": {"build_and_moments_s": t_build, "walk_and_forces_s": t_walk,
+                   "force_share": t_walk / (t_build + t_walk),
+                   "note": "share of the walk + force summation in the oracle's evaluation; the paper puts "
+                           "the force step at upwards of 90% of the cycles (§1, §3.2)"},
+        "direct_sum": direct,
         "single_core": {"value": 1.0 / (t_b + t_f), "unit": "force-evals/s", "cores": 1,
                         "sample": f"build of all bodies ({t_b:.2f} s) + walk and forces of {len(sel)} of "
                                   f"{len(gb)} seeded walk groups, scaled ({t_f:.2f} s)"},
@@ -142,6 +200,65 @@ def _clock_mhz():
     except OSError:
         pass
     return None
+
+
+BUILD_STAGES = ("bbox", "keys", "sort", "gather", "topology", "levels", "groups", "moments", "radii")
+
+
+def build_bytes(n, dim, f64, ncells, ngroups):
+    """Algorithmic HBM bytes of each stage of the build (what the stage has
+    to read and write at least) for n bodies of the given input dtype,
+    ncells cells and ngroups walk groups."""
+    e = 8 if f64 else 4                              # input element size
+    pos = dim * e
+    passes = (dim * (21 if dim == 3 else 31) + 7) // 8   # 8-bit digits of the keys
+    return {
+        "bbox": n * (pos + e),                          # positions and masses read
+        "keys": n * (pos + 12),                         # positions read; key and index written
+        "sort": passes * n * 24,                        # each pass: key + index read and written
+        "gather": n * (4 + pos + e + 32 + (0 if f64 else 16)),   # index, position, mass in; FP64 body (+ FP32 copy) out
+        "topology": n * 8 + ncells * 32,                # sorted keys read, cells written
+        "levels": ncells * 12,                          # levels read, level-order maps written
+        "groups": ncells * 12 + ngroups * 8,            # counts and flags read, groups written
+        "moments": n * 32 + ncells * (112 + 48 + 112),  # bodies read; moments and walk records written, children read
+        "radii": ncells * 72,                           # cell and centre of mass read, squared radius written
+    }
+
+
+def stage_breakdown(tc, step, steps, n, dim, f64, traffic=None):
+    """Per-stage device time of `steps` further steps (HIP events around every
+    stage on the context's stream; outside the timed region), and the build
+    stages' achieved bandwidth against their algorithmic bytes."""
+    tc.set_stage_timing(True)
+    for _ in range(steps):
+        step()
+    st = tc.stage_timing()
+    tc.set_stage_timing(False)
+    ncells, ngroups = tc.num_cells(), tc.num_groups()
+    per = {k: {"ms_per_step": v[0] / steps, "per_step": v[1] / steps} for k, v in st.items()}
+    total = sum(v["ms_per_step"] for v in per.values())
+    for v in per.values():
+        v["share"] = v["ms_per_step"] / total if total > 0 else None
+    nbytes = build_bytes(n, dim, f64, ncells, ngroups)
+    rows, b_sum, t_sum, hbm_sum = {}, 0, 0.0, 0.0
+    for k in BUILD_STAGES:
+        ms = per[k]["ms_per_step"]
+        gbs = nbytes[k] / (ms * 1e-3) / 1e9 if ms > 0 else None
+        rows[k] = {"algorithmic_bytes": nbytes[k], "ms": ms, "GB/s": gbs,
+                   "frac": None if gbs is None else gbs / PEAK_HBM_GBS}
+        if traffic is not None and k in traffic["stages"]:
+            tb = traffic["stages"][k]["bytes"]
+            rows[k]["traffic"] = tb
+            rows[k]["traffic_GB/s"] = tb / (ms * 1e-3) / 1e9 if ms > 0 else None
+            hbm_sum += tb
+        b_sum += nbytes[k]
+        t_sum += ms
+    build = {"bound": "hbm", "achieved": b_sum / (t_sum * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": b_sum / (t_sum * 1e-3) / 1e9 / PEAK_HBM_GBS,
+             "traffic": hbm_sum if traffic is not None else None,
+             "traffic_summary": traffic.get("summary") if traffic is not None else None,
+             "algorithmic_bytes": b_sum, "ms": t_sum, "cells": ncells, "groups": ngroups, "stages": rows}
+    return {"steps": steps, "total_ms_per_step": total, "stages": per}, build
 
 
 def rel_error(acc, ref):
@@ -179,6 +296,39 @@ def interp_ms_at_error(sweep, E):
             f = (np.log(E) - np.log(e0)) / (np.log(e1) - np.log(e0))
             return float(np.exp(np.log(m0) + f * (np.log(m1) - np.log(m0))))
     return None
+
+
+def train_closure(tc, w, args, pos, mass):
+    """Residual pairs of the method itself at theta = 0.9 for the seeded
+    training and validation targets (tc_residuals), then training on the
+    GPU (tc_mlp_step); returns the training statistics with the validation
+    MSE of the analytic quadrupole term beside the network's."""
+    import torch
+
+    import workloads
+    from paper_1211_2293_amd import closure
+    tc.build(pos, mass)
+    tc.moments()
+    t0 = time.perf_counter()
+    tr = workloads.sample_indices(w.n, args.train_targets, seed=203)
+    va = workloads.sample_indices(w.n, args.val_targets, seed=204)
+    f_tr, y_tr = closure.residual_pairs(tc, 0.9, w.eps, tr)
+    f_va, y_va = closure.residual_pairs(tc, 0.9, w.eps, va)
+    torch.cuda.synchronize()
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p0, order = workloads.training_draws(f_tr.shape[0], args.epochs, 4096)
+    stats = closure.train(tc, f_tr, y_tr, p0, order, epochs=args.epochs, batch=4096, lr=args.lr,
+                          lr_final=args.lr_final, val=(f_va, y_va), log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    stats["val_mse_quadrupole"] = float(((closure.quadrupole_prediction(f_va) - y_va) ** 2).mean())
+    stats.update({"residual_seconds": t_res, "train_seconds": t_train, "theta": 0.9,
+                  "targets": [len(tr), len(va)], "lr": [args.lr, args.lr_final]})
+    log(f"  closure: {stats['pairs']} pairs in {t_res:.2f} s; {stats['steps']} steps in {t_train:.2f} s; "
+        f"validation MSE {stats['val_mse']:.3e} vs {stats['val_mse_quadrupole']:.3e} for the analytic "
+        f"quadrupole term and {stats['val_mse_zero']:.3e} predicting zero")
+    return stats
 
 
 def learned_study(w, args):
@@ -306,24 +456,7 @@ def learned_study(w, args):
     del tf
     torch.cuda.empty_cache()
 
-    t0 = time.perf_counter()
-    tr = workloads.sample_indices(w.n, args.train_targets, seed=203)
-    va = workloads.sample_indices(w.n, args.val_targets, seed=204)
-    f_tr, y_tr = closure.residual_pairs(tc, 0.9, w.eps, tr)
-    f_va, y_va = closure.residual_pairs(tc, 0.9, w.eps, va)
-    torch.cuda.synchronize()
-    t_res = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    p0, order = workloads.training_draws(f_tr.shape[0], args.epochs, 4096)
-    stats = closure.train(tc, f_tr, y_tr, p0, order, epochs=args.epochs, batch=4096, lr=args.lr,
-                          lr_final=args.lr / 100, val=(f_va, y_va), log=log)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    stats.update({"residual_seconds": t_res, "train_seconds": t_train, "theta": 0.9,
-                  "targets": [len(tr), len(va)]})
-    log(f"  closure: {stats['pairs']} pairs in {t_res:.2f} s; {stats['steps']} steps in {t_train:.2f} s; "
-        f"validation MSE {stats['val_mse']:.3e} vs {stats['val_mse_zero']:.3e} predicting zero")
-    del f_tr, y_tr, f_va, y_va
+    stats = train_closure(tc, w, args, pos, mass)
 
     learned = []
     for th_l, th_p, tau in args.learned:
@@ -335,14 +468,27 @@ def learned_study(w, args):
         acc = run().cpu().numpy()[sample]
         e = rel_error(acc, ref)
         kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
+        _, gcnt = tc.groups()
+        samples = int(((kept + fell) * gcnt.cpu().numpy().astype(np.int64)).sum())
         inter = tc.interactions()
         plain_ms = interp_ms_at_error(sweep, e["E"])
+        at_l = [r["ms_per_eval"] for r in sweep if abs(r["theta"] - th_l) < 1e-9]
+        # a learned evaluation costs at least the plain walk at theta_l (a free
+        # network), and its network at least its BF16 products at the matrix
+        # cores' peak on top
+        floor_mfma_ms = samples * MLP_FLOPS_PER_SAMPLE / (PEAK_BF16_TFLOPS * 1e12) * 1e3
         row = {"theta_l": th_l, "theta_p": th_p, "tau": tau if np.isfinite(tau) else "inf",
                "ms_per_eval": ms, "evals_per_s": 1e3 / ms, "E": e["E"], "p99": e["p99"],
                "interactions_per_body": inter / w.n, "learned_cells": int(kept.sum()),
-               "fallback_cells": int(fell.sum()),
+               "fallback_cells": int(fell.sum()), "network_samples": samples,
                "plain_evals_per_s_at_same_E": None if plain_ms is None else 1e3 / plain_ms,
-               "speedup_vs_plain_at_same_E": None if plain_ms is None else plain_ms / ms}
+               "speedup_vs_plain_at_same_E": None if plain_ms is None else plain_ms / ms,
+               "plain_ms_at_theta_l": at_l[0] if at_l else None,
+               "network_mfma_floor_ms": floor_mfma_ms}
+        if plain_ms and at_l and fell.sum() == 0:
+            # with every learned cell kept the walk is the plain walk at theta_l
+            row["ceiling_speedup_free_network"] = plain_ms / at_l[0]
+            row["ceiling_speedup_at_mfma_peak"] = plain_ms / (at_l[0] + floor_mfma_ms)
         learned.append(row)
         log(f"  learned theta_l={th_l} theta_p={th_p} tau={tau}: {ms:.3f} ms/eval, E={e['E']:.3e}, "
             f"kept {row['learned_cells']} fell back {row['fallback_cells']}, speedup at same E "
@@ -376,8 +522,9 @@ def main():
     ap.add_argument("--fmm-leaf-cap", type=int, default=64, help="leaf size of the FMM's own tree")
     ap.add_argument("--train-targets", type=int, default=4096)
     ap.add_argument("--val-targets", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--lr-final", type=float, default=1e-5)
     ap.add_argument("--learned", type=lambda v: tuple(float(x) for x in v.split(",")), nargs="*",
                     default=[(0.8, 0.5, float("inf")), (0.8, 0.5, 1e-3), (0.8, 0.5, 1e-2), (0.8, 0.5, 3e-2),
                              (0.7, 0.5, float("inf")), (0.7, 0.5, 1e-2)],
@@ -389,6 +536,11 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="one wave per walk group at every n")
     ap.add_argument("--graph", action="store_true",
                     help="replay the pre-force part of each step as a HIP graph")
+    ap.add_argument("--stage-steps", type=int, default=10,
+                    help="further steps with HIP events around every stage (after the timed steps)")
+    ap.add_argument("--closure", type=lambda v: tuple(float(x) for x in v.split(",")), default=None,
+                    metavar="THETA_L,THETA_P,TAU",
+                    help="every step uses the learned walk (trained first on the workload's own residuals)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -434,11 +586,20 @@ def run(args, w, theta, dev, treecode, workloads, torch):
     tc.moments()
     tc.walk(theta)
     tc.forces(w.G, w.eps)
+    closure_info = None
+    if args.closure is not None:
+        # the learned walk in every step: train on the workload's own residuals first
+        closure_info = train_closure(tc, w, args, pos, mass)
+        tl, tp, tau = args.closure
+        tc.set_closure(tl, tp, tau)
+        tc.build(pos, mass)
+        tc.moments()
+        tc.forces_learned(tl, tp, tau, G=w.G, eps=w.eps, want_pot=False)
     torch.cuda.synchronize()
 
     diags = []
     # one row of 8 FP64 diagnostics per step, written on the device
-    record = torch.empty((args.warmup + args.steps, 8), dtype=torch.float64, device="cuda:0")
+    record = torch.empty((args.warmup + args.steps + args.stage_steps, 8), dtype=torch.float64, device="cuda:0")
 
     def step():
         tc.leapfrog(w.dt, pos, vel)
@@ -476,6 +637,26 @@ def run(args, w, theta, dev, treecode, workloads, torch):
     evals_per_s = 1e3 / ms_per_step
     log(f"{ms_per_step:.3f} ms/step, force kernel {kern_avg_ms:.3f} ms/launch ({launches} launches), "
         f"{inter / w.n:.0f} interactions/body, {achieved_tflops:.1f} TFLOP/s in the force kernel")
+    learned_stats = None
+    if args.closure is not None:
+        kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
+        _, gcnt = tc.groups()
+        gcnt = gcnt.cpu().numpy().astype(np.int64)
+        samples = int(((kept + fell) * gcnt).sum())
+        mfma_tflops = samples * MLP_FLOPS_PER_SAMPLE / (kern_avg_ms * 1e-3) / 1e12
+        learned_stats = {"learned_cells": int(kept.sum()), "fallback_cells": int(fell.sum()),
+                         "fallback_fraction": float(fell.sum() / max(kept.sum() + fell.sum(), 1)),
+                         "network_samples": samples, "network_tflops": mfma_tflops,
+                         "network_frac_of_bf16_peak": mfma_tflops / PEAK_BF16_TFLOPS}
+        log(f"learned walk: {learned_stats}")
+
+    if args.stage_steps > 0:
+        stages, build_roof = stage_breakdown(tc, step, args.stage_steps, w.n, w.dim, w.pos.dtype == np.float64,
+                                             traffic=build_traffic_from_profile(w, theta))
+        log("stages (ms/step): " + ", ".join(f"{k} {v['ms_per_step']:.3f}" for k, v in stages["stages"].items()))
+        log(f"build: {build_roof['achieved']:.0f} GB/s of algorithmic bytes ({build_roof['frac']:.3f} of HBM)")
+    else:
+        stages = build_roof = None
 
     if diags and diags[0] is None:
         diags = list(record[:len(diags)].cpu().numpy())
@@ -516,6 +697,7 @@ def run(args, w, theta, dev, treecode, workloads, torch):
         "force_kernel_interactions_per_s": inter / (kern_avg_ms * 1e-3),
         "diagnostics_drift": drift,
         "gpu": gpu,
+        "stages": stages,
         "roofline": {
             "bound": "alu",
             "kernel": "k_walk_force",
@@ -526,25 +708,42 @@ def run(args, w, theta, dev, treecode, workloads, torch):
             "traffic": traffic_from_profile(w, theta),
             "kernel_ms": kern_avg_ms,
             "flops_per_interaction": FLOPS_PER_INTERACTION[w.dim],
+            "build": build_roof,
         },
     }
-    if not args.no_study:
+    if args.closure is not None:
+        tl, tp, tau = args.closure
+        result["config"]["workload"] = (f"{w.name} N={w.n} dim={w.dim} learned walk theta_L={tl} theta_P={tp} "
+                                        f"tau={tau} eps={w.eps} leaf_cap={w.leaf_cap} dt={w.dt} KDK leapfrog step "
+                                        f"(build+moments+radii+learned walk and forces+kicks"
+                                        f"{'' if args.no_diag else '+diagnostics'})")
+        result["config"]["closure"] = {"theta_l": tl, "theta_p": tp, "tau": tau if np.isfinite(tau) else "inf"}
+        result["closure_training"] = closure_info
+        result["learned"] = learned_stats
+        result["roofline"].update({"kernel": "k_walk_force_learned", "bound": "alu",
+                                   "note": "interactions of the walk's monopole and body entries; the network's "
+                                           "BF16 products are in learned.network_tflops"})
+    sample = workloads.sample_indices(w.n, args.sample, seed=104)
+    if not args.no_study or args.closure is not None:
         # error of a fresh evaluation at the final positions
-        sample = workloads.sample_indices(w.n, args.sample, seed=104)
         st = torch.from_numpy(sample.astype(np.int32)).to(dev)
         tc.build(pos, mass)
         tc.moments()
-        tc.walk(theta)
-        acc, _ = tc.forces(w.G, w.eps, want_pot=False)
+        if args.closure is not None:
+            acc, _ = tc.forces_learned(*args.closure, G=w.G, eps=w.eps, want_pot=False)
+        else:
+            tc.walk(theta)
+            acc, _ = tc.forces(w.G, w.eps, want_pot=False)
         ref, _ = tc.direct(st, G=w.G, eps=w.eps)
         result["rel_force_error"] = dict(rel_error(acc.cpu().numpy()[sample], ref.cpu().numpy()[:, :w.dim]),
                                          sample=f"{len(sample)} seeded bodies vs the FP64 direct sum")
         log(f"relative force error E = {result['rel_force_error']['E']:.3e}")
+    if not args.no_study:
         log("learned-vs-plain study ...")
         result["study"] = learned_study(w, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on whole force evaluations ...")
-        result["cpu_baseline"] = cpu_baseline(w, theta, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(w, theta, args.cpu_seconds, sample=sample)
         log(result["cpu_baseline"]["sample"])
     print(json.dumps(result), flush=True)
 
