@@ -125,6 +125,25 @@ int tc_forces(tc_ctx *ctx, double G, double eps, void *acc, void *pot);
  * workspace, n, dt or theta change.  Results are the same as without it. */
 int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one whole
+ * force evaluation, tc_build + tc_moments + tc_walk(theta) + tc_forces(G,
+ * eps) with the same arguments, checks and results, whose workspace is a
+ * device array inside the library (TC_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends) instead of the caller's.  Nothing is allocated:
+ * no device or pinned memory, no events (force and stage timing skip this
+ * call).  TC_EWORKSPACE when tc_workspace_bytes(n, dim, leaf_cap) exceeds
+ * the scratch (45,712 bodies in 3D with leaf_cap 16).  Afterwards the
+ * context works on that scratch as if tc_set_workspace had been called with
+ * it (tc_leapfrog, tc_diag, the accessors), until the next
+ * tc_set_workspace.  Every context on one GPU shares its scratch, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller. */
+#define TC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tc_forces_noalloc(tc_ctx *ctx, const void *pos, const void *mass, int64_t n, int leaf_cap, int dtype,
+                      double theta, double G, double eps, void *acc, void *pot);
+
 /* ---- per-body lists (the treecode as §3.1 states it) ----------------------
  * Every body walks the tree alone (its box is the point itself) at the
  * opening radii of the last tc_walk, and its list of accepted cells and

@@ -11,9 +11,16 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 using namespace tc;
+
+// Device scratch for tc_forces_noalloc: the workspace of callers that cannot
+// allocate device memory.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code this name is only a handle for
+// hipGetSymbolAddress; its device address is looked up once per device.
+static __device__ __align__(256) uint8_t scratch[TC_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -149,6 +156,7 @@ struct tc_ctx {
     // the pre-force part of tc_leapfrog as a replayed graph (see tc_leapfrog)
     bool use_graph = false;
     bool capturing = false;    // inside the graph capture of the pre-force part
+    bool no_alloc = false;     // inside tc_forces_noalloc: no host copies that need pinned memory
     // Level sizes of an earlier tree, for the moments pass: each build copies
     // its level offsets to pinned host memory behind an event; a later call
     // takes them once the event has completed.  Only launch shapes depend
@@ -316,8 +324,9 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
                                        ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
                                        ctx->at<uint32_t>(l.off_lvl_off), s));
     }
-    // the depth of this tree, for later moments passes (not inside a capture)
-    if (!ctx->capturing) {
+    // the depth of this tree, for later moments passes (not inside a capture,
+    // and not where nothing may be allocated: the copy needs pinned memory)
+    if (!ctx->capturing && !ctx->no_alloc) {
         harvest_depth(ctx);
         if (!ctx->lvl_host) TC_HIP(ctx, hipHostMalloc((void**)&ctx->lvl_host, 4 * 64, hipHostMallocDefault));
         if (!ctx->lvl_ev) TC_HIP(ctx, hipEventCreateWithFlags(&ctx->lvl_ev, hipEventDisableTiming));
@@ -1106,6 +1115,64 @@ int tc_forces_learned(tc_ctx* ctx, double G, double eps, double theta_l, double 
     if (pot)
         TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)ctx->n,
                                    hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+// The device address of this device's scratch, looked up on the first call
+// on each device (with that device current) and kept.
+int scratch_address(tc_ctx* ctx, uint8_t** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static uint8_t* addr[kMaxDevices] = {};
+    int dev = 0;
+    TC_HIP(ctx, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return internal_fail("device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        TC_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return internal_fail("no device address for the scratch array");
+        addr[dev] = static_cast<uint8_t*>(p);
+    }
+    *out = addr[dev];
+    return TC_OK;
+}
+
+int tc_forces_noalloc(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf_cap, int dtype,
+                      double theta, double G, double eps, void* acc, void* pot) {
+    if (!ctx || !pos || !mass) return TC_EINVAL;
+    const int dim = ctx->dim;
+    if (!valid_sizes(n, dim, leaf_cap)) return TC_EINVAL;
+    if (dtype != TC_F32 && dtype != TC_F64) return TC_EINVAL;
+    const size_t es = dtype == TC_F64 ? 8 : 4;
+    if (!aligned(pos, es) || !aligned(mass, es)) return TC_EINVAL;
+    if (!(theta >= 0.0 && theta <= 1.0)) return TC_EINVAL;
+    if (!(eps > 0.0) || !isfinite(eps) || !isfinite(G)) return TC_EINVAL;
+    if ((acc && !aligned(acc, 4)) || (pot && !aligned(pot, 4))) return TC_EINVAL;
+    if (make_layout(n, dim, leaf_cap).total > (size_t)TC_NOALLOC_SCRATCH_BYTES) return TC_EWORKSPACE;
+    uint8_t* ws = nullptr;
+    int rc = scratch_address(ctx, &ws);
+    if (rc != TC_OK) return rc;
+    ctx->ws = ws;
+    ctx->ws_bytes = (size_t)TC_NOALLOC_SCRATCH_BYTES;
+    ctx->state = kNone;
+    // no events either: timing stays off for this call
+    const bool timing = ctx->timing, stage_timing = ctx->stage_timing;
+    ctx->timing = ctx->stage_timing = false;
+    ctx->no_alloc = true;
+    hipStream_t s = ctx->stream;
+    rc = do_build(ctx, pos, mass, n, leaf_cap, dtype, s);
+    if (rc == TC_OK) rc = do_moments(ctx, s);
+    if (rc == TC_OK) rc = do_walk(ctx, theta, s);
+    if (rc == TC_OK) rc = do_forces(ctx, G, eps);
+    ctx->no_alloc = false;
+    ctx->timing = timing;
+    ctx->stage_timing = stage_timing;
+    if (rc != TC_OK) return rc;
+    const Layout& l = ctx->lay;
+    if (acc)
+        TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)n * dim, hipMemcpyDeviceToDevice, s));
+    if (pot) TC_HIP(ctx, hipMemcpyAsync(pot, ctx->at<float>(l.off_pot), 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
     return TC_OK;
 }
 

@@ -23,6 +23,7 @@ TC_F32, TC_F64 = 0, 1
 GROUP = 64
 CLUSTER = 1024
 MLP_NPARAM = 5059
+NOALLOC_SCRATCH_BYTES = 64 << 20     # TC_NOALLOC_SCRATCH_BYTES
 # tc_stage order
 STAGES = ("kick_drift", "bbox", "keys", "sort", "gather", "topology", "levels", "groups", "moments", "radii",
           "forces", "kick", "diag")
@@ -72,6 +73,7 @@ def lib():
         "tc_forces_learned": (i32, [P, dbl, dbl, dbl, dbl, dbl, P, P]),
         "tc_get_learned_counts": (i32, [P, P, P]),
         "tc_set_closure": (i32, [P, dbl, dbl, dbl]),
+        "tc_forces_noalloc": (i32, [P, P, P, i64, i32, i32, dbl, dbl, dbl, P, P]),
         "tc_set_stage_timing": (i32, [P, i32]),
         "tc_get_stage_timing": (i32, [P, P, P]),
         "tc_residuals": (i32, [P, dbl, dbl, P, i32, P, P, P, i64, C.POINTER(C.c_int64)]),

@@ -201,3 +201,23 @@ def test_closure_mode_and_stage_timing_check_arguments_first(L):
     assert L.tc_set_stage_timing(h, 0) == T.TC_OK
     L.tc_destroy(h)
     L.tc_destroy(h2)
+
+
+def test_noalloc_entry_checks_arguments_first(L):
+    h = _ctx(L)
+    fake = C.c_void_p(1 << 40)
+    f = L.tc_forces_noalloc
+    dbl = C.c_double
+    assert f(None, fake, fake, 1000, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EINVAL
+    assert f(h, None, fake, 1000, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EINVAL
+    assert f(h, fake, fake, 0, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EINVAL
+    assert f(h, fake, fake, 1000, 16, 7, dbl(0.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EINVAL
+    assert f(h, fake, fake, 1000, 16, T.TC_F32, dbl(1.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EINVAL
+    assert f(h, fake, fake, 1000, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(0.0), None, None) == T.TC_EINVAL
+    assert f(h, fake, fake, 1000, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(1e-2), C.c_void_p((1 << 40) + 2),
+             None) == T.TC_EINVAL
+    # a system whose workspace exceeds the scratch is refused before any device call
+    big = 1 << 20
+    assert L.tc_workspace_bytes(big, 3, 16) > T.NOALLOC_SCRATCH_BYTES
+    assert f(h, fake, fake, big, 16, T.TC_F32, dbl(0.5), dbl(1.0), dbl(1e-2), None, None) == T.TC_EWORKSPACE
+    L.tc_destroy(h)
