@@ -168,3 +168,37 @@ def test_graph_replay_matches_eager_launches(created_stream):
         np.testing.assert_array_equal(dg, de)
     # both buffer pairs started from the same state
     np.testing.assert_array_equal(graph[0][0], graph[1][0])
+
+
+def test_stage_timing_counts_every_stage_and_changes_nothing():
+    """Per-stage timing brackets each stage of a leapfrog step once per step
+    (the diagnostics once per call) and leaves the results bit for bit as
+    they are without it."""
+    w = workloads.plummer_sphere(30000, seed=73)
+
+    def run(timed):
+        pos, vel, mass = to_dev(w.pos), to_dev(w.vel), to_dev(w.mass)
+        tc = treecode.Treecode(3, leaf_cap=16)
+        tc.build(pos, mass)
+        tc.moments()
+        tc.walk(0.5)
+        tc.forces(1.0, 1e-2)
+        tc.set_stage_timing(timed)
+        rec = torch.empty(8, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            tc.leapfrog(1e-3, pos, vel)
+            tc.diag_async(vel, rec)
+        st = tc.stage_timing() if timed else None
+        tc.set_stage_timing(False)
+        assert tc.status() == treecode.TC_OK
+        return pos.cpu().numpy(), vel.cpu().numpy(), rec.cpu().numpy(), st
+
+    x0, v0, d0, _ = run(False)
+    x1, v1, d1, st = run(True)
+    np.testing.assert_array_equal(x1, x0)
+    np.testing.assert_array_equal(v1, v0)
+    np.testing.assert_array_equal(d1, d0)
+    for name, (ms, cnt) in st.items():
+        assert cnt == 3, (name, cnt)
+        assert ms > 0.0, name
+    print("stage ms per step: " + ", ".join(f"{k} {v[0] / 3:.3f}" for k, v in st.items()), flush=True)
