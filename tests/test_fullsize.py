@@ -2,8 +2,9 @@
 benchmark times (build, moments, radii, fused walk + force through the C
 ABI): trees, groups and interaction counts bit-exact against the oracle over
 all bodies, forces on a seeded sample of walk groups within 1e-5 relative L2
-(the oracle computes those groups one by one), and the learned walk at
-tau = inf on sampled groups."""
+(the oracle computes those groups one by one), and the learned walk on
+sampled groups: at tau = inf on the 1M sphere, with the clustered
+workload's fallback threshold on its 16.7M bodies."""
 import numpy as np
 import pytest
 
@@ -98,3 +99,56 @@ def test_learned_walk_1m_sampled_groups():
     total = oracle.rel_l2(g_acc, a[bodies] + ref["corr"][bodies])
     print(f"learned 1M, {len(bodies)} sampled bodies: corrections {corr:.2e}, total {total:.2e}", flush=True)
     assert corr < 1e-2 and total < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_learned_walk_16m_clustered_sampled_groups():
+    """The 16.7M-body clustered workload with its learned configuration
+    (theta_L = 0.7, theta_P = 0.5, fallback at tau = 1e-3) on sampled walk
+    groups against the oracle's learned walk: kept and fallen-back cells per
+    group (groups whose statistics all lie clear of tau) and the forces of
+    those groups' bodies."""
+    from paper_1211_2293_amd import treecode
+    w = workloads.clustered()
+    tl, tp, tau = 0.7, 0.5, 1e-3
+    print(f"{w.name} n={w.n}: GPU learned walk", flush=True)
+    tc = treecode.Treecode(3, leaf_cap=16)
+    keep = (to_dev(w.pos), to_dev(w.mass))
+    tc.build(*keep)
+    tc.moments()
+    # a random network scaled so that a few percent of its fallback
+    # statistics exceed tau (unscaled, their median is about 2.5e-2): near a
+    # tail of the distribution some groups hold no statistic within rounding
+    # of tau, whereas near its median every group does.  With this network
+    # and sample, 6 of the 160 groups lie clear of tau by 2%, holding 1257
+    # kept and 110 fallen-back cells
+    p = mlp.unflatten(mlp.init_params(seed=14).astype(np.float64))
+    p["W3"] *= 0.007
+    theta = mlp.flatten(p).astype(np.float32)
+    tc.mlp_load(to_dev(theta))
+    acc, pot = tc.forces_learned(tl, tp, tau, eps=w.eps)
+    kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
+    gb, gc = (v.cpu().numpy() for v in tc.groups())
+    assert tc.status() == treecode.TC_OK
+    print("  oracle tree", flush=True)
+    t = oracle.Tree(w.pos, w.mass, 16)
+    sel = np.sort(np.random.default_rng(302).choice(len(gb), size=160, replace=False))
+    print("  oracle learned walk on sampled groups", flush=True)
+    ref = mlp.learned_walk(t, tl, tp, tau, theta, eps=w.eps, groups=sel)
+    clear = np.ones(len(gb), bool)
+    clear[ref["pair_group"][np.abs(ref["pair_gmax"] - tau) <= 0.02 * tau]] = False
+    ok = sel[clear[sel]]
+    assert len(ok) >= 4
+    np.testing.assert_array_equal(kept[sel] + fell[sel], ref["kept"][sel] + ref["fell"][sel])
+    np.testing.assert_array_equal(kept[ok], ref["kept"][ok])
+    np.testing.assert_array_equal(fell[ok], ref["fell"][ok])
+    perm = t.bodies()["perm"]
+    bodies = np.concatenate([perm[b:b + k] for b, k in zip(gb[ok], gc[ok])])
+    ea = oracle.rel_l2(acc.cpu().numpy()[bodies], ref["acc"][bodies])
+    ep = oracle.rel_l2(pot.cpu().numpy()[bodies], ref["pot"][bodies])
+    print(f"  {len(ok)} groups, {len(bodies)} bodies: kept {kept[ok].sum()} fell {fell[ok].sum()}; "
+          f"acc {ea:.2e} pot {ep:.2e}", flush=True)
+    assert fell[ok].sum() > 0 and kept[ok].sum() > 0
+    # the few kept cells carry BF16 network corrections (FP32 on the GPU, FP64
+    # in the oracle); everything else is the plain walk's 1e-5
+    assert ea < 1e-4 and ep < TOL
