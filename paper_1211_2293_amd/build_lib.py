@@ -19,6 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 SOURCES = ["api.hip", "build.hip", "force.hip", "step.hip", "closure.hip", "learned.hip", "direct.hip", "perbody.hip", "fmm.hip"]
+# a benchmark program beside the library: the force loop's own throughput
+PROBE_SRC = "loop_probe.hip"
+PROBE = os.path.join(HERE, "loop_probe")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -45,10 +48,25 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def _build_probe(verbose: bool) -> str:
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, *CFLAGS, os.path.join(CSRC, PROBE_SRC), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in p.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{err}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        probe = ex.submit(_build_probe, verbose)
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -44,7 +44,8 @@ constexpr int kWavesPerBlock = 4;
 // only; the cells of the deal level ([deal_lo, deal_hi) in level order) are
 // dealt out by index modulo NP; everything deeper follows its ancestor at
 // the deal level.  The parts' lists together are the whole walk's.
-template <int D, bool PLAIN, bool QUAD, int NP = 1>
+// STAGED: the list sums in staged batches (flush).
+template <int D, bool PLAIN, bool QUAD, int NP = 1, bool STAGED = false>
 __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, const float4* __restrict__ walkq,
                                            const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
                                            float4* L, uint32_t* S, float4* LQ, int lpl_log2, float eps2,
@@ -143,7 +144,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 nm2p += na;
             } else if (na) {
                 if (len + na > kListCap) {
-                    flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                    flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
                     len = 0;
                 }
                 if (accept)
@@ -174,7 +175,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                         tot += cl;
                     }
                     if (len + tot > kListCap) {
-                        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                        flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
                         len = 0;
                     }
                     if (jj < my_cnt)
@@ -191,7 +192,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                     for (int o = 0; o < cl; o += kWave) {
                         const int m = min(kWave, cl - o);
                         if (len + m > kListCap) {
-                            flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+                            flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
                             len = 0;
                         }
                         if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
@@ -209,7 +210,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 q1 = q1n;
             }
         }
-        flush<D, PLAIN>(L, len, xi, yi, zi, eps2, a);
+        flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
         if (QUAD) flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
 }
 
@@ -338,7 +339,7 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
 
         Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         int64_t nm2p = 0, np2p = 0;
-        walk_group<D, PLAIN, QUAD, kCoopParts>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv],
+        walk_group<D, PLAIN, QUAD, kCoopParts, true>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv],
                                                lpl_log2, eps2, lox, hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi,
                                                0u, 1, a, nm2p, np2p, wv, deal_lo, deal_hi);
         double px = (double)a.sx + (double)a.cx, py = (double)a.sy + (double)a.cy;
