@@ -61,14 +61,13 @@ struct Acc {
 // STAGED takes each half of a batch of 8 entries in three stages
 // (distances, reciprocal square roots, sums): the same operations in the
 // same order, so the same bits, but the four v_rsq issue back to back and
-// wait on one another's latency instead of each on its own.  Measured: the
-// loop alone with its list in LDS, 5 waves per SIMD, ran 2.75e12
-// interactions/s entry by entry and 3.1-3.2e12 staged (8 waves: 3.2e12 and
-// 3.4e12); in the walk kernels it paid only where the list sums share the
-// SIMD with few walking waves (walks shared by a block's waves: 8% at
-// 50,000 bodies); with one wave per group the compiler then issues four
-// list reads at a time instead of eight, and the kernel ran as fast at 1M
-// bodies and 1.8% slower at 4M.
+// their latencies overlap instead of each stalling the wave in turn.
+// Measured with loop_probe (this loop alone over a list in LDS): 2.9e12
+// interactions/s entry by entry and 3.0e12 staged at 5 waves per SIMD,
+// 3.15e12 either way at 8.  In the walk kernels it pays in the shared walks
+// (8% at 50,000 bodies); with one wave per group the compiler then issues
+// four list reads at a time instead of eight, and that kernel ran as fast at
+// 1M bodies and 1.8% slower at 4M.
 template <int D, bool PLAIN = false, bool STAGED = false>
 static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, float zi, float eps2, Acc& a) {
     const int lane = threadIdx.x & (kWave - 1);
