@@ -133,7 +133,7 @@ int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
  * until the process ends) instead of the caller's.  Nothing is allocated:
  * no device or pinned memory, no events (force and stage timing skip this
  * call).  TC_EWORKSPACE when tc_workspace_bytes(n, dim, leaf_cap) exceeds
- * the scratch (45,712 bodies in 3D with leaf_cap 16).  Afterwards the
+ * the scratch (47,854 bodies in 3D with leaf_cap 16).  Afterwards the
  * context works on that scratch as if tc_set_workspace had been called with
  * it (tc_leapfrog, tc_diag, the accessors), until the next
  * tc_set_workspace.  Every context on one GPU shares its scratch, which

@@ -76,9 +76,6 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_diag_part = take(8 * 8 * (size_t)kDiagBlocks);
     l.off_diag_out = take(8 * 8);
     l.lvl_tiles = sort_tiles_max(l.cmax);
-    l.off_lvl_keys_a = take(8 * (size_t)l.cmax);
-    l.off_lvl_keys_b = take(8 * (size_t)l.cmax);
-    l.off_lvl_idx_a = take(4 * (size_t)l.cmax);
     l.off_lvl_idx_b = take(4 * (size_t)l.cmax);
     l.off_pre2bfs = take(4 * (size_t)l.cmax);
     l.off_lvl_hist = take(4 * 256 * (size_t)l.lvl_tiles);
@@ -318,8 +315,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     }
     {
         StageScope st_(ctx, TC_STAGE_LEVELS, s);
-        TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm, ctx->at<uint64_t>(l.off_lvl_keys_a),
-                                       ctx->at<uint32_t>(l.off_lvl_idx_a), ctx->at<uint64_t>(l.off_lvl_keys_b),
+        TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm,
                                        ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
                                        ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
                                        ctx->at<uint32_t>(l.off_lvl_off), s));

@@ -193,10 +193,50 @@ __global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t
 // Recording every round's per-wave digit counts and placing all keys after
 // one prefix pass (three barriers per tile instead of three per round) took
 // 18.4 us.  PER keys per thread, tiles of 256 PER keys (sort_per).
-template <int PER>
+//
+// Where a pass's pairs come from and go to.  A plain pass reads keys and
+// values (nullable) and writes both at their places.  The level pass sorts
+// the cells by level (pre-order within a level, so the children of a cell
+// stay adjacent): it reads each cell's level as its key and its pre-order
+// index as its value, writes the level order both ways, and the first tile
+// writes where each level starts (its digit bases: no tile precedes it).
+struct PairsIn {
+    const uint64_t* __restrict__ k;
+    const uint32_t* __restrict__ v;
+    __device__ uint64_t key(int64_t i) const { return k[i]; }
+    __device__ uint32_t val(int64_t i) const { return v ? v[i] : 0u; }
+};
+struct PairsOut {
+    uint64_t* __restrict__ k;
+    uint32_t* __restrict__ v;
+    __device__ void put(uint32_t p, uint64_t key, uint32_t val) const {
+        k[p] = key;
+        if (v) v[p] = val;
+    }
+    __device__ void starts(int, uint32_t) const {}
+};
+struct LevelsIn {
+    const Cell* __restrict__ cells;
+    __device__ uint64_t key(int64_t i) const { return (uint64_t)cells[i].level; }
+    __device__ uint32_t val(int64_t i) const { return (uint32_t)i; }
+};
+struct LevelsOut {
+    uint32_t* __restrict__ bfs2pre;
+    uint32_t* __restrict__ pre2bfs;
+    uint32_t* __restrict__ lvl_off;   // levels 0..L and the end
+    int L;
+    __device__ void put(uint32_t p, uint64_t, uint32_t val) const {
+        bfs2pre[p] = val;
+        pre2bfs[val] = p;
+    }
+    __device__ void starts(int d, uint32_t base) const {
+        if (d <= L + 1) lvl_off[d] = base;
+    }
+};
+
+template <int PER, class In>
 // n_live (nullable, device): sort only the first min(n, *n_live) keys.
-__global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                   const uint32_t* __restrict__ n_live, int shift,
+__global__ void __launch_bounds__(256) k_sort_hist(In in, int64_t n, const uint32_t* __restrict__ n_live, int shift,
                                                    uint32_t* __restrict__ hist, int64_t tiles) {
     if (n_live && (int64_t)*n_live < n) n = *n_live;
     __shared__ uint32_t cnt[4][256];
@@ -208,7 +248,7 @@ __global__ void __launch_bounds__(256) k_sort_hist(const uint64_t* __restrict__ 
 #pragma unroll 4
     for (int j = 0; j < PER; ++j) {
         const int64_t i = base + j * 256 + t;
-        if (i < n) atomicAdd(&cnt[w][(unsigned)(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&cnt[w][(unsigned)(in.key(i) >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[(int64_t)t * tiles + tile] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
@@ -256,11 +296,9 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, 
 // kSortScanInScatter) this costs less than the scan's own launch.
 constexpr int64_t kSortScanInScatter = 128;
 
-template <int PER, bool SCAN = false>
-__global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                      int64_t n, const uint32_t* __restrict__ n_live, int shift,
-                                                      const uint32_t* __restrict__ hist,
+template <int PER, bool SCAN, class In, class Out>
+__global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n, const uint32_t* __restrict__ n_live,
+                                                      int shift, const uint32_t* __restrict__ hist,
                                                       uint32_t* __restrict__ digit_tot, int64_t tiles) {
     if (n_live && (int64_t)*n_live < n) n = *n_live;
     __shared__ uint32_t s_base[256];
@@ -284,14 +322,15 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
         const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
         s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
     }
+    if (tile == 0) out.starts(t, s_base[t]);
     for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
     uint64_t kr[PER];
     uint32_t vr[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int64_t i = tile * (256 * PER) + r * 256 + t;
-        kr[r] = i < n ? kin[i] : 0ull;
-        vr[r] = (i < n && vin) ? vin[i] : 0u;
+        kr[r] = i < n ? in.key(i) : 0ull;
+        vr[r] = i < n ? in.val(i) : 0u;
     }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -313,8 +352,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const uint64_t* __restrict
         if (valid) {
             uint32_t p = s_base[d] + (uint32_t)__popcll(before);
             for (int a = 0; a < w; ++a) p += s_wcnt[a][d];
-            kout[p] = k;
-            if (vout) vout[p] = vr[r];
+            out.put(p, k, vr[r]);
         }
         __syncthreads();
         s_base[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
@@ -860,18 +898,6 @@ __global__ void __launch_bounds__(kDeepThreads) k_moments_head(const uint32_t* _
     }
 }
 
-// Start of each level in level order (levels 0..L, plus the end), from the
-// per-level counts the level sort produced.
-__device__ __forceinline__ void level_offsets(const uint32_t* __restrict__ digit_tot, int L,
-                                              uint32_t* __restrict__ lvl_off) {
-    uint32_t run = 0;
-    for (int l = 0; l <= L; ++l) {
-        lvl_off[l] = run;
-        run += digit_tot[l];
-    }
-    lvl_off[L + 1] = run;
-}
-
 // ----------------------------------------------------------------- mac ----
 
 template <int D>
@@ -910,38 +936,6 @@ __global__ void __launch_bounds__(256) k_mac(const Cell* __restrict__ cells, con
         if (rc_out) rc_out[pre2bfs[k]] = r * r;
         else walk[pre2bfs[k]].rcrit2 = r * r;
     }
-}
-
-// --------------------------------------------------------- level order ----
-// Level order of the cells: a stable sort of (level, pre-order index), one
-// 8-bit radix pass over the live cells (the sort reads their count on the
-// device; the grid covers the cmax bound).  Within a level, pre-order keeps
-// children of one parent adjacent.
-
-__global__ void __launch_bounds__(256) k_level_keys(const Cell* __restrict__ cells, const DevParams* __restrict__ prm,
-                                                    int64_t cmax, uint64_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ idx) {
-    int64_t C = prm->ncells;
-    if (C > cmax) C = cmax;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C; k += (int64_t)gridDim.x * blockDim.x) {
-        keys[k] = (uint64_t)cells[k].level;
-        idx[k] = (uint32_t)k;
-    }
-}
-
-// The inverse of the level order, and (one thread) the start of each level
-// from the per-level counts of the sort.
-__global__ void __launch_bounds__(256) k_level_inverse(const uint32_t* __restrict__ bfs2pre,
-                                                       const DevParams* __restrict__ prm, int64_t cmax,
-                                                       uint32_t* __restrict__ pre2bfs,
-                                                       const uint32_t* __restrict__ digit_tot, int L,
-                                                       uint32_t* __restrict__ lvl_off) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) level_offsets(digit_tot, L, lvl_off);
-    int64_t C = prm->ncells;
-    if (C > cmax) C = cmax;
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < C;
-         b += (int64_t)gridDim.x * blockDim.x)
-        pre2bfs[bfs2pre[b]] = (uint32_t)b;
 }
 
 // ---------------------------------------------------------- walk groups ----
@@ -1048,27 +1042,31 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
     return hipGetLastError();
 }
 
+// One pass of the reduce-then-scan sort (2 or 3 launches).
+template <int PER, class In, class Out>
+static void sort_pass(In in, Out out, int64_t n, const uint32_t* n_live, int shift, uint32_t* hist,
+                      uint32_t* digit_tot, hipStream_t s) {
+    const int64_t tiles = (n + 256 * PER - 1) / (256 * PER);
+    hipLaunchKernelGGL((k_sort_hist<PER, In>), dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live, shift, hist,
+                       tiles);
+    if (tiles <= kSortScanInScatter) {
+        hipLaunchKernelGGL((k_sort_scatter<PER, true, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
+                           n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
+        return;
+    }
+    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
+    hipLaunchKernelGGL((k_sort_scatter<PER, false, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
+                       n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
+}
+
 template <int PER>
 static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, int64_t n,
                         const uint32_t* n_live, int passes, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
-    const int64_t tiles = (n + 256 * PER - 1) / (256 * PER);
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
         const bool even = (p % 2) == 0;
-        const uint64_t* kin = even ? keys_a : keys_b;
-        const uint32_t* vin = even ? idx_a : idx_b;
-        uint64_t* kout = even ? keys_b : keys_a;
-        uint32_t* vout = even ? idx_b : idx_a;
-        hipLaunchKernelGGL(k_sort_hist<PER>, dim3((unsigned)tiles), dim3(256), 0, s, kin, n, n_live, shift, hist,
-                           tiles);
-        if (tiles <= kSortScanInScatter) {
-            hipLaunchKernelGGL((k_sort_scatter<PER, true>), dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout,
-                               vout, n, n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
-            continue;
-        }
-        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
-        hipLaunchKernelGGL((k_sort_scatter<PER, false>), dim3((unsigned)tiles), dim3(256), 0, s, kin, vin, kout, vout,
-                           n, n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
+        const PairsIn in{even ? keys_a : keys_b, even ? idx_a : idx_b};
+        const PairsOut out{even ? keys_b : keys_a, even ? idx_b : idx_a};
+        sort_pass<PER>(in, out, n, n_live, 8 * p, hist, digit_tot, s);
     }
 }
 
@@ -1116,18 +1114,17 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     return hipGetLastError();
 }
 
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
-                              uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_level_keys, dim3(grid_for(cmax)), dim3(256), 0, s, cells, prm, cmax, keys_a, idx_a);
-    // one 8-bit pass by level (stable, so pre-order within a level)
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint32_t* bfs2pre,
+                              uint32_t* hist, uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
+                              hipStream_t s) {
+    // one pass by level over the live cells (their count is on the device)
+    const LevelsIn in{cells};
+    const LevelsOut out{bfs2pre, pre2bfs, lvl_off, levels_for(dim)};
     switch (sort_per(cmax)) {
-        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
-        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
-        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, cmax, &prm->ncells, 1, hist, digit_tot, s); break;
+        case 16: sort_pass<16>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
+        case 8: sort_pass<8>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
+        default: sort_pass<4>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
     }
-    hipLaunchKernelGGL(k_level_inverse, dim3(grid_for(cmax)), dim3(256), 0, s, (const uint32_t*)idx_b, prm, cmax,
-                       pre2bfs, (const uint32_t*)digit_tot, levels_for(dim), lvl_off);
     return hipGetLastError();
 }
 

@@ -95,7 +95,7 @@ struct Layout {
     size_t off_params, off_keys_a, off_keys_b, off_idx_a, off_idx_b, off_bodies, off_range,
         off_nper, off_cstart, off_scan_part, off_hist, off_digit_tot, off_cells, off_mom,
         off_walk, off_mom_lvl, off_kids, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
-        off_diag_out, off_lvl_keys_a, off_lvl_keys_b, off_lvl_idx_a, off_lvl_idx_b, off_pre2bfs,
+        off_diag_out, off_lvl_idx_b, off_pre2bfs,
         off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_gorder, off_bcost, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
         off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, off_walkq, off_split, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
@@ -122,9 +122,10 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
                            int64_t cmax, DevParams* prm, hipStream_t s);
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint64_t* keys_a,
-                              uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, uint32_t* hist,
-                              uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
+// Level order (one radix pass by level over the live cells): bfs2pre and
+// pre2bfs, and lvl_off, where each level starts (levels 0..L and the end).
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint32_t* bfs2pre,
+                              uint32_t* hist, uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
                               hipStream_t s);
 hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
                          int64_t scan_tiles, int32_t* gbeg, int32_t* gcnt, int64_t gmax, DevParams* prm,
