@@ -536,10 +536,10 @@ __global__ void __launch_bounds__(256) k_quad_pack(const Moments* __restrict__ m
 // clustered bodies (57 groups per wave) single groups took 15.7 ms, runs of
 // 14, 16 or 64 14.9-15.3 ms, key order 14.7-15.2 ms.  Only the schedule
 // depends on the costs: each group's walk and sums are the same in any order, so stale
-// or missing costs cost time, never accuracy.  k_group_order sorts the
-// runs of one share per block (and zeroes that share's work counter), by
-// the mean cost of a run (gathered there from the costs of the groups'
-// middle bodies) in buckets of 1/16 of an octave (log2 with four fraction bits);
+// or missing costs cost time, never accuracy.  k_group_order gathers the
+// costs of one share's groups and sorts its runs, one share per block (and
+// zeroes that share's work counter), by the mean cost of a run in buckets
+// of 1/16 of an octave (log2 with four fraction bits);
 // places within a bucket are taken with LDS atomics, so they may differ
 // from run to run.
 constexpr int kOrderBuckets = 512;
@@ -553,18 +553,12 @@ __device__ __forceinline__ int cost_bucket(uint32_t v) {
     return b < kOrderBuckets ? b : kOrderBuckets - 1;
 }
 
-// Group g's cost: the list length its middle body had last time.
-__device__ __forceinline__ uint32_t group_cost(const uint32_t* __restrict__ bcost, const uint32_t* __restrict__ perm,
-                                               const int32_t* __restrict__ gbeg, const int32_t* __restrict__ gcnt,
-                                               uint32_t g) {
-    return bcost[perm[gbeg[g] + gcnt[g] / 2]];
-}
-
 __global__ void __launch_bounds__(kOrderThreads) k_group_order(const uint32_t* __restrict__ bcost,
                                                                const uint32_t* __restrict__ perm,
                                                                const int32_t* __restrict__ gbeg,
                                                                const int32_t* __restrict__ gcnt,
                                                                const DevParams* __restrict__ prm,
+                                                               uint32_t* __restrict__ gcost,
                                                                uint16_t* __restrict__ ckey,
                                                                uint32_t* __restrict__ order,
                                                                uint32_t* __restrict__ queue, uint32_t waves) {
@@ -583,12 +577,31 @@ __global__ void __launch_bounds__(kOrderThreads) k_group_order(const uint32_t* _
     const uint32_t run = max(1u, NG / (4u * W));
     const uint32_t nc = (hi - lo + run - 1) / run;
     if (t < kOrderBuckets) hist[t] = 0u;
+    // the share's group costs, four groups per thread with their loads
+    // issued together (three dependent loads each)
+    for (uint32_t g0 = lo + (uint32_t)t; g0 < hi; g0 += 4 * kOrderThreads) {
+        int32_t gb[4], gc[4];
+        uint32_t pb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t g = g0 + u * kOrderThreads;
+            gb[u] = g < hi ? gbeg[g] : 0;
+            gc[u] = g < hi ? gcnt[g] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pb[u] = g0 + u * kOrderThreads < hi ? perm[gb[u] + gc[u] / 2] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t g = g0 + u * kOrderThreads;
+            if (g < hi) gcost[g] = bcost[pb[u]];
+        }
+    }
     __syncthreads();
     // each run's bucket (kept at its first group's key) and the groups per bucket
     for (uint32_t c = (uint32_t)t; c < nc; c += kOrderThreads) {
         const uint32_t c0 = lo + c * run, c1 = min(hi, c0 + run);
         uint64_t sum = 0;
-        for (uint32_t g = c0; g < c1; ++g) sum += group_cost(bcost, perm, gbeg, gcnt, g);
+        for (uint32_t g = c0; g < c1; ++g) sum += gcost[g];
         const uint64_t mean = sum / (c1 - c0);
         const int b = cost_bucket(mean > 0xffffffffull ? 0xffffffffu : (uint32_t)mean);
         ckey[c0] = (uint16_t)b;
@@ -690,11 +703,12 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     const unsigned nb = (unsigned)want;
     int lpl_log2 = 0;                                   // lanes per leaf: next power of two, <= 64
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
-    // the group order: run keys after the places of order (2 gmax words
-    // in, as the layout reserves), then the counting sort of each share
+    // the group order: costs and run keys after the gmax places of order
+    // (as the layout reserves), then the counting sort of each share
+    uint32_t* gcost = order + gmax;
     uint16_t* ckey = reinterpret_cast<uint16_t*>(order + 2 * gmax);
     hipLaunchKernelGGL(k_group_order, dim3(kXcd), dim3(kOrderThreads), 0, s, (const uint32_t*)bcost, perm, gbeg,
-                       gcnt, prm, ckey, order, queue, (uint32_t)(nb * kWavesPerBlock));
+                       gcnt, prm, gcost, ckey, order, queue, (uint32_t)(nb * kWavesPerBlock));
     if (share && n <= coop_max_n(dim)) {
         // one block per group at a time, as many blocks as can be resident
         const int deal = coop_deal_level(n, dim);
