@@ -14,10 +14,16 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def _check_against_oracle(pos, mass, lc, theta, eps, G=1.0):
-    g = gpu_tree(pos, mass, lc, theta=theta, G=G, eps=eps)
+def _check_against_oracle(pos, mass, lc, theta, eps, G=1.0, split=None, t=None):
+    tc = None
+    if split is not None:
+        from paper_1211_2293_amd import treecode
+        tc = treecode.Treecode(pos.shape[1], leaf_cap=lc)
+        tc.set_split(split)
+    g = gpu_tree(pos, mass, lc, theta=theta, G=G, eps=eps, tc=tc)
     assert g["status"] == 0
-    t = oracle.Tree(pos.astype(np.float64), np.asarray(mass, np.float64), lc)
+    if t is None:
+        t = oracle.Tree(pos.astype(np.float64), np.asarray(mass, np.float64), lc)
     gb, gc = t.groups(64, 1024)
     np.testing.assert_array_equal(g["gbeg"], gb)
     np.testing.assert_array_equal(g["gcnt"], gc)
@@ -48,6 +54,19 @@ def test_plummer(theta):
 def test_disk_2d(theta):
     w = workloads.gaussian_disk(10000, seed=61)
     _check_against_oracle(w.pos, w.mass, 16, theta, 1e-2)
+
+
+@pytest.mark.parametrize("dim,lc", [(3, 1), (3, 3), (3, 32), (3, 64), (3, 100), (3, 256), (2, 1), (2, 64)])
+def test_leaf_caps_in_both_walk_kernels(dim, lc):
+    """Leaf sizes from 1 to the largest allowed: the walk copies the bodies of
+    unaccepted leaves with the next power of two of leaf_cap lanes per leaf
+    (at most 64), larger leaves in rounds of 64, and the list fills and
+    flushes at other points.  Shared walks (the default at this size) and
+    one wave per group (split mode 0) against the oracle."""
+    w = workloads.plummer_sphere(20000, seed=66) if dim == 3 else workloads.gaussian_disk(20000, seed=67)
+    t = oracle.Tree(w.pos.astype(np.float64), w.mass.astype(np.float64), lc)
+    for split in (1, 0):
+        _check_against_oracle(w.pos, w.mass, lc, 0.6, 1e-2, split=split, t=t)
 
 
 def test_clustered_pareto_masses():
