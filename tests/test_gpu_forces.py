@@ -44,6 +44,13 @@ def test_uniform_cube_fp64_state(theta):
     _check_against_oracle(w.pos, w.mass, w.leaf_cap, theta, w.eps)
 
 
+def test_disk_2d_fp64_state():
+    """FP64 positions and masses in 2D (the FP64 key path and the bodies
+    without an FP32 copy), as the FP64 cube does in 3D."""
+    pos = np.random.default_rng(68).normal(0.0, 1.0, (5000, 2))      # FP64, not FP32-rounded
+    _check_against_oracle(pos, np.full(5000, 1.0 / 5000), 8, 0.5, 1e-2)
+
+
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.7, 0.9])
 def test_plummer(theta):
     w = workloads.plummer_sphere(30000, seed=60)
