@@ -595,6 +595,12 @@ __global__ void __launch_bounds__(kTopoTile) k_topo_count(const uint64_t* __rest
     }
 }
 
+// The cells that start at body i (levels a_i..l*_i) at their pre-order
+// indices cstart[i] + (l - a_i): prefix, first body, level, parent and the
+// leaf mark.  Their ends (count and skip) come from k_topo_ends, one lane
+// per cell: a body that starts many cells would otherwise run their
+// searches one after another while the other lanes of its wave, most of
+// which start none, wait.
 template <int D>
 __global__ void __launch_bounds__(256) k_topo_emit(const uint64_t* __restrict__ keys, int64_t n,
                                                    const uint32_t* __restrict__ range,
@@ -617,34 +623,54 @@ __global__ void __launch_bounds__(256) k_topo_emit(const uint64_t* __restrict__ 
         for (int l = a; l <= lstar; ++l) {
             const int64_t k = (int64_t)base + (l - a);
             if (k >= cmax) break;
-            const int shift = D * (L - l);
-            const uint64_t prefix = l == 0 ? 0ull : key >> shift;
-            int64_t end = n;
-            if (l > 0) {
-                // first body after i whose level-l prefix differs: gallop, then bisect
-                int64_t lo = i, step = 1, hi = i + 1;
-                while (hi < n && (keys[hi] >> shift) == prefix) {
-                    lo = hi;
-                    step <<= 1;
-                    hi = i + step;
-                }
-                if (hi > n) hi = n;
-                while (hi - lo > 1) {
-                    const int64_t mid = lo + ((hi - lo) >> 1);
-                    if ((keys[mid] >> shift) == prefix) lo = mid; else hi = mid;
-                }
-                end = hi;
-            }
             Cell c;
-            c.prefix = prefix;
+            c.prefix = l == 0 ? 0ull : key >> (D * (L - l));
             c.begin = (int32_t)i;
-            c.count = (int32_t)(end - i);
-            c.skip = (int32_t)cstart[end];
+            c.count = 0;                           // k_topo_ends
+            c.skip = 0;
             c.parent = (l == 0) ? -1 : (l > a ? (int32_t)(k - 1) : -2);
             c.level = l;
             c.leaf_nch = (l == lstar) ? (int32_t)0x80000000u : 0;
             cells[k] = c;
         }
+    }
+}
+
+// Each cell's end: the first body after its first whose prefix at the
+// cell's level differs (a galloping search, then bisection over the sorted
+// keys; the root ends at n), giving its body count and its skip (the
+// pre-order index of the cell that starts there).
+template <int D>
+__global__ void __launch_bounds__(256) k_topo_ends(const uint64_t* __restrict__ keys, int64_t n,
+                                                   const uint32_t* __restrict__ cstart, Cell* __restrict__ cells,
+                                                   const DevParams* __restrict__ prm, int64_t cmax) {
+    constexpr int L = D == 3 ? 21 : 31;
+    int64_t C = prm->ncells;
+    if (C > cmax) C = cmax;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < C;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const Cell c = cells[k];
+        const int64_t i = c.begin;
+        const int l = c.level;
+        int64_t end = n;
+        if (l > 0) {
+            const int shift = D * (L - l);
+            const uint64_t prefix = c.prefix;
+            int64_t lo = i, step = 1, hi = i + 1;
+            while (hi < n && (keys[hi] >> shift) == prefix) {
+                lo = hi;
+                step <<= 1;
+                hi = i + step;
+            }
+            if (hi > n) hi = n;
+            while (hi - lo > 1) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if ((keys[mid] >> shift) == prefix) lo = mid; else hi = mid;
+            }
+            end = hi;
+        }
+        cells[k].count = (int32_t)(end - i);
+        cells[k].skip = (int32_t)cstart[end];
     }
 }
 
@@ -1110,7 +1136,10 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     scan_u32(nper, n, nullptr, cstart, scan_part, scan_tiles, s);
     if (dim == 3) hipLaunchKernelGGL(k_topo_emit<3>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
     else hipLaunchKernelGGL(k_topo_emit<2>, dim3(nb), dim3(256), 0, s, keys, n, (const uint32_t*)range, (const uint32_t*)cstart, cells, cmax, prm);
-    hipLaunchKernelGGL(k_topo_link, dim3(grid_for(cmax)), dim3(256), 0, s, cells, (const DevParams*)prm, cmax);
+    const unsigned nc = grid_for(cmax);
+    if (dim == 3) hipLaunchKernelGGL(k_topo_ends<3>, dim3(nc), dim3(256), 0, s, keys, n, (const uint32_t*)cstart, cells, (const DevParams*)prm, cmax);
+    else hipLaunchKernelGGL(k_topo_ends<2>, dim3(nc), dim3(256), 0, s, keys, n, (const uint32_t*)cstart, cells, (const DevParams*)prm, cmax);
+    hipLaunchKernelGGL(k_topo_link, dim3(nc), dim3(256), 0, s, cells, (const DevParams*)prm, cmax);
     return hipGetLastError();
 }
 
