@@ -67,6 +67,8 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_mom = take(sizeof(Moments) * (size_t)l.cmax);
     l.off_walk = take(sizeof(WalkCell) * (size_t)l.cmax);
     l.off_mom_lvl = take(sizeof(Moments) * (size_t)l.cmax);   // level-order copy for the moments pass
+    // ... and, earlier in each build, the packed input records (cmax > n)
+    static_assert(sizeof(Moments) >= sizeof(double4), "packed records must fit the level-order buffer");
     l.off_kids = take(8 * (size_t)l.cmax);
     l.off_acc = take(4 * (size_t)n * dim);
     l.off_pot = take(4 * (size_t)n);
@@ -286,7 +288,10 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     DevParams* prm = ctx->prm();
     {
         StageScope st_(ctx, TC_STAGE_BBOX, s);
-        TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part), prm, s));
+        // the packed records live in the moments pass's level-order buffer
+        // (at least 112 B per body, unused until the moments pass)
+        TC_HIP(ctx, launch_bbox(pos, mass, n, dim, f64, ctx->at<double>(l.off_bbox_part),
+                                ctx->at<char>(l.off_mom_lvl), prm, s));
     }
     {
         StageScope st_(ctx, TC_STAGE_KEYS, s);
@@ -302,7 +307,7 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     }
     {
         StageScope st_(ctx, TC_STAGE_GATHER, s);
-        TC_HIP(ctx, launch_gather(pos, mass, ctx->at<uint32_t>(l.off_idx_a), n, dim, f64,
+        TC_HIP(ctx, launch_gather(ctx->at<char>(l.off_mom_lvl), ctx->at<uint32_t>(l.off_idx_a), n, f64,
                                   ctx->at<Body>(l.off_bodies), ctx->at<float4>(l.off_bodies32), s));
     }
     {

@@ -32,22 +32,39 @@ __device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
 
 // ---------------------------------------------------------------- bbox ----
 
+// The input's bodies packed four values to a record, (x, y, z, m) with z = 0
+// in 2D, in the input's order: the gather then reads one record per body
+// instead of a position and a mass from two places.
+template <typename T> struct Packed;
+template <> struct Packed<float> { using type = float4; };
+template <> struct Packed<double> { using type = double4; };
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_bbox_part(const T* __restrict__ pos, const T* __restrict__ mass,
-                                                   int64_t n, double* __restrict__ part) {
+                                                   int64_t n, double* __restrict__ part,
+                                                   typename Packed<T>::type* __restrict__ packed) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        T c[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double v = (double)pos[i * D + a];
+            c[a] = pos[i * D + a];
+            const double v = (double)c[a];
             if (!isfinite(v)) { bad = 1; continue; }
             lo[a] = fmin(lo[a], v);
             hi[a] = fmax(hi[a], v);
         }
-        const double m = (double)mass[i];
+        const T mt = mass[i];
+        const double m = (double)mt;
         if (!(isfinite(m) && m > 0.0)) bad = 1;
+        typename Packed<T>::type r;
+        r.x = c[0];
+        r.y = c[1];
+        r.z = c[2];
+        r.w = mt;
+        packed[i] = r;
     }
     __shared__ double s_lo[3][256], s_hi[3][256];
     __shared__ int s_bad[256];
@@ -193,6 +210,13 @@ __global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t
 // Recording every round's per-wave digit counts and placing all keys after
 // one prefix pass (three barriers per tile instead of three per round) took
 // 18.4 us.  PER keys per thread, tiles of 256 PER keys (sort_per).
+// Placing each key straight at its output place writes about one key per
+// digit per round of 256, so a line of the output is written in many
+// pieces; large sorts (STAGE, from kSortStageMin keys) first rank the whole
+// tile into LDS in output order and then write each digit's run with
+// consecutive threads (16.7M keys: 2.36 to 1.64 ms for the eight passes,
+// 4M: 0.56 to 0.46; 1M keys, whose passes stay in the caches, 0.20 to 0.22,
+// so smaller sorts do not stage; the same at 1.5M).
 //
 // Where a pass's pairs come from and go to.  A plain pass reads keys and
 // values (nullable) and writes both at their places.  The level pass sorts
@@ -295,18 +319,28 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, 
 // total, which block 0 also stores in digit_tot.  For a few tiles (at most
 // kSortScanInScatter) this costs less than the scan's own launch.
 constexpr int64_t kSortScanInScatter = 128;
+// Sorts of at least kSortStageMin keys stage each tile in LDS (STAGE).
+constexpr int64_t kSortStageMin = (int64_t)1 << 21;
+constexpr int kSortStagePer = 16;
 
-template <int PER, bool SCAN, class In, class Out>
+template <int PER, bool SCAN, bool STAGE, class In, class Out>
 __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n, const uint32_t* __restrict__ n_live,
                                                       int shift, const uint32_t* __restrict__ hist,
                                                       uint32_t* __restrict__ digit_tot, int64_t tiles) {
     if (n_live && (int64_t)*n_live < n) n = *n_live;
-    __shared__ uint32_t s_base[256];
+    constexpr int kTile = 256 * PER;
+    constexpr int kStage = STAGE ? kTile : 1;
+    __shared__ uint32_t s_base[256];   // where the tile's keys of each digit start in the output
+    __shared__ uint32_t s_pos[256];    // running place of each digit (staged: in the tile, else in the output)
+    __shared__ uint32_t s_lstart[256]; // staged: where each digit's keys start in the tile
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
+    __shared__ uint64_t s_key[kStage];
+    __shared__ uint32_t s_val[kStage];
     const int t = threadIdx.x, w = t >> 6, lane = wave_lane();
     const int64_t tile = blockIdx.x;
+    uint32_t own = 0;   // this tile's count of digit t (staged only)
     if (SCAN) {
         const uint32_t* row = hist + (int64_t)t * tiles;
         uint32_t pre = 0, tot = 0;
@@ -317,18 +351,28 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
             if (k < tile) pre += v;
         }
         if (tile == 0) digit_tot[t] = tot;
+        if (STAGE) own = row[tile];
         s_base[t] = block_exscan_u32(tot, s_w, &s_tot) + pre;
     } else {
-        const uint32_t dbase = block_exscan_u32(digit_tot[t], s_w, &s_tot);
-        s_base[t] = dbase + hist[(int64_t)t * tiles + tile];
+        const uint32_t tot = digit_tot[t];
+        const uint32_t here = hist[(int64_t)t * tiles + tile];
+        if (STAGE) own = (tile + 1 < tiles ? hist[(int64_t)t * tiles + tile + 1] : tot) - here;
+        s_base[t] = block_exscan_u32(tot, s_w, &s_tot) + here;
     }
     if (tile == 0) out.starts(t, s_base[t]);
+    if (STAGE) {
+        const uint32_t l = block_exscan_u32(own, s_w, &s_tot);
+        s_lstart[t] = l;
+        s_pos[t] = l;
+    } else {
+        s_pos[t] = s_base[t];
+    }
     for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
     uint64_t kr[PER];
     uint32_t vr[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const int64_t i = tile * (256 * PER) + r * 256 + t;
+        const int64_t i = tile * kTile + r * 256 + t;
         kr[r] = i < n ? in.key(i) : 0ull;
         vr[r] = i < n ? in.val(i) : 0u;
     }
@@ -336,7 +380,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const bool valid = tile * (256 * PER) + r * 256 + t < n;
+        const bool valid = tile * kTile + r * 256 + t < n;
         const uint64_t k = kr[r];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
@@ -350,31 +394,51 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
         if (valid && before == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t p = s_base[d] + (uint32_t)__popcll(before);
+            uint32_t p = s_pos[d] + (uint32_t)__popcll(before);
             for (int a = 0; a < w; ++a) p += s_wcnt[a][d];
-            out.put(p, k, vr[r]);
+            if (STAGE) {
+                s_key[p] = k;
+                s_val[p] = vr[r];
+            } else {
+                out.put(p, k, vr[r]);
+            }
         }
         __syncthreads();
-        s_base[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
+        s_pos[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
         for (int a = 0; a < 4; ++a) s_wcnt[a][t] = 0;
         __syncthreads();
+    }
+    if (STAGE) {
+        // The tile's keys now sit in LDS in output order, digit by digit:
+        // consecutive threads write consecutive places of a digit's run.
+        const int64_t left = n - tile * kTile;
+        const int live = left < kTile ? (int)left : kTile;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int l = r * 256 + t;
+            if (l < live) {
+                const uint64_t k = s_key[l];
+                const uint32_t d = (uint32_t)(k >> shift) & 255u;
+                out.put(s_base[d] + (uint32_t)l - s_lstart[d], k, s_val[l]);
+            }
+        }
     }
 }
 
 // -------------------------------------------------------------- gather ----
 
-template <typename T, int D>
-__global__ void __launch_bounds__(256) k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(const typename Packed<T>::type* __restrict__ packed,
                                                 const uint32_t* __restrict__ perm, int64_t n,
                                                 Body* __restrict__ bodies, float4* __restrict__ bodies32) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t o = perm[i];
+        const typename Packed<T>::type r = packed[perm[i]];
         Body b;
-        b.x = (double)pos[o * D + 0];
-        b.y = (double)pos[o * D + 1];
-        b.z = D == 3 ? (double)pos[o * D + 2] : 0.0;
-        b.m = (double)mass[o];
+        b.x = (double)r.x;
+        b.y = (double)r.y;
+        b.z = (double)r.z;
+        b.m = (double)r.w;
         bodies[i] = b;
         // FP32 inputs also get a compact copy (exactly the input values)
         if (bodies32) bodies32[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.m);
@@ -1042,14 +1106,14 @@ __global__ void __launch_bounds__(256) k_export(const Cell* __restrict__ cells, 
 // ------------------------------------------------------------ launchers ----
 
 hipError_t launch_bbox(const void* pos, const void* mass, int64_t n, int dim, int f64,
-                       double* part, DevParams* prm, hipStream_t s) {
+                       double* part, void* packed, DevParams* prm, hipStream_t s) {
     const unsigned nb = grid_for(n, 1024);
     if (f64) {
-        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part);
-        else hipLaunchKernelGGL((k_bbox_part<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part);
+        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part, (double4*)packed);
+        else hipLaunchKernelGGL((k_bbox_part<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, n, part, (double4*)packed);
     } else {
-        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part);
-        else hipLaunchKernelGGL((k_bbox_part<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part);
+        if (dim == 3) hipLaunchKernelGGL((k_bbox_part<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part, (float4*)packed);
+        else hipLaunchKernelGGL((k_bbox_part<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, n, part, (float4*)packed);
     }
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, (int)nb, dim, prm);
     return hipGetLastError();
@@ -1069,54 +1133,53 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
 }
 
 // One pass of the reduce-then-scan sort (2 or 3 launches).
-template <int PER, class In, class Out>
+template <int PER, bool STAGE, class In, class Out>
 static void sort_pass(In in, Out out, int64_t n, const uint32_t* n_live, int shift, uint32_t* hist,
                       uint32_t* digit_tot, hipStream_t s) {
     const int64_t tiles = (n + 256 * PER - 1) / (256 * PER);
     hipLaunchKernelGGL((k_sort_hist<PER, In>), dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live, shift, hist,
                        tiles);
     if (tiles <= kSortScanInScatter) {
-        hipLaunchKernelGGL((k_sort_scatter<PER, true, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
+        hipLaunchKernelGGL((k_sort_scatter<PER, true, STAGE, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
                            n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
         return;
     }
     hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
-    hipLaunchKernelGGL((k_sort_scatter<PER, false, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
+    hipLaunchKernelGGL((k_sort_scatter<PER, false, STAGE, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
                        n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
 }
 
-template <int PER>
+template <int PER, bool STAGE>
 static void sort_passes(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b, int64_t n,
                         const uint32_t* n_live, int passes, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
     for (int p = 0; p < passes; ++p) {
         const bool even = (p % 2) == 0;
         const PairsIn in{even ? keys_a : keys_b, even ? idx_a : idx_b};
         const PairsOut out{even ? keys_b : keys_a, even ? idx_b : idx_a};
-        sort_pass<PER>(in, out, n, n_live, 8 * p, hist, digit_tot, s);
+        sort_pass<PER, STAGE>(in, out, n, n_live, 8 * p, hist, digit_tot, s);
     }
 }
 
 hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
                        int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
     const int passes = (key_bits + 7) / 8;    // even for 62/63-bit keys: result lands in _a
+    if (n >= kSortStageMin) {
+        sort_passes<kSortStagePer, true>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s);
+        return hipGetLastError();
+    }
     switch (sort_per(n)) {
-        case 16: sort_passes<16>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
-        case 8: sort_passes<8>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
-        default: sort_passes<4>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
+        case 16: sort_passes<16, false>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
+        case 8: sort_passes<8, false>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
+        default: sort_passes<4, false>(keys_a, idx_a, keys_b, idx_b, n, nullptr, passes, hist, digit_tot, s); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
-                         int dim, int f64, Body* bodies, float4* bodies32, hipStream_t s) {
+hipError_t launch_gather(const void* packed, const uint32_t* perm, int64_t n, int f64, Body* bodies,
+                         float4* bodies32, hipStream_t s) {
     const unsigned nb = grid_for(n);
-    if (f64) {
-        if (dim == 3) hipLaunchKernelGGL((k_gather<double, 3>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies, (float4*)nullptr);
-        else hipLaunchKernelGGL((k_gather<double, 2>), dim3(nb), dim3(256), 0, s, (const double*)pos, (const double*)mass, perm, n, bodies, (float4*)nullptr);
-    } else {
-        if (dim == 3) hipLaunchKernelGGL((k_gather<float, 3>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies, bodies32);
-        else hipLaunchKernelGGL((k_gather<float, 2>), dim3(nb), dim3(256), 0, s, (const float*)pos, (const float*)mass, perm, n, bodies, bodies32);
-    }
+    if (f64) hipLaunchKernelGGL(k_gather<double>, dim3(nb), dim3(256), 0, s, (const double4*)packed, perm, n, bodies, (float4*)nullptr);
+    else hipLaunchKernelGGL(k_gather<float>, dim3(nb), dim3(256), 0, s, (const float4*)packed, perm, n, bodies, bodies32);
     return hipGetLastError();
 }
 
@@ -1150,9 +1213,9 @@ hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const De
     const LevelsIn in{cells};
     const LevelsOut out{bfs2pre, pre2bfs, lvl_off, levels_for(dim)};
     switch (sort_per(cmax)) {
-        case 16: sort_pass<16>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
-        case 8: sort_pass<8>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
-        default: sort_pass<4>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
+        case 16: sort_pass<16, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
+        case 8: sort_pass<8, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
+        default: sort_pass<4, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
     }
     return hipGetLastError();
 }

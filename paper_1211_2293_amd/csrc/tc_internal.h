@@ -107,8 +107,10 @@ Layout make_layout(int64_t n, int dim, int leaf_cap);
 
 // ---- launchers (all enqueue on `s`, return hipSuccess or the launch error)
 // build.hip
+// Also packs the input into (x, y, z, m) records (float4, or double4 for FP64
+// input; n of them at `packed`) for launch_gather.
 hipError_t launch_bbox(const void* pos, const void* mass, int64_t n, int dim, int f64,
-                       double* part, DevParams* prm, hipStream_t s);
+                       double* part, void* packed, DevParams* prm, hipStream_t s);
 hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevParams* prm,
                        uint64_t* keys, uint32_t* idx, hipStream_t s);
 // LSD radix sort (stable) of the low key_bits bits; idx_a / idx_b may both be
@@ -116,8 +118,8 @@ hipError_t launch_keys(const void* pos, int64_t n, int dim, int f64, const DevPa
 // hist holds 256 x sort_tiles_max(n) counts.
 hipError_t launch_sort(uint64_t* keys_a, uint32_t* idx_a, uint64_t* keys_b, uint32_t* idx_b,
                        int64_t n, int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t s);
-hipError_t launch_gather(const void* pos, const void* mass, const uint32_t* perm, int64_t n,
-                         int dim, int f64, Body* bodies, float4* bodies32, hipStream_t s);
+hipError_t launch_gather(const void* packed, const uint32_t* perm, int64_t n, int f64, Body* bodies,
+                         float4* bodies32, hipStream_t s);
 hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_cap,
                            uint32_t* range, uint32_t* nper, uint32_t* cstart,
                            uint32_t* scan_part, int64_t scan_tiles, Cell* cells,
