@@ -258,16 +258,25 @@ struct LevelsOut {
     }
 };
 
+// Tiles of `tile` keys that hold the first n keys (at least one, so that
+// the first tile always writes the digit starts).
+__device__ __forceinline__ int64_t live_tiles(int64_t n, int64_t tile) {
+    return n > 0 ? (n + tile - 1) / tile : 1;
+}
+
 template <int PER, class In>
-// n_live (nullable, device): sort only the first min(n, *n_live) keys.
+// n_live (nullable, device): sort only the first min(n, *n_live) keys; the
+// tiles past them (a pass over the cells is sized for the most cells a tree
+// can have) count, scan and scatter nothing.
 __global__ void __launch_bounds__(256) k_sort_hist(In in, int64_t n, const uint32_t* __restrict__ n_live, int shift,
                                                    uint32_t* __restrict__ hist, int64_t tiles) {
     if (n_live && (int64_t)*n_live < n) n = *n_live;
+    const int64_t tile = blockIdx.x;
+    if (tile >= live_tiles(n, 256 * PER)) return;   // nothing reads the counts of later tiles
     __shared__ uint32_t cnt[4][256];
     const int t = threadIdx.x, w = t >> 6;
     for (int a = 0; a < 4; ++a) cnt[a][t] = 0;
     __syncthreads();
-    const int64_t tile = blockIdx.x;
     const int64_t base = tile * (256 * PER);
 #pragma unroll 4
     for (int j = 0; j < PER; ++j) {
@@ -297,17 +306,21 @@ __device__ __forceinline__ uint32_t block_exscan_u32(uint32_t v, uint32_t* s_w, 
     return wbase + x - v;
 }
 
-__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, int64_t tiles,
+template <int PER>
+__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ hist, int64_t tiles, int64_t n,
+                                                   const uint32_t* __restrict__ n_live,
                                                    uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
+    if (n_live && (int64_t)*n_live < n) n = *n_live;
+    const int64_t tl = live_tiles(n, 256 * PER);
     uint32_t* h = hist + (int64_t)blockIdx.x * tiles;
     uint32_t carry = 0;
-    for (int64_t c = 0; c < tiles; c += 256) {
+    for (int64_t c = 0; c < tl; c += 256) {
         const int64_t i = c + threadIdx.x;
-        const uint32_t v = i < tiles ? h[i] : 0u;
+        const uint32_t v = i < tl ? h[i] : 0u;
         const uint32_t ex = block_exscan_u32(v, s_w, &s_tot);
-        if (i < tiles) h[i] = carry + ex;
+        if (i < tl) h[i] = carry + ex;
         carry += s_tot;
         __syncthreads();
     }
@@ -330,6 +343,8 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
     if (n_live && (int64_t)*n_live < n) n = *n_live;
     constexpr int kTile = 256 * PER;
     constexpr int kStage = STAGE ? kTile : 1;
+    const int64_t tl = live_tiles(n, kTile);
+    if ((int64_t)blockIdx.x >= tl) return;
     __shared__ uint32_t s_base[256];   // where the tile's keys of each digit start in the output
     __shared__ uint32_t s_pos[256];    // running place of each digit (staged: in the tile, else in the output)
     __shared__ uint32_t s_lstart[256]; // staged: where each digit's keys start in the tile
@@ -345,7 +360,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
         const uint32_t* row = hist + (int64_t)t * tiles;
         uint32_t pre = 0, tot = 0;
 #pragma unroll 8
-        for (int64_t k = 0; k < tiles; ++k) {
+        for (int64_t k = 0; k < tl; ++k) {
             const uint32_t v = row[k];
             tot += v;
             if (k < tile) pre += v;
@@ -356,7 +371,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
     } else {
         const uint32_t tot = digit_tot[t];
         const uint32_t here = hist[(int64_t)t * tiles + tile];
-        if (STAGE) own = (tile + 1 < tiles ? hist[(int64_t)t * tiles + tile + 1] : tot) - here;
+        if (STAGE) own = (tile + 1 < tl ? hist[(int64_t)t * tiles + tile + 1] : tot) - here;
         s_base[t] = block_exscan_u32(tot, s_w, &s_tot) + here;
     }
     if (tile == 0) out.starts(t, s_base[t]);
@@ -475,23 +490,49 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = s_tot;
 }
 
-__global__ void __launch_bounds__(256) k_scan_part(uint32_t* __restrict__ part, int64_t tiles,
-                                                   uint32_t* __restrict__ out, int64_t n,
-                                                   const uint32_t* __restrict__ n_live) {
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_tot;
+// The tiles' sums in one block of 1024 threads, four consecutive tiles per
+// thread, over the tiles that hold live values only.
+__global__ void __launch_bounds__(1024) k_scan_part(uint32_t* __restrict__ part, int64_t tiles,
+                                                    uint32_t* __restrict__ out, int64_t n,
+                                                    const uint32_t* __restrict__ n_live) {
+    __shared__ uint32_t s_w[16];
+    const int64_t m = live_count(n, n_live);
+    int64_t tl = (m + kScanTile - 1) / kScanTile;
+    if (tl > tiles) tl = tiles;
+    const int t = threadIdx.x, lane = wave_lane(), w = t >> 6;
     uint32_t carry = 0;
-    for (int64_t c = 0; c < tiles; c += 256) {
-        const int64_t i = c + threadIdx.x;
-        const uint32_t v = i < tiles ? part[i] : 0u;
-        const uint32_t ex = block_exscan_u32(v, s_w, &s_tot);
-        if (i < tiles) part[i] = carry + ex;
-        carry += s_tot;
+    for (int64_t c = 0; c < tl; c += 4 * 1024) {
+        const int64_t i = c + 4 * t;
+        const uint32_t v0 = i < tl ? part[i] : 0u, v1 = i + 1 < tl ? part[i + 1] : 0u;
+        const uint32_t v2 = i + 2 < tl ? part[i + 2] : 0u, v3 = i + 3 < tl ? part[i + 3] : 0u;
+        const uint32_t own = v0 + v1 + v2 + v3;
+        uint32_t x = own;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) s_w[w] = x;
         __syncthreads();
+        uint32_t wbase = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) wbase += s_w[k];
+            tot += s_w[k];
+        }
+        uint32_t e = carry + wbase + x - own;
+        if (i < tl) part[i] = e;
+        e += v0;
+        if (i + 1 < tl) part[i + 1] = e;
+        e += v1;
+        if (i + 2 < tl) part[i + 2] = e;
+        e += v2;
+        if (i + 3 < tl) part[i + 3] = e;
+        carry += tot;
+        __syncthreads();    // s_w is rewritten by the next round
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         out[n] = carry;
-        out[live_count(n, n_live)] = carry;
+        out[m] = carry;
     }
 }
 
@@ -651,7 +692,7 @@ static void scan_u32(const uint32_t* in, int64_t n, const uint32_t* n_live, uint
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live, part);
-    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, s, part, tiles, out, n, n_live);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, part, tiles, out, n, n_live);
     if ((reinterpret_cast<uintptr_t>(in) & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0)
         hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)tiles), dim3(256), 0, s, in, n, n_live,
                            (const uint32_t*)part, out);
@@ -1192,7 +1233,7 @@ static void sort_pass(In in, Out out, int64_t n, const uint32_t* n_live, int shi
                            n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
         return;
     }
-    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tiles, digit_tot);
+    hipLaunchKernelGGL(k_sort_scan<PER>, dim3(256), dim3(256), 0, s, hist, tiles, n, n_live, digit_tot);
     hipLaunchKernelGGL((k_sort_scatter<PER, false, STAGE, In, Out>), dim3((unsigned)tiles), dim3(256), 0, s, in, out, n,
                        n_live, shift, (const uint32_t*)hist, digit_tot, tiles);
 }
