@@ -52,6 +52,13 @@ CASES = {
                                workloads.plummer_sphere(131073, seed=50).mass, 16),
     "disk2d-131073": lambda: (workloads.gaussian_disk(131073, seed=51).pos,
                               workloads.gaussian_disk(131073, seed=51).mass, 16),
+    # from 2^21 keys the radix passes rank each 4096-key tile in LDS before
+    # writing it: a ragged last tile (2,848 keys) with the clumped, skewed
+    # digits of the clustered mixture, and one key past the threshold in 2D
+    "clustered-2100000": lambda: (workloads.clustered(2_100_000, seed=52).pos,
+                                  workloads.clustered(2_100_000, seed=52).mass, 16),
+    "disk2d-2097153": lambda: (workloads.gaussian_disk(2_097_153, seed=53).pos,
+                               workloads.gaussian_disk(2_097_153, seed=53).mass, 16),
 }
 
 
