@@ -133,7 +133,7 @@ def test_deterministic():
     np.testing.assert_array_equal(g1["pot"], g2["pot"])
 
 
-@pytest.mark.parametrize("wl", ["plummer", "disk"])
+@pytest.mark.parametrize("wl", ["plummer", "disk", "plummer-200k"])
 def test_schedule_does_not_change_results(wl):
     """The persistent waves take the groups in an order set by the previous
     evaluation's per-body list lengths; a group's walk and sums do not depend
@@ -142,7 +142,9 @@ def test_schedule_does_not_change_results(wl):
     from a permuted copy of it."""
     from paper_1211_2293_amd import treecode
     from tests.gpu_util import to_dev
-    w = workloads.plummer_sphere(60000, seed=79) if wl == "plummer" else workloads.gaussian_disk(60000, seed=80)
+    # (60,000 bodies: the shared walks; 200,000: one wave per group)
+    w = (workloads.plummer_sphere(60000, seed=79) if wl == "plummer" else
+         workloads.gaussian_disk(60000, seed=80) if wl == "disk" else workloads.plummer_sphere(200000, seed=82))
     tc = treecode.Treecode(w.dim, leaf_cap=16)
 
     def run(pos, mass):
