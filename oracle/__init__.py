@@ -64,6 +64,8 @@ def lib():
         L.orc_groups.restype = i64
         L.orc_walk_counts_ranges.argtypes = [P, dbl, i64, P, P, P, P]
         L.orc_walk_counts_ranges.restype = None
+        L.orc_walk_tests_ranges.argtypes = [P, dbl, i64, P, P, P]
+        L.orc_walk_tests_ranges.restype = None
         L.orc_tree_forces_ranges.argtypes = [P, dbl, dbl, dbl, i64, P, P, i32, P, P]
         L.orc_tree_forces_ranges.restype = None
         L.orc_residuals.argtypes = [P, dbl, dbl, i64, P, i64, P, P, P, P, P]
@@ -232,6 +234,15 @@ class Tree:
         lib().orc_walk_counts_ranges(self._h, float(theta), len(gbeg), _p(gbeg), _p(gcnt),
                                      _p(m2p), _p(p2p))
         return m2p, p2p
+
+    def walk_tests_groups(self, theta, gbeg, gcnt):
+        """Cells whose opening test runs in each group's walk (the root and
+        every child of an opened cell): a measure of the walk's work."""
+        gbeg = np.ascontiguousarray(gbeg, np.int64)
+        gcnt = np.ascontiguousarray(gcnt, np.int64)
+        tests = np.zeros(len(gbeg), np.int64)
+        lib().orc_walk_tests_ranges(self._h, float(theta), len(gbeg), _p(gbeg), _p(gcnt), _p(tests))
+        return tests
 
     def forces_groups(self, theta, gbeg, gcnt, G=1.0, eps=1e-3, acc=None, pot=None, order=1):
         """Treecode forces of the bodies of the given groups, original

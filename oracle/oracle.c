@@ -432,6 +432,7 @@ typedef struct {
     int32_t *items;       /* terminal cells in walk order; -1-c marks a P2P leaf c */
     int64_t nitems, cap;
     int64_t m2p, p2p;     /* accepted cells, bodies from opened leaves */
+    int64_t tests;        /* cells whose opening test ran */
 } walk_out;
 
 static void push_item(walk_out *w, int32_t v)
@@ -450,6 +451,7 @@ static void push_item(walk_out *w, int32_t v)
 static void walk_rec(const orc_tree *t, int64_t c, const double *rcrit2, const double *lo,
                      const double *hi, walk_out *w)
 {
+    w->tests += 1;
     if (accepts(t, c, rcrit2, lo, hi)) {
         w->m2p += 1;
         push_item(w, (int32_t)c);
@@ -529,6 +531,23 @@ void orc_walk_counts_ranges(const orc_tree *t, double theta, int64_t ng, const i
         walk_range(t, rc, gbeg[g], gbeg[g] + gcnt[g], &w);
         m2p[g] = w.m2p;
         p2p[g] = w.p2p;
+    }
+    free(rc);
+}
+
+/* Cells whose opening test ran in the walk of each explicit group (a
+ * measurement of the walk's work, not part of the method): the root and
+ * every child of an opened cell. */
+void orc_walk_tests_ranges(const orc_tree *t, double theta, int64_t ng, const int64_t *gbeg,
+                           const int64_t *gcnt, int64_t *tests)
+{
+    double *rc = malloc(t->ncells * sizeof(double));
+    orc_mac_radii(t, theta, rc);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t g = 0; g < ng; ++g) {
+        walk_out w = {0};
+        walk_range(t, rc, gbeg[g], gbeg[g] + gcnt[g], &w);
+        tests[g] = w.tests;
     }
     free(rc);
 }

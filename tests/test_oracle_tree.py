@@ -246,6 +246,29 @@ def test_walk_matches_brute_force_and_partitions(case, theta):
         assert p2p[g] == sum(c["count"][-1 - it] for it in items if it < 0)
 
 
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.9])
+def test_walk_tests_are_the_terminal_items_and_their_ancestors(case, theta):
+    """Cells tested by a group's walk (a work measure): every terminal item
+    (accepted cell or opened leaf) and every cell opened on the way to it,
+    which are exactly the items' ancestors; at theta = 0 nothing is accepted,
+    so every group tests every cell."""
+    _, _, _, t = case
+    c = t.cells()
+    gb, gc = t.groups(64, 1024)
+    tests = t.walk_tests_groups(theta, gb, gc)
+    if theta == 0.0:
+        assert np.all(tests == t.ncells)
+    for g in range(len(gb)):
+        items = t.walk_items_range(theta, gb[g], gb[g] + gc[g])
+        anc = set()
+        for it in items:
+            k = int(c["parent"][it if it >= 0 else -1 - it])
+            while k >= 0 and k not in anc:
+                anc.add(k)
+                k = int(c["parent"][k])
+        assert tests[g] == len(items) + len(anc)
+
+
 @pytest.mark.parametrize("gs", [64, 1, 7])
 def test_theta_zero_reproduces_direct_sum(case, gs):
     pos, mass, _, t = case
