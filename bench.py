@@ -637,6 +637,13 @@ def run(args, w, theta, dev, treecode, workloads, torch):
     evals_per_s = 1e3 / ms_per_step
     log(f"{ms_per_step:.3f} ms/step, force kernel {kern_avg_ms:.3f} ms/launch ({launches} launches), "
         f"{inter / w.n:.0f} interactions/body, {achieved_tflops:.1f} TFLOP/s in the force kernel")
+    try:                                            # cells whose opening test ran in the walk
+        tested = int(tc.tests().sum().item())
+    except treecode.TcError:                        # learned or split walks keep no count
+        tested = None
+    if tested is not None:
+        log(f"walk: {tested} cells tested per evaluation, {tested / (kern_avg_ms * 1e-3):.3e} per second of the "
+            f"force kernel")
     learned_stats = None
     if args.closure is not None:
         kept, fell = (v.cpu().numpy() for v in tc.learned_counts())
@@ -708,6 +715,12 @@ def run(args, w, theta, dev, treecode, workloads, torch):
             "traffic": traffic_from_profile(w, theta),
             "kernel_ms": kern_avg_ms,
             "flops_per_interaction": FLOPS_PER_INTERACTION[w.dim],
+            "walk": None if tested is None else {
+                "cells_tested": tested,
+                "cells_tested_per_s": tested / (kern_avg_ms * 1e-3),
+                "note": "cells whose opening test ran (the root and every child of an opened cell) in one "
+                        "force evaluation, over all groups, and their rate over the force kernel's time; the "
+                        "walk shares the kernel with the force loop"},
             "build": build_roof,
         },
     }

@@ -133,7 +133,7 @@ int tc_leapfrog(tc_ctx *ctx, double dt, void *pos, void *vel);
  * until the process ends) instead of the caller's.  Nothing is allocated:
  * no device or pinned memory, no events (force and stage timing skip this
  * call).  TC_EWORKSPACE when tc_workspace_bytes(n, dim, leaf_cap) exceeds
- * the scratch (47,854 bodies in 3D with leaf_cap 16).  Afterwards the
+ * the scratch (47,786 bodies in 3D with leaf_cap 16).  Afterwards the
  * context works on that scratch as if tc_set_workspace had been called with
  * it (tc_leapfrog, tc_diag, the accessors), until the next
  * tc_set_workspace.  Every context on one GPU shares its scratch, which
@@ -402,6 +402,16 @@ int tc_get_groups(tc_ctx *ctx, int32_t *begin, int32_t *count);
  * of tc_num_groups() entries): accepted cells and bodies of opened leaves
  * (the group's own bodies included).  Synchronises.  Requires tc_forces. */
 int tc_get_counts(tc_ctx *ctx, int64_t *m2p, int64_t *p2p);
+
+/* Per-group number of cells whose opening test ran in the last tc_forces
+ * walk (device int64 [tc_num_groups()]): the root and every child of an
+ * opened cell, a measure of the walk's work (§3.1's traversal; not part of
+ * the method's results).  TC_EINVAL for a NULL buffer; TC_ESTATE unless
+ * the last force evaluation was a tc_forces (or tc_leapfrog) walk by one
+ * wave or by waves sharing a group (not split walks, tc_set_split(ctx, 2),
+ * whose tasks repeat the top of the walk, nor the learned, per-body-list or
+ * FMM evaluations).  Synchronises like tc_get_counts. */
+int tc_get_tests(tc_ctx *ctx, int64_t *tests);
 
 /* Time the force kernel with HIP events on the context's stream: when on,
  * every tc_forces accumulates the kernel's duration. */

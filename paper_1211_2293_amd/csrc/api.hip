@@ -104,6 +104,7 @@ Layout make_layout(int64_t n, int dim, int leaf_cap) {
     l.off_rcp2 = take(8 * (size_t)l.cmax);
     l.off_m2p = take(8 * (size_t)l.gmax);
     l.off_p2p = take(8 * (size_t)l.gmax);
+    l.off_tests = take(8 * (size_t)l.gmax);
     l.off_nlearn = take(8 * (size_t)l.gmax);
     l.off_nfall = take(8 * (size_t)l.gmax);
     l.off_pb_cnt = take(4 * (size_t)n);
@@ -168,6 +169,7 @@ struct tc_ctx {
     bool plain_acc = false;    // uncompensated running sums (precision study)
     int mp_order = 1;          // 1: monopole cells, 2: with quadrupole terms (3D)
     int split = 1;             // 0: one wave per group; 1: shared walks (coop); 2: split walks up to split_max_n
+    bool tests_kept = false;   // the last force evaluation counted each group's tested cells
     bool pb_counted = false;   // per-body list lengths of the current walk are known
     int64_t pb_total = 0;
     // the fast multipole plan (tc_fmm_plan) in the caller's buffer
@@ -424,6 +426,7 @@ int do_forces_learned(tc_ctx* ctx, double G, double eps, double tau) {
     ctx->G = G;
     ctx->eps = eps;
     ctx->state = kForced;
+    ctx->tests_kept = false;
     return TC_OK;
 }
 
@@ -454,8 +457,8 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
                                             ctx->at<int32_t>(l.off_gcnt), l.gmax, ctx->n, ctx->dim, ctx->leaf_cap,
                                             (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float4>(l.off_split),
                                             ctx->at<float>(l.off_acc), ctx->at<float>(l.off_pot),
-                                            ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p), ctx->plain_acc,
-                                            ctx->stream));
+                                            ctx->at<int64_t>(l.off_m2p), ctx->at<int64_t>(l.off_p2p),
+                                            ctx->at<int64_t>(l.off_tests), ctx->plain_acc, ctx->stream));
     } else {
         TC_HIP(ctx, launch_walk_force(ctx->at<WalkCell>(l.off_walk), walkq, ctx->at<Body>(l.off_bodies),
                                       ctx->dtype == TC_F32 ? ctx->at<float4>(l.off_bodies32) : nullptr,
@@ -465,7 +468,8 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
                                       ctx->dim, ctx->leaf_cap,
                                       (float)G, (float)(eps * eps), ctx->prm(), ctx->at<float>(l.off_acc),
                                       ctx->at<float>(l.off_pot), ctx->at<int64_t>(l.off_m2p),
-                                      ctx->at<int64_t>(l.off_p2p), ctx->plain_acc, ctx->split != 0,
+                                      ctx->at<int64_t>(l.off_p2p), ctx->at<int64_t>(l.off_tests), ctx->plain_acc,
+                                      ctx->split != 0,
                                       ctx->at<uint32_t>(l.off_lvl_off), ctx->stream));
     }
     if (ctx->timing) {
@@ -476,6 +480,7 @@ int do_forces(tc_ctx* ctx, double G, double eps) {
     ctx->G = G;
     ctx->eps = eps;
     ctx->state = kForced;
+    ctx->tests_kept = !(ctx->split == 2 && ctx->n <= split_max_n(ctx->dim));
     return TC_OK;
 }
 
@@ -762,6 +767,7 @@ int tc_fmm_forces(tc_ctx* ctx, double G, double eps, void* acc, void* pot) {
     ctx->G = G;
     ctx->eps = eps;
     ctx->state = kForced;
+    ctx->tests_kept = false;
     if (acc)
         TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * 3, hipMemcpyDeviceToDevice, s));
     if (pot)
@@ -923,6 +929,7 @@ int tc_lists_forces(tc_ctx* ctx, double G, double eps, uint32_t* lists, int64_t 
     ctx->G = G;
     ctx->eps = eps;
     ctx->state = kForced;
+    ctx->tests_kept = false;
     if (acc)
         TC_HIP(ctx, hipMemcpyAsync(acc, ctx->at<float>(l.off_acc), 4 * (size_t)ctx->n * ctx->dim,
                                    hipMemcpyDeviceToDevice, s));
@@ -1295,6 +1302,17 @@ int tc_get_counts(tc_ctx* ctx, int64_t* m2p, int64_t* p2p) {
     if (p2p)
         TC_HIP(ctx, hipMemcpyAsync(p2p, ctx->at<int64_t>(l.off_p2p), 8 * (size_t)ng,
                                    hipMemcpyDeviceToDevice, ctx->stream));
+    return TC_OK;
+}
+
+int tc_get_tests(tc_ctx* ctx, int64_t* tests) {
+    if (!ctx || !tests) return TC_EINVAL;
+    if (ctx->state < kForced || !ctx->tests_kept) return TC_ESTATE;
+    int64_t ng = 0;
+    int rc = tc_num_groups(ctx, &ng);
+    if (rc != TC_OK) return rc;
+    TC_HIP(ctx, hipMemcpyAsync(tests, ctx->at<int64_t>(ctx->lay.off_tests), 8 * (size_t)ng,
+                               hipMemcpyDeviceToDevice, ctx->stream));
     return TC_OK;
 }
 

@@ -52,7 +52,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                                            double lox, double hix, double loy, double hiy, double loz, double hiz,
                                            double rx, double ry, double rz, float xi, float yi, float zi,
                                            uint32_t first, int first_len, Acc& a, int64_t& nm2p, int64_t& np2p,
-                                           int part = 0, uint32_t deal_lo = 0, uint32_t deal_hi = 0) {
+                                           int64_t& ntest, int part = 0, uint32_t deal_lo = 0, uint32_t deal_hi = 0) {
     constexpr int R = D == 3 ? 8 : 4;                    // lanes (cells) per popped range
     constexpr int RP = kWave / R;                        // ranges per full round
     constexpr int kReserve = (R - 1) * (D == 3 ? 21 : 31) + R;
@@ -93,6 +93,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
             const bool opened = own && !acc0 && !leaf;
             const bool accept = acc0 && emit;
             const bool direct = leaf && !acc0 && emit;
+            ntest += __popcll(__ballot(own && emit));    // each tested cell once over the parts
 
             // push the children ranges of opened cells
             const uint64_t O = __ballot(opened);
@@ -228,7 +229,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
                                                     const DevParams* __restrict__ prm,
                                                     float* __restrict__ acc, float* __restrict__ pot,
                                                     int64_t* __restrict__ m2p_out,
-                                                    int64_t* __restrict__ p2p_out) {
+                                                    int64_t* __restrict__ p2p_out,
+                                                    int64_t* __restrict__ tst_out) {
     static_assert(!QUAD || D == 3, "quadrupole terms are 3D");
     __shared__ float4 s_list[kWavesPerBlock][kListCap];
     __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
@@ -263,9 +265,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
             const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
 
             Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            int64_t nm2p = 0, np2p = 0;
+            int64_t nm2p = 0, np2p = 0, ntest = 0;
             walk_group<D, PLAIN, QUAD>(walk, walkq, bodies, bodies32, L, S, LQ, lpl_log2, eps2, lox, hix, loy, hiy,
-                                       loz, hiz, rx, ry, rz, xi, yi, zi, 0u, 1, a, nm2p, np2p);
+                                       loz, hiz, rx, ry, rz, xi, yi, zi, 0u, 1, a, nm2p, np2p, ntest);
 
             if (valid) {
                 // the body met itself once as a direct entry: no force (zero
@@ -286,6 +288,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
             if (lane == 0) {
                 m2p_out[gi] = nm2p;
                 p2p_out[gi] = np2p;
+                tst_out[gi] = ntest;
             }
             g = sched.pop(xq);
         }
@@ -313,13 +316,14 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
     const int32_t* __restrict__ gcnt, const uint32_t* __restrict__ order, uint32_t* __restrict__ bcost,
     const uint32_t* __restrict__ lvl_off, int deal, int lpl_log2, float G, float eps2,
     const DevParams* __restrict__ prm,
-    float* __restrict__ acc, float* __restrict__ pot, int64_t* __restrict__ m2p_out, int64_t* __restrict__ p2p_out) {
+    float* __restrict__ acc, float* __restrict__ pot, int64_t* __restrict__ m2p_out, int64_t* __restrict__ p2p_out,
+    int64_t* __restrict__ tst_out) {
     constexpr int kCoopParts = NW;
     __shared__ float4 s_list[NW][kListCap];
     __shared__ uint32_t s_stack[NW][kStackCap];
     __shared__ float4 s_qlist[NW][QUAD ? 3 * kQuadCap : 1];
     __shared__ double s_part[NW - 1][4][kWave];
-    __shared__ int64_t s_cnt[NW - 1][2];
+    __shared__ int64_t s_cnt[NW - 1][3];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     const uint32_t deal_lo = lvl_off[deal], deal_hi = lvl_off[deal + 1];   // the cells dealt out
     // blocks take the positions of order in strides of the grid
@@ -338,10 +342,10 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
         const float xi = (float)(me.x - rx), yi = (float)(me.y - ry), zi = (float)(me.z - rz);
 
         Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        int64_t nm2p = 0, np2p = 0;
+        int64_t nm2p = 0, np2p = 0, ntest = 0;
         walk_group<D, PLAIN, QUAD, kCoopParts, true>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv],
                                                lpl_log2, eps2, lox, hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi,
-                                               0u, 1, a, nm2p, np2p, wv, deal_lo, deal_hi);
+                                               0u, 1, a, nm2p, np2p, ntest, wv, deal_lo, deal_hi);
         double px = (double)a.sx + (double)a.cx, py = (double)a.sy + (double)a.cy;
         double pz = (double)a.sz + (double)a.cz, pp = (double)a.sp + (double)a.cp;
         if (wv > 0) {
@@ -352,6 +356,7 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) {
                 s_cnt[wv - 1][0] = nm2p;
                 s_cnt[wv - 1][1] = np2p;
+                s_cnt[wv - 1][2] = ntest;
             }
         }
         __syncthreads();
@@ -363,6 +368,7 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
                 pp += s_part[w][3][lane];
                 nm2p += s_cnt[w][0];
                 np2p += s_cnt[w][1];
+                ntest += s_cnt[w][2];
             }
             if (valid) {
                 // the body met itself once as a direct entry (in one of the
@@ -381,6 +387,7 @@ __global__ void __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) {
                 m2p_out[g] = nm2p;
                 p2p_out[g] = np2p;
+                tst_out[g] = ntest;
             }
         }
         __syncthreads();                                  // s_part is reused by the next group
@@ -454,10 +461,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
         }
     }
     Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int64_t nm2p = 0, np2p = 0;
+    int64_t nm2p = 0, np2p = 0, ntest = 0;   // tested cells are not kept for split walks
     walk_group<D, PLAIN, QUAD>(walk, walkq, bodies, bodies32, s_list[wv], s_stack[wv], s_qlist[wv], lpl_log2, eps2,
                                lox, hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi, first, first_len, a, nm2p,
-                               np2p);
+                               np2p, ntest);
     if (valid)
         part[(int64_t)t * n + i] = make_float4(a.sx + a.cx, a.sy + a.cy, a.sz + a.cz, a.sp + a.cp);
     if (lane == 0 && (nm2p | np2p)) {
@@ -492,10 +499,12 @@ __global__ void __launch_bounds__(256) k_split_reduce(const float4* __restrict__
     }
 }
 
-__global__ void k_zero_u64(unsigned long long* __restrict__ a, unsigned long long* __restrict__ b, int64_t k) {
+__global__ void k_zero_u64(unsigned long long* __restrict__ a, unsigned long long* __restrict__ b,
+                           unsigned long long* __restrict__ c, int64_t k) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
         a[i] = 0ull;
         b[i] = 0ull;
+        c[i] = 0ull;
     }
 }
 
@@ -645,12 +654,13 @@ hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, co
                                    const float4* bodies32, const uint32_t* perm, const int32_t* gbeg,
                                    const int32_t* gcnt, int64_t gmax, int64_t n, int dim, int leaf_cap, float G,
                                    float eps2, const DevParams* prm, float4* part, float* acc, float* pot,
-                                   int64_t* m2p, int64_t* p2p, bool plain, hipStream_t s) {
+                                   int64_t* m2p, int64_t* p2p, int64_t* tests, bool plain, hipStream_t s) {
     int lpl_log2 = 0;
     while ((1 << lpl_log2) < leaf_cap && lpl_log2 < 6) ++lpl_log2;
     unsigned long long* c1 = reinterpret_cast<unsigned long long*>(m2p);
     unsigned long long* c2 = reinterpret_cast<unsigned long long*>(p2p);
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((gmax + 255) / 256)), dim3(256), 0, s, c1, c2, gmax);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((gmax + 255) / 256)), dim3(256), 0, s, c1, c2,
+                       reinterpret_cast<unsigned long long*>(tests), gmax);
     const int T = dim == 3 ? kSplitTasks<3> : kSplitTasks<2>;
     const unsigned nb = (unsigned)((gmax * T + kWavesPerBlock - 1) / kWavesPerBlock);
 #define TC_LAUNCH_SPLIT(DIM, PL, QU)                                                                               \
@@ -681,7 +691,8 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
                              uint32_t* queue, uint32_t* bcost,
                              int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, bool plain, bool share, const uint32_t* lvl_off, hipStream_t s) {
+                             int64_t* p2p, int64_t* tests, bool plain, bool share, const uint32_t* lvl_off,
+                             hipStream_t s) {
     // as many blocks as can be resident at once (the waves are persistent)
     static int resident[3] = {0, 0, 0};                // 2D, 3D, 3D with quadrupoles
     const int kind = dim == 3 ? (walkq ? 2 : 1) : 0;
@@ -716,7 +727,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
 #define TC_LAUNCH_COOP_NW(DIM, PL, QU, NW)                                                                          \
     hipLaunchKernelGGL((k_walk_force_coop<DIM, PL, QU, NW>), dim3(nb), dim3(NW * kWave), 0, s, walk, walkq, bodies,  \
                        bodies32, perm, gbeg, gcnt, order, bcost, lvl_off, deal, lpl_log2, G, eps2, prm, acc, pot,  \
-                       m2p, p2p)
+                       m2p, p2p, tests)
 #define TC_LAUNCH_COOP(DIM, PL, QU)                                                                                 \
     do {                                                                                                            \
         if (nw == 8) TC_LAUNCH_COOP_NW(DIM, PL, QU, 8);                                                             \
@@ -738,7 +749,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     }
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
     hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
-                       gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p)
+                       gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p, tests)
     if (dim == 3 && walkq) {
         if (plain) TC_LAUNCH_WF(3, true, true);
         else TC_LAUNCH_WF(3, false, true);

@@ -97,7 +97,7 @@ struct Layout {
         off_walk, off_mom_lvl, off_kids, off_bodies32, off_acc, off_pot, off_m2p, off_p2p, off_bbox_part, off_diag_part,
         off_diag_out, off_lvl_idx_b, off_pre2bfs,
         off_lvl_hist, off_gper, off_goff, off_gscan_part, off_gbeg, off_gcnt, off_queue, off_gorder, off_bcost, off_lvl_off, off_inv_perm, off_rcount, off_roffs,
-        off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, off_walkq, off_split, total;
+        off_rscan_part, off_mlp, off_rcp2, off_nlearn, off_nfall, off_pb_cnt, off_pb_off, off_pb_part, off_walkq, off_split, off_tests, total;
     int64_t lvl_tiles;   // radix tiles over cmax cells (level sort)
     int64_t gmax;        // bound on walk groups
     int64_t cscan_tiles; // scan tiles over cmax cells
@@ -155,7 +155,8 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
                              const int32_t* gbeg, const int32_t* gcnt, int64_t gmax, uint32_t* order,
                              uint32_t* queue, uint32_t* bcost, int64_t n, int dim, int leaf_cap, float G, float eps2,
                              const DevParams* prm, float* acc, float* pot, int64_t* m2p,
-                             int64_t* p2p, bool plain, bool share, const uint32_t* lvl_off, hipStream_t s);
+                             int64_t* p2p, int64_t* tests, bool plain, bool share, const uint32_t* lvl_off,
+                             hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* part, int64_t tiles,
                            hipStream_t s);
 // closure.hip
@@ -200,7 +201,7 @@ hipError_t launch_walk_force_split(const WalkCell* walk, const float4* walkq, co
                                    const float4* bodies32, const uint32_t* perm, const int32_t* gbeg,
                                    const int32_t* gcnt, int64_t gmax, int64_t n, int dim, int leaf_cap, float G,
                                    float eps2, const DevParams* prm, float4* part, float* acc, float* pot,
-                                   int64_t* m2p, int64_t* p2p, bool plain, hipStream_t s);
+                                   int64_t* m2p, int64_t* p2p, int64_t* tests, bool plain, hipStream_t s);
 hipError_t launch_quad_pack(const Moments* mom, const uint32_t* pre2bfs, const DevParams* prm, int64_t cmax,
                             float4* walkq, hipStream_t s);
 // perbody.hip

@@ -66,6 +66,7 @@ def lib():
         "tc_get_keys": (i32, [P, P, P]),
         "tc_get_cells": (i32, [P] * 12),
         "tc_get_counts": (i32, [P, P, P]),
+        "tc_get_tests": (i32, [P, P]),
         "tc_num_groups": (i32, [P, C.POINTER(C.c_int64)]),
         "tc_get_groups": (i32, [P, P, P]),
         "tc_set_timing": (i32, [P, i32]),
@@ -290,6 +291,12 @@ class Treecode:
         p2p = torch.empty(G, dtype=torch.int64, device=dev)
         _check(lib().tc_get_counts(self._h, _ptr(m2p), _ptr(p2p)))
         return m2p, p2p
+
+    def tests(self):
+        """Cells tested by each group's walk in the last force evaluation."""
+        t = torch.empty(self.num_groups(), dtype=torch.int64, device=self.stream.device)
+        _check(lib().tc_get_tests(self._h, _ptr(t)))
+        return t
 
     def interactions(self) -> int:
         """Body-entry interactions of the last force evaluation (self

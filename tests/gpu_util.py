@@ -34,7 +34,7 @@ def gpu_tree(pos, mass, leaf_cap, theta=None, G=1.0, eps=None, moments=True, tc=
         acc, pot = tc.forces(G, eps)
         m2p, p2p = tc.counts()
         out.update(acc=acc.cpu().numpy(), pot=pot.cpu().numpy(), m2p=m2p.cpu().numpy(),
-                   p2p=p2p.cpu().numpy())
+                   p2p=p2p.cpu().numpy(), tests=tc.tests().cpu().numpy())
     gb, gc = tc.groups()
     out["gbeg"], out["gcnt"] = gb.cpu().numpy(), gc.cpu().numpy()
     torch.cuda.synchronize()

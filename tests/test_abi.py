@@ -59,6 +59,9 @@ def test_call_order_and_arguments(L):
     assert L.tc_diag_async(h, fake, C.c_void_p((1 << 40) + 4)) == T.TC_EINVAL    # out not 8-byte aligned
     n = C.c_int64()
     assert L.tc_num_cells(h, C.byref(n)) == T.TC_ESTATE
+    assert L.tc_get_tests(h, fake) == T.TC_ESTATE
+    assert L.tc_get_tests(h, None) == T.TC_EINVAL
+    assert L.tc_get_tests(None, fake) == T.TC_EINVAL
     # argument checks come first
     assert L.tc_walk(h, -0.1) == T.TC_EINVAL
     assert L.tc_walk(h, float("nan")) == T.TC_EINVAL

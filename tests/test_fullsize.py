@@ -32,10 +32,12 @@ def _sampled_parity(w, theta, eps, ngroups=128, seed=300, counts_all=True):
         m2p, p2p = t.walk_counts_groups(theta, gb, gc)
         np.testing.assert_array_equal(g["m2p"], m2p)
         np.testing.assert_array_equal(g["p2p"], p2p)
+        np.testing.assert_array_equal(g["tests"], t.walk_tests_groups(theta, gb, gc))
     else:
         m2p, p2p = t.walk_counts_groups(theta, gb[sel], gc[sel])
         np.testing.assert_array_equal(g["m2p"][sel], m2p)
         np.testing.assert_array_equal(g["p2p"][sel], p2p)
+        np.testing.assert_array_equal(g["tests"][sel], t.walk_tests_groups(theta, gb[sel], gc[sel]))
     print("  oracle forces on sampled groups", flush=True)
     a, p = t.forces_groups(theta, gb[sel], gc[sel], G=w.G, eps=eps)
     perm = t.bodies()["perm"]

@@ -30,6 +30,7 @@ def _check_against_oracle(pos, mass, lc, theta, eps, G=1.0, split=None, t=None):
     m2p, p2p = t.walk_counts_groups(theta, gb, gc)
     np.testing.assert_array_equal(g["m2p"], m2p)
     np.testing.assert_array_equal(g["p2p"], p2p)
+    np.testing.assert_array_equal(g["tests"], t.walk_tests_groups(theta, gb, gc))
     a, p = t.forces_groups(theta, gb, gc, G=G, eps=eps)
     ea, ep = oracle.rel_l2(g["acc"], a), oracle.rel_l2(g["pot"], p)
     print(f"n={len(pos)} theta={theta}: acc {ea:.2e} pot {ep:.2e} "
@@ -244,7 +245,15 @@ def test_shared_walks_match_one_wave(case):
         tc.set_split(mode)
         acc, pot = tc.forces(1.0, 1e-2)
         m2p, p2p = (v.cpu().numpy() for v in tc.counts())
-        out[mode] = (acc.cpu().numpy(), pot.cpu().numpy(), m2p, p2p)
+        if mode == 2 and w.n <= (12288 if w.dim == 3 else 24576):
+            with pytest.raises(treecode.TcError):     # split walks keep no tested-cell counts
+                tc.tests()
+            tests = None
+        else:
+            tests = tc.tests().cpu().numpy()
+        out[mode] = (acc.cpu().numpy(), pot.cpu().numpy(), m2p, p2p, tests)
+    # cells tested: a shared walk's parts test each cell once between them
+    np.testing.assert_array_equal(out[1][4], out[0][4])
     for mode in (1, 2):
         np.testing.assert_array_equal(out[mode][2], out[0][2])
         np.testing.assert_array_equal(out[mode][3], out[0][3])
