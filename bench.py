@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -63,12 +64,34 @@ def make_workload(name: str, n: int | None):
     return gen() if n is None else gen(n)
 
 
-def force_kernel_source_hash() -> str:
+def code_only(text: str) -> str:
+    """A source's code without its comments and blank lines, so that a
+    change of comments alone does not mark a counter profile stale."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
+def sources_hash(files, read=None) -> str:
+    """Hash of the code of the given csrc files (read(f) supplies another
+    version of a file's text)."""
     h = hashlib.sha256()
-    for f in ("force.hip", "walk_common.h", "tc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1211_2293_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        if read is None:
+            with open(os.path.join(ROOT, "paper_1211_2293_amd", "csrc", f), encoding="utf-8") as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(code_only(text).encode())
     return h.hexdigest()[:16]
+
+
+FORCE_SOURCES = ("force.hip", "walk_common.h", "tc_internal.h")
+BUILD_SOURCES = ("build.hip", "tc_internal.h")
+
+
+def force_kernel_source_hash() -> str:
+    return sources_hash(FORCE_SOURCES)
 
 
 def traffic_from_profile(w, theta: float):
@@ -88,11 +111,7 @@ def traffic_from_profile(w, theta: float):
 
 
 def build_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("build.hip", "tc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1211_2293_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return sources_hash(BUILD_SOURCES)
 
 
 def build_traffic_from_profile(w, theta: float):

@@ -3,16 +3,20 @@
 // its bodies' total mass at their centre of mass).
 //
 // Pipeline, one stream, no host synchronisation:
-//   bbox     root cube: per-axis minimum corner, power-of-two side (FP64)
+//   bbox     root cube: per-axis minimum corner, power-of-two side (FP64);
+//            the same pass packs the input as (x, y, z, m) records
 //   keys     Morton key of FP64-quantised coordinates, index iota
-//   sort     stable LSD radix sort of (key, index), 8 bits per pass
-//   gather   bodies into key order, FP64
+//   sort     stable LSD radix sort of (key, index), 8 bits per pass (large
+//            sorts rank each tile in LDS before writing it out)
+//   gather   bodies into key order, FP64, one packed record per body
 //   topology all cells at once from the sorted keys (no per-level launches):
 //            body i starts the cells of levels a_i..l*_i, where a_i is one
 //            more than its common-prefix length with body i-1 and l*_i is
 //            one below the deepest level at which a run of leaf_cap+1
 //            consecutive keys around i still shares a prefix; their
-//            exclusive scan is the depth-first pre-order index
+//            exclusive scan is the depth-first pre-order index; the level
+//            order is one more radix pass, keyed by level, and the walk
+//            groups one more scan
 //   moments  FP64, leaves over bodies in order (one launch), then internal
 //            cells level by level from the deepest up, each over its
 //            children in digit order read from level-order copies (the top

@@ -3,8 +3,8 @@
 // into its children; the list is then summed to give the force; §3.2: the
 // per-body sums are independent of each other).
 //
-// One wavefront per group of 64 consecutive bodies in key order, one lane
-// per body.  The walk tests whole batches of cells at once: a per-wave LDS
+// One wavefront per walk group (at most 64 consecutive bodies in key order,
+// never straddling a cluster cell), one lane per body.  The walk tests whole batches of cells at once: a per-wave LDS
 // stack holds ranges of sibling cells (the children of one opened cell are
 // contiguous in level order), and each round pops up to 8 ranges (4 in 2D),
 // gives every lane one cell, and runs the opening test for all of them in
@@ -15,7 +15,9 @@
 // own body in FP32, reading each entry as an LDS broadcast.  Coordinates are
 // relative to the group's box centre (FP64 difference, then rounded) so FP32
 // keeps the significant digits; chunks of 64 entries are summed plainly and
-// folded into Neumaier-compensated totals.
+// folded into Neumaier-compensated totals.  Each group's walk also counts
+// the cells it tests (the root and every child of an opened cell), a
+// measure of the walk's work that is kept per group.
 //
 // Stack bound: a round pushes at most 64 ranges; popping a single range at a
 // time is a depth-first descent that adds at most (R-1) ranges per level
