@@ -47,7 +47,7 @@ constexpr int kWavesPerBlock = 4;
 // dealt out by index modulo NP; everything deeper follows its ancestor at
 // the deal level.  The parts' lists together are the whole walk's.
 // STAGED: the list sums in staged batches (flush).
-template <int D, bool PLAIN, bool QUAD, int NP = 1, bool STAGED = false>
+template <int D, bool PLAIN, bool QUAD, int NP = 1, bool STAGED = false, int STEP = 8>
 __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, const float4* __restrict__ walkq,
                                            const Body* __restrict__ bodies, const float4* __restrict__ bodies32,
                                            float4* L, uint32_t* S, float4* LQ, int lpl_log2, float eps2,
@@ -147,7 +147,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 nm2p += na;
             } else if (na) {
                 if (len + na > kListCap) {
-                    flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
+                    flush<D, PLAIN, STAGED, STEP>(L, len, xi, yi, zi, eps2, a);
                     len = 0;
                 }
                 if (accept)
@@ -178,7 +178,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                         tot += cl;
                     }
                     if (len + tot > kListCap) {
-                        flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
+                        flush<D, PLAIN, STAGED, STEP>(L, len, xi, yi, zi, eps2, a);
                         len = 0;
                     }
                     if (jj < my_cnt)
@@ -195,7 +195,7 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                     for (int o = 0; o < cl; o += kWave) {
                         const int m = min(kWave, cl - o);
                         if (len + m > kListCap) {
-                            flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
+                            flush<D, PLAIN, STAGED, STEP>(L, len, xi, yi, zi, eps2, a);
                             len = 0;
                         }
                         if (lane < m) L[len + lane] = body_entry(bodies, bodies32, bl + o + lane, rx, ry, rz);
@@ -213,11 +213,11 @@ __device__ __forceinline__ void walk_group(const WalkCell* __restrict__ walk, co
                 q1 = q1n;
             }
         }
-        flush<D, PLAIN, STAGED>(L, len, xi, yi, zi, eps2, a);
+        flush<D, PLAIN, STAGED, STEP>(L, len, xi, yi, zi, eps2, a);
         if (QUAD) flush_quad<PLAIN>(LQ, qlen, xi, yi, zi, eps2, a);
 }
 
-template <int D, bool PLAIN, bool QUAD>
+template <int D, bool PLAIN, bool QUAD, int STEP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ? 4 : 5, 8))) k_walk_force(const WalkCell* __restrict__ walk,
                                                     const float4* __restrict__ walkq,
                                                     const Body* __restrict__ bodies,
@@ -268,8 +268,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUAD ?
 
             Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             int64_t nm2p = 0, np2p = 0, ntest = 0;
-            walk_group<D, PLAIN, QUAD>(walk, walkq, bodies, bodies32, L, S, LQ, lpl_log2, eps2, lox, hix, loy, hiy,
-                                       loz, hiz, rx, ry, rz, xi, yi, zi, 0u, 1, a, nm2p, np2p, ntest);
+            walk_group<D, PLAIN, QUAD, 1, false, STEP>(walk, walkq, bodies, bodies32, L, S, LQ, lpl_log2, eps2, lox,
+                                                       hix, loy, hiy, loz, hiz, rx, ry, rz, xi, yi, zi, 0u, 1, a, nm2p,
+                                                       np2p, ntest);
 
             if (valid) {
                 // the body met itself once as a direct entry: no force (zero
@@ -704,9 +705,9 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = kind == 2   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, true>, 256, 0)
-                : kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, false>, 256, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2, false, false>, 256, 0);
+            e = kind == 2   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, true, 8>, 256, 0)
+                : kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<3, false, false, 8>, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_force<2, false, false, 8>, 256, 0);
         if (e != hipSuccess) return e;
         res = cus * (per_cu > 0 ? per_cu : 1);
     }
@@ -749,9 +750,22 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
 #undef TC_LAUNCH_COOP_NW
         return hipGetLastError();
     }
+    // With two to four groups per resident wave (counting n/64 groups) the
+    // list sums go in rounds of 4 entries, else 8: the same sums either
+    // way, and measured per force kernel (3D Plummer, rounds of 4 against
+    // 8): 1.89 against 1.94 ms at 1M bodies, 2.29 against 2.32 at 1.25M,
+    // but 0.86 against 0.85 at 400,000, 7.85 against 7.76 at 4M and
+    // 0.1145 against 0.1140 ms for the 262,144-body disk.
+    const int64_t groups_lo = (n + kGroup - 1) / kGroup, waves_all = (int64_t)nb * kWavesPerBlock;
+    const bool short_rounds = groups_lo > 2 * waves_all && groups_lo <= 4 * waves_all;
+#define TC_LAUNCH_WF_STEP(DIM, PL, QU, ST)                                                                           \
+    hipLaunchKernelGGL((k_walk_force<DIM, PL, QU, ST>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32,  \
+                       perm, gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p, tests)
 #define TC_LAUNCH_WF(DIM, PL, QU)                                                                                \
-    hipLaunchKernelGGL((k_walk_force<DIM, PL, QU>), dim3(nb), dim3(256), 0, s, walk, walkq, bodies, bodies32, perm, \
-                       gbeg, gcnt, order, queue, bcost, lpl_log2, G, eps2, prm, acc, pot, m2p, p2p, tests)
+    do {                                                                                                         \
+        if (short_rounds) TC_LAUNCH_WF_STEP(DIM, PL, QU, 4);                                                     \
+        else TC_LAUNCH_WF_STEP(DIM, PL, QU, 8);                                                                  \
+    } while (0)
     if (dim == 3 && walkq) {
         if (plain) TC_LAUNCH_WF(3, true, true);
         else TC_LAUNCH_WF(3, false, true);
@@ -763,6 +777,7 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
         else TC_LAUNCH_WF(2, false, false);
     }
 #undef TC_LAUNCH_WF
+#undef TC_LAUNCH_WF_STEP
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Throughput of the force loop alone (a benchmark program, not part of
 // libtc): every wave sums a 256-entry list held in LDS for its 64 bodies,
-// over and over, with the same flush the walk kernels use (entry by entry,
-// and staged), at 5 and 8 resident waves per SIMD; and plain FP32 FMA
+// over and over, with the same flush the walk kernels use (entry by entry
+// in rounds of 8 or 4, and staged), at 5 and 8 resident waves per SIMD; and plain FP32 FMA
 // chains, for the unpacked VALU peak.  It shows what the loop can reach on
 // this chip when no walk shares the SIMD with it, which the 14 VALU
 // instructions per entry and a 4-cycle issue per wave64 instruction do not
@@ -35,7 +35,7 @@ constexpr int kWavesPerBlock = 4;
 
 // Each rep moves the bodies by a tiny amount, so no rep's sums can be
 // reused for the next; flush's LDS fences keep the list reads in the rep.
-template <bool STAGED>
+template <bool STAGED, int STEP>
 __global__ void __launch_bounds__(kWavesPerBlock * kWave) k_probe_loop(const float4* __restrict__ list, int reps,
                                                                        float eps2, float* __restrict__ out) {
     __shared__ float4 s_list[kWavesPerBlock][kListCap];
@@ -45,7 +45,8 @@ __global__ void __launch_bounds__(kWavesPerBlock * kWave) k_probe_loop(const flo
     __syncthreads();
     const float xi = 0.01f * lane, yi = -0.02f * lane, zi = 0.005f * lane;
     Acc a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int r = 0; r < reps; ++r) flush<3, false, STAGED>(L, kListCap, xi + 1e-7f * (float)r, yi, zi, eps2, a);
+    for (int r = 0; r < reps; ++r)
+        flush<3, false, STAGED, STEP>(L, kListCap, xi + 1e-7f * (float)r, yi, zi, eps2, a);
     out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = (a.sx + a.cx) + (a.sy + a.cy) + (a.sz + a.cz) + (a.sp + a.cp);
 }
 
@@ -71,21 +72,21 @@ float time_ms(hipEvent_t e0, hipEvent_t e1) {
     return ms;
 }
 
-template <bool STAGED>
+template <bool STAGED, int STEP = 8>
 void probe_loop(int cus, int waves_per_simd, int reps, const float4* list, float* out, hipEvent_t e0, hipEvent_t e1) {
     const int blocks = cus * waves_per_simd;          // 4 waves per block: waves_per_simd per SIMD
     for (int pass = 0; pass < 3; ++pass) {            // the first pass warms up
         PROBE_CHECK(hipEventRecord(e0, 0));
-        hipLaunchKernelGGL(k_probe_loop<STAGED>, dim3(blocks), dim3(kWavesPerBlock * kWave), 0, 0, list, reps,
-                           1e-4f, out);
+        hipLaunchKernelGGL((k_probe_loop<STAGED, STEP>), dim3(blocks), dim3(kWavesPerBlock * kWave), 0, 0, list,
+                           reps, 1e-4f, out);
         PROBE_CHECK(hipGetLastError());
         PROBE_CHECK(hipEventRecord(e1, 0));
         const float ms = time_ms(e0, e1);
         if (pass == 0) continue;
         const double inter = (double)reps * kListCap * blocks * kWavesPerBlock * kWave;
         std::printf("force loop %s, %d waves per SIMD: %.3f ms, %.3e interactions/s, %.1f TFLOP/s\n",
-                    STAGED ? "staged" : "entry by entry", waves_per_simd, ms, inter / (ms * 1e-3),
-                    20.0 * inter / (ms * 1e-3) / 1e12);
+                    STAGED ? "staged" : STEP == 4 ? "entry by entry (rounds of 4)" : "entry by entry",
+                    waves_per_simd, ms, inter / (ms * 1e-3), 20.0 * inter / (ms * 1e-3) / 1e12);
     }
 }
 
@@ -130,6 +131,7 @@ int main(int argc, char** argv) {
     }
     for (int w : {5, 8}) {
         probe_loop<false>(cus, w, reps, list, out, e0, e1);
+        probe_loop<false, 4>(cus, w, reps, list, out, e0, e1);
         probe_loop<true>(cus, w, reps, list, out, e0, e1);
     }
     std::vector<float> back(nout);

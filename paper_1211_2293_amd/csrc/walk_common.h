@@ -68,8 +68,12 @@ struct Acc {
 // (8% at 50,000 bodies); with one wave per group the compiler then issues
 // four list reads at a time instead of eight, and that kernel ran as fast at
 // 1M bodies and 1.8% slower at 4M.
-template <int D, bool PLAIN = false, bool STAGED = false>
+template <int D, bool PLAIN = false, bool STAGED = false, int STEP = 8>
 static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float yi, float zi, float eps2, Acc& a) {
+    // entries per unrolled round: the staged form takes batches of 8; the
+    // order of the sums is the same for any STEP
+    constexpr int kStep = STAGED ? 8 : STEP;
+    static_assert(8 % kStep == 0, "rounds must divide the padding of 8");
     const int lane = threadIdx.x & (kWave - 1);
     const int padded = (cnt + 7) & ~7;
     for (int j = cnt + lane; j < padded; j += kWave) L[j] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -83,7 +87,7 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
             az = a.sz;
             ap = a.sp;
         }
-        for (int k = 0; k < lim; k += 8) {
+        for (int k = 0; k < lim; k += kStep) {
             if (STAGED) {
 #pragma unroll
                 for (int h4 = 0; h4 < 8; h4 += 4) {
@@ -118,7 +122,7 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
                 continue;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kStep; ++u) {
                 const float4 p = L[e + k + u];
                 const float dx = p.x - xi, dy = p.y - yi;
                 float r2, dz = 0.f;
