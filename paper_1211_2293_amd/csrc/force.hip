@@ -754,8 +754,9 @@ hipError_t launch_walk_force(const WalkCell* walk, const float4* walkq, const Bo
     // list sums go in rounds of 4 entries, else 8: the same sums either
     // way, and measured per force kernel (3D Plummer, rounds of 4 against
     // 8): 1.89 against 1.94 ms at 1M bodies, 2.29 against 2.32 at 1.25M,
-    // but 0.86 against 0.85 at 400,000, 7.85 against 7.76 at 4M and
-    // 0.1145 against 0.1140 ms for the 262,144-body disk.
+    // but 0.86 against 0.85 at 400,000, 7.89 against 7.86 at 4M, 16.45
+    // against 16.19 at 16.7M and 0.1145 against 0.1140 ms for the
+    // 262,144-body disk.
     const int64_t groups_lo = (n + kGroup - 1) / kGroup, waves_all = (int64_t)nb * kWavesPerBlock;
     const bool short_rounds = groups_lo > 2 * waves_all && groups_lo <= 4 * waves_all;
 #define TC_LAUNCH_WF_STEP(DIM, PL, QU, ST)                                                                           \
