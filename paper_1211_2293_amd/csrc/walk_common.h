@@ -73,9 +73,10 @@ static __device__ __forceinline__ void flush(float4* L, int cnt, float xi, float
     // entries per unrolled round: the staged form takes batches of 8; the
     // order of the sums is the same for any STEP
     constexpr int kStep = STAGED ? 8 : STEP;
-    static_assert(8 % kStep == 0, "rounds must divide the padding of 8");
+    static_assert(8 % kStep == 0, "rounds of 1, 2, 4 or 8 entries");
     const int lane = threadIdx.x & (kWave - 1);
-    const int padded = (cnt + 7) & ~7;
+    // zero entries pad the list to whole rounds (they add exact zeros)
+    const int padded = (cnt + kStep - 1) & ~(kStep - 1);
     for (int j = cnt + lane; j < padded; j += kWave) L[j] = make_float4(0.f, 0.f, 0.f, 0.f);
     wave_lds_sync();
     for (int e = 0; e < padded; e += kWave) {
