@@ -60,6 +60,34 @@ def test_disk_2d_262k():
     _sampled_parity(w, 0.5, w.eps)
 
 
+@pytest.mark.timeout(300)
+def test_plummer_1m_quadrupole_cells():
+    """Accepted cells with their quadrupole terms in the one-wave kernel at
+    the benchmark's size (its list in rounds of 4 entries there): counts of
+    every group bit-exact, forces of sampled groups within 1e-5 of the
+    oracle's second-order sums."""
+    from paper_1211_2293_amd import treecode
+    w = workloads.plummer_sphere()
+    theta = 0.6
+    tc = treecode.Treecode(3, leaf_cap=16)
+    tc.set_multipole(2)
+    g = gpu_tree(w.pos, w.mass, w.leaf_cap, theta=theta, G=w.G, eps=w.eps, tc=tc)
+    assert g["status"] == 0
+    t = oracle.Tree(w.pos, w.mass, w.leaf_cap)
+    gb, gc = g["gbeg"], g["gcnt"]
+    m2p, p2p = t.walk_counts_groups(theta, gb, gc)
+    np.testing.assert_array_equal(g["m2p"], m2p)
+    np.testing.assert_array_equal(g["p2p"], p2p)
+    sel = np.sort(np.random.default_rng(303).choice(len(gb), size=128, replace=False))
+    a, p = t.forces_groups(theta, gb[sel], gc[sel], G=w.G, eps=w.eps, order=2)
+    perm = t.bodies()["perm"]
+    bodies = np.concatenate([perm[b:b + k] for b, k in zip(gb[sel], gc[sel])])
+    ea = oracle.rel_l2(g["acc"][bodies], a[bodies])
+    ep = oracle.rel_l2(g["pot"][bodies], p[bodies])
+    print(f"1M quadrupole cells, {len(bodies)} sampled bodies: acc {ea:.2e} pot {ep:.2e}", flush=True)
+    assert ea < TOL and ep < TOL
+
+
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("theta", [0.3, 0.7])
 def test_two_plummer_4m(theta):
