@@ -61,6 +61,14 @@ def test_disk_2d_262k():
 
 
 @pytest.mark.timeout(300)
+def test_disk_2d_1m():
+    """A 2D system with two to four groups per resident wave (the force
+    kernel's list in rounds of 4 entries)."""
+    w = workloads.gaussian_disk(1_048_576, seed=86)
+    _sampled_parity(w, 0.5, w.eps)
+
+
+@pytest.mark.timeout(300)
 def test_plummer_1m_quadrupole_cells():
     """Accepted cells with their quadrupole terms in the one-wave kernel at
     the benchmark's size (its list in rounds of 4 entries there): counts of
