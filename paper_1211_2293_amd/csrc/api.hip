@@ -322,7 +322,10 @@ int do_build(tc_ctx* ctx, const void* pos, const void* mass, int64_t n, int leaf
     }
     {
         StageScope st_(ctx, TC_STAGE_LEVELS, s);
-        TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, dim, prm,
+        // tiles sized for the cells a tree usually holds (about 4 per leaf_cap
+        // bodies), not for the slots
+        const int64_t cells_est = std::min<int64_t>(l.cmax, 4 * n / leaf_cap + 1);
+        TC_HIP(ctx, launch_level_order(ctx->at<Cell>(l.off_cells), l.cmax, cells_est, dim, prm,
                                        ctx->at<uint32_t>(l.off_lvl_idx_b), ctx->at<uint32_t>(l.off_lvl_hist),
                                        ctx->at<uint32_t>(l.off_digit_tot), ctx->at<uint32_t>(l.off_pre2bfs),
                                        ctx->at<uint32_t>(l.off_lvl_off), s));

@@ -1299,13 +1299,16 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
     return hipGetLastError();
 }
 
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint32_t* bfs2pre,
-                              uint32_t* hist, uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
-                              hipStream_t s) {
-    // one pass by level over the live cells (their count is on the device)
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int64_t cells_est, int dim, const DevParams* prm,
+                              uint32_t* bfs2pre, uint32_t* hist, uint32_t* digit_tot, uint32_t* pre2bfs,
+                              uint32_t* lvl_off, hipStream_t s) {
+    // one pass by level over the live cells (their count is on the device,
+    // so the tile follows the host's estimate of it: the slots are several
+    // times more; 1M bodies: 19 against 29 us per pass with tiles sized for
+    // the slots)
     const LevelsIn in{cells};
     const LevelsOut out{bfs2pre, pre2bfs, lvl_off, levels_for(dim)};
-    switch (sort_per(cmax)) {
+    switch (sort_per(cells_est)) {
         case 16: sort_pass<16, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
         case 8: sort_pass<8, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;
         default: sort_pass<4, false>(in, out, cmax, &prm->ncells, 0, hist, digit_tot, s); break;

@@ -126,7 +126,8 @@ hipError_t launch_topology(const uint64_t* keys, int64_t n, int dim, int leaf_ca
                            int64_t cmax, DevParams* prm, hipStream_t s);
 // Level order (one radix pass by level over the live cells): bfs2pre and
 // pre2bfs, and lvl_off, where each level starts (levels 0..L and the end).
-hipError_t launch_level_order(const Cell* cells, int64_t cmax, int dim, const DevParams* prm, uint32_t* bfs2pre,
+// cells_est, an estimate of the live cells (any value works), sets the tile.
+hipError_t launch_level_order(const Cell* cells, int64_t cmax, int64_t cells_est, int dim, const DevParams* prm, uint32_t* bfs2pre,
                               uint32_t* hist, uint32_t* digit_tot, uint32_t* pre2bfs, uint32_t* lvl_off,
                               hipStream_t s);
 hipError_t launch_groups(const Cell* cells, int64_t cmax, uint32_t* gper, uint32_t* goff, uint32_t* scan_part,
