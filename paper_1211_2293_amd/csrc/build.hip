@@ -213,9 +213,10 @@ __global__ void __launch_bounds__(256) k_keys(const T* __restrict__ pos, int64_t
 // after round: 20.2 us per pass of 1M keys, 16.0 us with the loads first).
 // Recording every round's per-wave digit counts and placing all keys after
 // one prefix pass (three barriers per tile instead of three per round) took
-// 18.4 us.  Two copies of the running places and counts let a round clear
-// the next round's counts while it places its keys: two barriers per round
-// (1M keys: 0.197 against 0.201 ms per sort; 16.7M: 1.59 against 1.64).
+// 18.4 us.  Copies of the running places (two) and counts (three) let a
+// round place its keys while the next round's places are advanced and a
+// later round's counts cleared: one barrier per round instead of three
+// (1M keys: 0.191 against 0.201 ms per sort; 16.7M: 1.57 against 1.64).
 // PER keys per thread, tiles of 256 PER keys (sort_per).
 // Placing each key straight at its output place writes about one key per
 // digit per round of 256, so a line of the output is written in many
@@ -354,11 +355,13 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
     if ((int64_t)blockIdx.x >= tl) return;
     __shared__ uint32_t s_base[256];   // where the tile's keys of each digit start in the output
     // running place of each digit (staged: in the tile, else in the output)
-    // and each wave's count of each digit in the current round; both in two
-    // copies, a round reading one while the next is prepared in the other
+    // in two copies, and each wave's count of each digit in a round in three:
+    // round r reads place copy r % 2 and count copy r % 3, writes place copy
+    // (r + 1) % 2 and clears count copy (r + 2) % 3, so one barrier per round
+    // separates every write of a copy from its reads
     __shared__ uint32_t s_pos[2][256];
     __shared__ uint32_t s_lstart[256]; // staged: where each digit's keys start in the tile
-    __shared__ uint32_t s_wcnt[2][4][256];
+    __shared__ uint32_t s_wcnt[3][4][256];
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_tot;
     __shared__ uint64_t s_key[kStage];
@@ -392,7 +395,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
     } else {
         s_pos[0][t] = s_base[t];
     }
-    for (int a = 0; a < 4; ++a) s_wcnt[0][a][t] = 0;
+    for (int a = 0; a < 4; ++a) s_wcnt[0][a][t] = s_wcnt[1][a][t] = 0;
     uint64_t kr[PER];
     uint32_t vr[PER];
 #pragma unroll
@@ -416,12 +419,12 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
             peers &= bit ? bb : ~bb;
         }
         const uint64_t before = peers & lt;
-        const int cur = r & 1, nxt = cur ^ 1;
-        if (valid && before == 0) s_wcnt[cur][w][d] = (uint32_t)__popcll(peers);
+        const int cur = r & 1, nxt = cur ^ 1, cc = r % 3, cz = (r + 2) % 3;
+        if (valid && before == 0) s_wcnt[cc][w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
             uint32_t p = s_pos[cur][d] + (uint32_t)__popcll(before);
-            for (int a = 0; a < w; ++a) p += s_wcnt[cur][a][d];
+            for (int a = 0; a < w; ++a) p += s_wcnt[cc][a][d];
             if (STAGE) {
                 s_key[p] = k;
                 s_val[p] = vr[r];
@@ -429,14 +432,14 @@ __global__ void __launch_bounds__(256) k_sort_scatter(In in, Out out, int64_t n,
                 out.put(p, k, vr[r]);
             }
         }
-        // the next round's copies: places advanced by this round's counts,
-        // counts cleared (the last round to read them was the previous one)
-        s_pos[nxt][t] = s_pos[cur][t] + s_wcnt[cur][0][t] + s_wcnt[cur][1][t] + s_wcnt[cur][2][t] +
-                        s_wcnt[cur][3][t];
-        for (int a = 0; a < 4; ++a) s_wcnt[nxt][a][t] = 0;
-        __syncthreads();
+        // the next round's places, advanced by this round's counts, and the
+        // counts of the round after it cleared (last read by the previous round)
+        s_pos[nxt][t] = s_pos[cur][t] + s_wcnt[cc][0][t] + s_wcnt[cc][1][t] + s_wcnt[cc][2][t] +
+                        s_wcnt[cc][3][t];
+        for (int a = 0; a < 4; ++a) s_wcnt[cz][a][t] = 0;
     }
     if (STAGE) {
+        __syncthreads();
         // The tile's keys now sit in LDS in output order, digit by digit:
         // consecutive threads write consecutive places of a digit's run.
         const int64_t left = n - tile * kTile;
