@@ -52,6 +52,14 @@ CASES = {
                                workloads.plummer_sphere(131073, seed=50).mass, 16),
     "disk2d-131073": lambda: (workloads.gaussian_disk(131073, seed=51).pos,
                               workloads.gaussian_disk(131073, seed=51).mass, 16),
+    # one key past the sizes where the body sort's tiles grow (2048 keys per
+    # tile from 524,288 keys, 4096 from 1,048,576): 257 tiles, the last one
+    # holding a single key (both level orders, about 4 cells per 16 bodies
+    # expected, go in tiles of 1024 cells)
+    "plummer-524289": lambda: (workloads.plummer_sphere(524289, seed=53).pos,
+                               workloads.plummer_sphere(524289, seed=53).mass, 16),
+    "plummer-1048577": lambda: (workloads.plummer_sphere(1048577, seed=54).pos,
+                                workloads.plummer_sphere(1048577, seed=54).mass, 16),
     # from 2^21 keys the radix passes rank each 4096-key tile in LDS before
     # writing it: a ragged last tile (2,848 keys) with the clumped, skewed
     # digits of the clustered mixture, and one key past the threshold in 2D
