@@ -1316,7 +1316,7 @@ hipError_t launch_level_order(const Cell* cells, int64_t cmax, int64_t cells_est
                               uint32_t* lvl_off, hipStream_t s) {
     // one pass by level over the live cells (their count is on the device,
     // so the tile follows the host's estimate of it: the slots are several
-    // times more; 1M bodies: 19 against 29 us per pass with tiles sized for
+    // times more; 1M bodies: 16 against 27 us per pass with tiles sized for
     // the slots)
     const LevelsIn in{cells};
     const LevelsOut out{bfs2pre, pre2bfs, lvl_off, levels_for(dim)};
