@@ -216,7 +216,7 @@ class Tree:
                 return buf[:k]
             cap = k
 
-    def groups(self, gs=64, cluster=512):
+    def groups(self, gs=64, cluster=1024):
         """Groups of at most gs consecutive sorted bodies that never straddle
         a cluster cell (a maximal cell of at most `cluster` bodies, or a
         deeper leaf): returns (first body, size) arrays."""
